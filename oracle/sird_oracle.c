@@ -1,0 +1,561 @@
+/*
+ * Plain FP64 CPU oracle for the SIRD calibration hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is checked against.  It shares no code,
+ * header, constant or helper with the GPU library and is never linked into
+ * it.  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.
+ *
+ * What it computes, with the passage each part follows:
+ *   - the SIRD right-hand side, eq. (SIRD) of Sec. 2.2, in the natural
+ *     state (S, I, R, D);
+ *   - a piecewise-constant transmission rate beta_k on segments of
+ *     seg_days days (the build's replacement for the ramp of eq. (beta));
+ *     the segment index is taken from the step index, so all four stages of
+ *     a step use the same beta; the last segment extends to the end;
+ *   - the ramp of eq. (beta) itself, for the Euler variant of Sec. 3.1/3.3;
+ *   - classical RK4 with a fixed step h = 1/spd (the build's integrator),
+ *     and forward Euler (the scheme named in Sec. 3.1 and Sec. 3.3);
+ *   - the low-level costs MXSE, MSE, MAE, MAPE of Sec. 3.1 on the deceased
+ *     compartment, plus the sum of squared relative errors (SSRE);
+ *   - particle swarm optimisation as in Sec. 3.3 (inertia, cognitive and
+ *     social coefficients; out-of-box positions set to the bound), driven
+ *     by Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11);
+ *   - the gradient of the discrete loss by forward-mode tangent propagation
+ *     through every RK4 stage (an algorithm independent of the GPU's
+ *     reverse-mode adjoint);
+ *   - projected Adam (Kingma & Ba 2015) in box-normalised coordinates.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fopenmp -shared -fPIC.
+ * Evaluation order is the natural one; no contraction, no reordering.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon et al., SC'11).                               */
+/* One round: two 64x64->128 products of the even counter words with  */
+/* fixed multipliers, then a permutation/xor with the key; the key is  */
+/* bumped by the Weyl constants between rounds.                        */
+/* ------------------------------------------------------------------ */
+#define ORC_PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define ORC_PHILOX_M1 0xCA5A826395121157ULL
+#define ORC_PHILOX_W0 0x9E3779B97F4A7C15ULL /* golden ratio */
+#define ORC_PHILOX_W1 0xBB67AE8584CAA73BULL /* sqrt(3) - 1 */
+
+static void orc_mul128(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += ORC_PHILOX_W0;
+            k1 += ORC_PHILOX_W1;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        orc_mul128(ORC_PHILOX_M0, x0, &hi0, &lo0);
+        orc_mul128(ORC_PHILOX_M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0;
+        uint64_t y1 = lo1;
+        uint64_t y2 = hi0 ^ x3 ^ k1;
+        uint64_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Top 53 bits of a 64-bit word, scaled to [0, 1). */
+double orc_u01(uint64_t w)
+{
+    return (double)(w >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* ------------------------------------------------------------------ */
+/* Model: eq. (SIRD), Sec. 2.2.                                         */
+/* ------------------------------------------------------------------ */
+static void sird_rhs(double beta, double gamma, double mu, double N,
+                     const double y[4], double k[4])
+{
+    double S = y[0], I = y[1];
+    double infection = beta / N * S * I; /* (beta/N) S I */
+    k[0] = -infection;
+    k[1] = infection - (gamma + mu) * I;
+    k[2] = gamma * I;
+    k[3] = mu * I;
+}
+
+/* Segment of step n: all four stages of step n use beta_{k(n)}. */
+static int seg_of_step(long n, int seg_days, int spd, int K)
+{
+    long k = n / ((long)seg_days * (long)spd);
+    if (k > K - 1)
+        k = K - 1;
+    return (int)k;
+}
+
+/* eq. (beta): beta1 before t1, linear from beta1 to beta2 on [t1, t2),
+ * beta2 from t2 on.  t is measured in days from the window start. */
+double orc_beta_ramp(double t, double b1, double b2, double t1, double t2)
+{
+    if (t < t1)
+        return b1;
+    if (t < t2)
+        return b1 + (b2 - b1) / (t2 - t1) * (t - t1);
+    return b2;
+}
+
+static void rk4_step(double beta, double gamma, double mu, double N, double h,
+                     double y[4])
+{
+    double k1[4], k2[4], k3[4], k4[4], yt[4];
+    int c;
+    sird_rhs(beta, gamma, mu, N, y, k1);
+    for (c = 0; c < 4; ++c) yt[c] = y[c] + h / 2.0 * k1[c];
+    sird_rhs(beta, gamma, mu, N, yt, k2);
+    for (c = 0; c < 4; ++c) yt[c] = y[c] + h / 2.0 * k2[c];
+    sird_rhs(beta, gamma, mu, N, yt, k3);
+    for (c = 0; c < 4; ++c) yt[c] = y[c] + h * k3[c];
+    sird_rhs(beta, gamma, mu, N, yt, k4);
+    for (c = 0; c < 4; ++c)
+        y[c] = y[c] + h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+}
+
+static void euler_step(double beta, double gamma, double mu, double N, double h,
+                       double y[4])
+{
+    double k[4];
+    int c;
+    sird_rhs(beta, gamma, mu, N, y, k);
+    for (c = 0; c < 4; ++c) y[c] = y[c] + h * k[c];
+}
+
+/* Parameter vector of the piecewise-constant model:
+ *   theta = (beta_1 .. beta_K, gamma, mu, I0),  d = K + 3.
+ * Initial state: S = N - I0 - R0 - D0, I = I0, R = R0, D = D0. */
+static void initial_state(double N, double R0, double D0, double I0, double y[4])
+{
+    y[0] = N - I0 - R0 - D0;
+    y[1] = I0;
+    y[2] = R0;
+    y[3] = D0;
+}
+
+/* Integrate one parameter vector with RK4 over W days at spd steps/day.
+ * days (may be NULL): [4][W+1], compartment-major, state at every day.
+ * steps (may be NULL): [4][T+1], state after every step (T = W*spd). */
+void orc_integrate(int W, int spd, int seg_days, int K, double N, double R0,
+                   double D0, const double *theta, double *days, double *steps)
+{
+    double y[4];
+    double h = 1.0 / (double)spd;
+    double gamma = theta[K], mu = theta[K + 1], I0 = theta[K + 2];
+    long T = (long)W * spd;
+    initial_state(N, R0, D0, I0, y);
+    for (int c = 0; c < 4; ++c) {
+        if (days) days[(long)c * (W + 1)] = y[c];
+        if (steps) steps[(long)c * (T + 1)] = y[c];
+    }
+    for (long n = 0; n < T; ++n) {
+        double beta = theta[seg_of_step(n, seg_days, spd, K)];
+        rk4_step(beta, gamma, mu, N, h, y);
+        for (int c = 0; c < 4; ++c) {
+            if (steps) steps[(long)c * (T + 1) + n + 1] = y[c];
+            if (days && (n + 1) % spd == 0)
+                days[(long)c * (W + 1) + (n + 1) / spd] = y[c];
+        }
+    }
+}
+
+/* Paper-exact variant: forward Euler with the ramp of eq. (beta).
+ * theta = (beta1, beta2, t1, t2, gamma, mu); the window starts from the
+ * given state y0 = (S, I, R, D) (the paper takes it from the data on the
+ * first day).  beta is evaluated at the start of each step. */
+void orc_integrate_euler_ramp(int W, int spd, const double *theta,
+                              const double *y0, double N, double *days)
+{
+    double y[4];
+    double h = 1.0 / (double)spd;
+    long T = (long)W * spd;
+    for (int c = 0; c < 4; ++c) {
+        y[c] = y0[c];
+        days[(long)c * (W + 1)] = y[c];
+    }
+    for (long n = 0; n < T; ++n) {
+        double t = (double)n * h;
+        double beta = orc_beta_ramp(t, theta[0], theta[1], theta[2], theta[3]);
+        euler_step(beta, theta[4], theta[5], N, h, y);
+        if ((n + 1) % spd == 0)
+            for (int c = 0; c < 4; ++c) days[(long)c * (W + 1) + (n + 1) / spd] = y[c];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Costs, Sec. 3.1.  Dhat and y hold days 0..W (n = W + 1 values).      */
+/*   e_i = y_i - Dhat_i                                                 */
+/*   SSRE = sum_{i=1..W} ((Dhat_i - y_i) / max(y_i, 1))^2               */
+/*   MSE  = (1/n) sum e_i^2      MXSE = max e_i^2                        */
+/*   MAE  = (1/n) sum |e_i|      MAPE = (100/n) sum |e_i / max(y_i,1)|   */
+/* ------------------------------------------------------------------ */
+enum { ORC_SSRE = 0, ORC_MSE = 1, ORC_MXSE = 2, ORC_MAE = 3, ORC_MAPE = 4 };
+
+double orc_loss(int kind, int W, const double *Dhat, const double *y)
+{
+    int n = W + 1;
+    double acc = 0.0;
+    for (int i = 0; i <= W; ++i) {
+        double e = y[i] - Dhat[i];
+        double guard = y[i] > 1.0 ? y[i] : 1.0;
+        switch (kind) {
+        case ORC_SSRE:
+            if (i >= 1) {
+                double r = (Dhat[i] - y[i]) / guard;
+                acc = acc + r * r;
+            }
+            break;
+        case ORC_MSE: acc = acc + e * e; break;
+        case ORC_MXSE: {
+            /* a NaN anywhere makes the maximum NaN */
+            double sq = e * e;
+            if (i == 0 || sq > acc || isnan(sq)) acc = sq;
+            break;
+        }
+        case ORC_MAE: acc = acc + fabs(e); break;
+        case ORC_MAPE: acc = acc + fabs(e / guard); break;
+        default: return NAN;
+        }
+    }
+    if (kind == ORC_MSE || kind == ORC_MAE) acc = acc / (double)n;
+    if (kind == ORC_MAPE) acc = 100.0 * acc / (double)n;
+    return acc;
+}
+
+/* Losses of P parameter vectors (theta row-major [P][d]) on one problem. */
+void orc_loss_batch(int W, int spd, int seg_days, int K, double N, double R0,
+                    double D0, int P, const double *theta, const double *y,
+                    int kind, double *loss, int nthreads)
+{
+    int d = K + 3;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int p = 0; p < P; ++p) {
+        double *days = (double *)malloc(sizeof(double) * 4 * (size_t)(W + 1));
+        orc_integrate(W, spd, seg_days, K, N, R0, D0, theta + (long)p * d, days, NULL);
+        double l = orc_loss(kind, W, days + 3L * (W + 1), y);
+        loss[p] = l;
+        free(days);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* PSO, Sec. 3.3.                                                       */
+/* Random numbers: Philox4x64-10, key = (seed, stream).                 */
+/* A counter block (iteration, particle, m, purpose) yields four words;  */
+/* it serves the dimension pair j = 2m, 2m+1.                            */
+/*   init (purpose 0):     u_j  = u01(word 2*(j&1))                      */
+/*   velocity (purpose 1): r1_j = u01(word 2*(j&1)), r2_j = u01(word 2*(j&1)+1) */
+/* Arrays are row-major [P][d].                                          */
+/* ------------------------------------------------------------------ */
+static void philox_block(uint64_t seed, uint64_t stream, uint64_t it, uint64_t p,
+                         uint64_t m, uint64_t purpose, uint64_t out[4])
+{
+    uint64_t ctr[4] = {it, p, m, purpose};
+    uint64_t key[2] = {seed, stream};
+    orc_philox4x64_10(ctr, key, out);
+}
+
+void orc_pso_init(int P, int d, const double *lo, const double *hi,
+                  uint64_t seed, uint64_t stream, double *x, double *v,
+                  double *pbest_x, double *pbest_f, double *gbest_x,
+                  double *gbest_f, int64_t *gbest_idx)
+{
+    for (int p = 0; p < P; ++p) {
+        for (int j = 0; j < d; ++j) {
+            uint64_t w[4];
+            philox_block(seed, stream, 0, (uint64_t)p, (uint64_t)(j / 2), 0, w);
+            double u = orc_u01(w[2 * (j % 2)]);
+            double xv = lo[j] + u * (hi[j] - lo[j]);
+            x[(long)p * d + j] = xv;
+            v[(long)p * d + j] = 0.0;
+            pbest_x[(long)p * d + j] = xv;
+        }
+        pbest_f[p] = INFINITY;
+    }
+    for (int j = 0; j < d; ++j) gbest_x[j] = lo[j];
+    *gbest_f = INFINITY;
+    *gbest_idx = -1;
+}
+
+/* Personal and global bests after evaluating f = loss(x).
+ * NaN losses count as +inf.  Personal best: strict improvement.
+ * Global best: argmin of the personal bests, lowest index on ties,
+ * replacing the previous global best only on strict improvement.
+ * margin (may be NULL): the smallest relative gap of any comparison
+ * that decided an outcome in this update (near-tie detector). */
+void orc_pso_bests(int P, int d, const double *f, const double *x,
+                   double *pbest_x, double *pbest_f, double *gbest_x,
+                   double *gbest_f, int64_t *gbest_idx, double *margin)
+{
+    double mrel = INFINITY;
+    for (int p = 0; p < P; ++p) {
+        double fp = isnan(f[p]) ? INFINITY : f[p];
+        if (isfinite(fp) && isfinite(pbest_f[p])) {
+            double scale = fabs(pbest_f[p]) > fabs(fp) ? fabs(pbest_f[p]) : fabs(fp);
+            /* equal values come from equal positions and are decided
+             * identically by any implementation: they are not near-ties */
+            if (scale > 0.0 && fp != pbest_f[p]) {
+                double g = fabs(fp - pbest_f[p]) / scale;
+                if (g < mrel) mrel = g;
+            }
+        }
+        if (fp < pbest_f[p]) {
+            pbest_f[p] = fp;
+            for (int j = 0; j < d; ++j) pbest_x[(long)p * d + j] = x[(long)p * d + j];
+        }
+    }
+    int best = 0;
+    for (int p = 1; p < P; ++p)
+        if (pbest_f[p] < pbest_f[best]) best = p;
+    /* gap between the winner and the runner-up */
+    for (int p = 0; p < P; ++p) {
+        if (p == best || !isfinite(pbest_f[p]) || !isfinite(pbest_f[best])) continue;
+        if (pbest_f[p] == pbest_f[best]) continue;
+        double scale = fabs(pbest_f[p]) > fabs(pbest_f[best]) ? fabs(pbest_f[p]) : fabs(pbest_f[best]);
+        double g = scale > 0.0 ? fabs(pbest_f[p] - pbest_f[best]) / scale : 0.0;
+        if (g < mrel) mrel = g;
+    }
+    if (P > 0 && isfinite(*gbest_f) && isfinite(pbest_f[best])) {
+        double scale = fabs(*gbest_f) > fabs(pbest_f[best]) ? fabs(*gbest_f) : fabs(pbest_f[best]);
+        double g = scale > 0.0 ? fabs(*gbest_f - pbest_f[best]) / scale : 0.0;
+        if (g > 0.0 && g < mrel) mrel = g; /* an unchanged best (g == 0) decides nothing */
+    }
+    if (P > 0 && pbest_f[best] < *gbest_f) {
+        *gbest_f = pbest_f[best];
+        *gbest_idx = best;
+        for (int j = 0; j < d; ++j) gbest_x[j] = pbest_x[(long)best * d + j];
+    }
+    if (margin) *margin = mrel;
+}
+
+/* Velocity and position update of iteration it, every operation a single
+ * rounded IEEE multiply or add:
+ *   t = w*v;  t = t + (c1*r1)*(pb - x);  t = t + (c2*r2)*(g - x);
+ *   v = t;    x = min(max(x + v, lo), hi). */
+void orc_pso_move(int P, int d, uint64_t it, double w, double c1, double c2,
+                  const double *lo, const double *hi, uint64_t seed,
+                  uint64_t stream, const double *pbest_x, const double *gbest_x,
+                  double *x, double *v)
+{
+    for (int p = 0; p < P; ++p) {
+        for (int j = 0; j < d; ++j) {
+            uint64_t wd[4];
+            philox_block(seed, stream, it, (uint64_t)p, (uint64_t)(j / 2), 1, wd);
+            double r1 = orc_u01(wd[2 * (j % 2)]);
+            double r2 = orc_u01(wd[2 * (j % 2) + 1]);
+            long o = (long)p * d + j;
+            double xo = x[o];
+            double t = w * v[o];
+            double a1 = c1 * r1;
+            double d1 = pbest_x[o] - xo;
+            double a2 = c2 * r2;
+            double d2 = gbest_x[j] - xo;
+            double m1 = a1 * d1;
+            t = t + m1;
+            double m2 = a2 * d2;
+            t = t + m2;
+            v[o] = t;
+            double xn = xo + t;
+            if (xn < lo[j]) xn = lo[j];
+            if (xn > hi[j]) xn = hi[j];
+            x[o] = xn;
+        }
+    }
+}
+
+/* Whole PSO run on one problem: iters evaluations.  For it = 0..iters-1:
+ * f = loss(x); bests; record (gbest_f, gbest_idx, margin); move unless last.
+ * Final swarm state is returned through x, v, pbest_x, pbest_f, gbest_x. */
+void orc_pso_run(int W, int spd, int seg_days, int K, double N, double R0,
+                 double D0, const double *y, int kind, int P, const double *lo,
+                 const double *hi, double w, double c1, double c2, uint64_t seed,
+                 uint64_t stream, int iters, double *hist_f, int64_t *hist_idx,
+                 double *hist_margin, double *x, double *v, double *pbest_x,
+                 double *pbest_f, double *gbest_x, int nthreads)
+{
+    int d = K + 3;
+    double gbest_f;
+    int64_t gbest_idx;
+    double *f = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    orc_pso_init(P, d, lo, hi, seed, stream, x, v, pbest_x, pbest_f, gbest_x,
+                 &gbest_f, &gbest_idx);
+    for (int it = 0; it < iters; ++it) {
+        double margin;
+        orc_loss_batch(W, spd, seg_days, K, N, R0, D0, P, x, y, kind, f, nthreads);
+        orc_pso_bests(P, d, f, x, pbest_x, pbest_f, gbest_x, &gbest_f, &gbest_idx, &margin);
+        if (hist_f) hist_f[it] = gbest_f;
+        if (hist_idx) hist_idx[it] = gbest_idx;
+        if (hist_margin) hist_margin[it] = margin;
+        if (it < iters - 1)
+            orc_pso_move(P, d, (uint64_t)it, w, c1, c2, lo, hi, seed, stream,
+                         pbest_x, gbest_x, x, v);
+    }
+    free(f);
+}
+
+/* ------------------------------------------------------------------ */
+/* Gradient of the discrete loss by forward-mode differentiation.       */
+/* For each parameter j the tangent Ydot = dY/dtheta_j is carried       */
+/* through every RK4 stage:                                             */
+/*   kdot_s = J(Y_s) Ydot_s + (df/dtheta_j)(Y_s),                       */
+/*   Ydot_2 = ydot + h/2 kdot_1, Ydot_3 = ydot + h/2 kdot_2,            */
+/*   Ydot_4 = ydot + h kdot_3,                                          */
+/*   ydot+ = ydot + h/6 (kdot_1 + 2 kdot_2 + 2 kdot_3 + kdot_4),        */
+/* and dL/dtheta_j = sum_i (dl/dDhat_i) Ddot_i.                          */
+/* ------------------------------------------------------------------ */
+
+/* Jacobian-vector product of eq. (SIRD) plus the explicit parameter
+ * derivative.  which: 0 = beta (of the active segment), 1 = gamma,
+ * 2 = mu, -1 = none. */
+static void sird_tangent(double beta, double gamma, double mu, double N,
+                         const double y[4], const double yd[4], int which,
+                         double kd[4])
+{
+    double S = y[0], I = y[1];
+    double Sd = yd[0], Id = yd[1];
+    /* d[(beta/N) S I] = (beta/N)(Sd I + S Id) */
+    double infd = beta / N * (Sd * I + S * Id);
+    double dI = -(gamma + mu) * Id;
+    double dR = gamma * Id;
+    double dD = mu * Id;
+    double inf_beta = 0.0, dI_extra = 0.0, dR_extra = 0.0, dD_extra = 0.0;
+    if (which == 0) inf_beta = S * I / N;
+    if (which == 1) { dI_extra = -I; dR_extra = I; }
+    if (which == 2) { dI_extra = -I; dD_extra = I; }
+    kd[0] = -infd - inf_beta;
+    kd[1] = infd + inf_beta + dI + dI_extra;
+    kd[2] = dR + dR_extra;
+    kd[3] = dD + dD_extra;
+}
+
+/* dl/dDhat_i for the cost of the given kind (index i of days 0..W). */
+static double cost_dDhat(int kind, int W, int i, double Dhat, double y, int argmax)
+{
+    int n = W + 1;
+    double e = y - Dhat;
+    double guard = y > 1.0 ? y : 1.0;
+    double s = (e > 0.0) ? 1.0 : ((e < 0.0) ? -1.0 : 0.0);
+    switch (kind) {
+    case ORC_SSRE: return i >= 1 ? 2.0 * ((Dhat - y) / guard) / guard : 0.0;
+    case ORC_MSE: return -2.0 * e / (double)n;
+    case ORC_MXSE: return i == argmax ? -2.0 * e : 0.0;
+    case ORC_MAE: return -s / (double)n;
+    case ORC_MAPE: return -100.0 * s / guard / (double)n;
+    default: return NAN;
+    }
+}
+
+void orc_loss_grad_fwd(int W, int spd, int seg_days, int K, double N, double R0,
+                       double D0, const double *theta, const double *y, int kind,
+                       double *loss, double *grad)
+{
+    int d = K + 3;
+    long T = (long)W * spd;
+    double h = 1.0 / (double)spd;
+    double gamma = theta[K], mu = theta[K + 1], I0 = theta[K + 2];
+    double *days = (double *)malloc(sizeof(double) * 4 * (size_t)(W + 1));
+    orc_integrate(W, spd, seg_days, K, N, R0, D0, theta, days, NULL);
+    const double *Dhat = days + 3L * (W + 1);
+    *loss = orc_loss(kind, W, Dhat, y);
+    int argmax = 0;
+    if (kind == ORC_MXSE) {
+        double best = -1.0;
+        for (int i = 0; i <= W; ++i) {
+            double e = y[i] - Dhat[i];
+            if (e * e > best) { best = e * e; argmax = i; }
+        }
+    }
+    for (int j = 0; j < d; ++j) {
+        double yv[4], yd[4];
+        initial_state(N, R0, D0, I0, yv);
+        yd[0] = yd[1] = yd[2] = yd[3] = 0.0;
+        if (j == K + 2) { yd[0] = -1.0; yd[1] = 1.0; } /* dS0/dI0 = -1, dI0/dI0 = 1 */
+        double g = cost_dDhat(kind, W, 0, Dhat[0], y[0], argmax) * yd[3];
+        for (long n = 0; n < T; ++n) {
+            int k = seg_of_step(n, seg_days, spd, K);
+            double beta = theta[k];
+            int which = -1;
+            if (j == k) which = 0;
+            if (j == K) which = 1;
+            if (j == K + 1) which = 2;
+            double k1[4], k2[4], k3[4], k4[4], kd1[4], kd2[4], kd3[4], kd4[4];
+            double yt[4], ydt[4];
+            int c;
+            sird_rhs(beta, gamma, mu, N, yv, k1);
+            sird_tangent(beta, gamma, mu, N, yv, yd, which, kd1);
+            for (c = 0; c < 4; ++c) { yt[c] = yv[c] + h / 2.0 * k1[c]; ydt[c] = yd[c] + h / 2.0 * kd1[c]; }
+            sird_rhs(beta, gamma, mu, N, yt, k2);
+            sird_tangent(beta, gamma, mu, N, yt, ydt, which, kd2);
+            for (c = 0; c < 4; ++c) { yt[c] = yv[c] + h / 2.0 * k2[c]; ydt[c] = yd[c] + h / 2.0 * kd2[c]; }
+            sird_rhs(beta, gamma, mu, N, yt, k3);
+            sird_tangent(beta, gamma, mu, N, yt, ydt, which, kd3);
+            for (c = 0; c < 4; ++c) { yt[c] = yv[c] + h * k3[c]; ydt[c] = yd[c] + h * kd3[c]; }
+            sird_rhs(beta, gamma, mu, N, yt, k4);
+            sird_tangent(beta, gamma, mu, N, yt, ydt, which, kd4);
+            for (c = 0; c < 4; ++c) {
+                yv[c] = yv[c] + h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+                yd[c] = yd[c] + h / 6.0 * (kd1[c] + 2.0 * kd2[c] + 2.0 * kd3[c] + kd4[c]);
+            }
+            if ((n + 1) % spd == 0) {
+                int i = (int)((n + 1) / spd);
+                g = g + cost_dDhat(kind, W, i, Dhat[i], y[i], argmax) * yd[3];
+            }
+        }
+        grad[j] = g;
+    }
+    free(days);
+}
+
+/* ------------------------------------------------------------------ */
+/* Projected Adam (Kingma & Ba 2015) in box-normalised coordinates       */
+/* u = (theta - lo)/(hi - lo).  One step t >= 1 for n vectors [n][d].   */
+/* Dimensions with hi == lo are fixed and left untouched.               */
+/* ------------------------------------------------------------------ */
+void orc_adam_step(int n, int d, double *theta, const double *grad, double *m,
+                   double *v, const double *lo, const double *hi, int t,
+                   double lr, double b1, double b2, double eps)
+{
+    double bc1 = 1.0 - pow(b1, (double)t);
+    double bc2 = 1.0 - pow(b2, (double)t);
+    for (int q = 0; q < n; ++q) {
+        for (int j = 0; j < d; ++j) {
+            long o = (long)q * d + j;
+            double width = hi[j] - lo[j];
+            if (!(width > 0.0)) continue;
+            double u = (theta[o] - lo[j]) / width;
+            double gu = grad[o] * width;
+            m[o] = b1 * m[o] + (1.0 - b1) * gu;
+            v[o] = b2 * v[o] + (1.0 - b2) * gu * gu;
+            double mhat = m[o] / bc1;
+            double vhat = v[o] / bc2;
+            u = u - lr * mhat / (sqrt(vhat) + eps);
+            if (u < 0.0) u = 0.0;
+            if (u > 1.0) u = 1.0;
+            theta[o] = lo[j] + u * width;
+        }
+    }
+}

@@ -1,0 +1,44 @@
+"""The stored observation series are reproducible from the committed script
+(which calls only the oracle), and the workload shapes are as documented."""
+import importlib.util
+import os
+
+import numpy as np
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _maker():
+    spec = importlib.util.spec_from_file_location(
+        "make_series", os.path.join(ROOT, "synth", "make_series.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_stored_series_regenerate_bitwise(orc):
+    m = _maker()
+    for name in ("c1", "c2", "c4", "c5", "c3"):
+        fresh = m.MAKERS[name]()
+        stored = synth._load(name)
+        assert set(fresh) == set(stored)
+        for k in fresh:
+            np.testing.assert_array_equal(fresh[k], stored[k], err_msg=f"{name}.{k}")
+
+
+def test_workload_shapes():
+    assert synth.c1().particle_steps_per_iter == 256 * 600
+    assert synth.c2().particle_steps_per_iter == 8192 * 1800
+    c3 = synth.c3()
+    assert len(c3.fits) == 512 and all(28 <= f.W <= 365 for f in c3.fits)
+    assert all(f.K == -(-f.W // 14) and f.d == f.K + 3 for f in c3.fits)
+    assert len({f.stream for f in c3.fits}) == 512
+    wl, th = synth.c4()
+    assert th.shape == (65536, 16) and wl.fits[0].T == 7300
+    assert np.all(th >= wl.fits[0].lo) and np.all(th <= wl.fits[0].hi)
+    c5 = synth.c5(windows=[0, 51])
+    assert len(c5.fits) == 32 and c5.fits[-1].stream == 16 * 51 + 15
+    for f in synth.c1().fits + synth.c2().fits + c3.fits:
+        assert f.y.shape == (f.W + 1,) and np.all(np.diff(f.y) >= 0) and f.y[0] == f.D0
