@@ -1,0 +1,187 @@
+"""Throughput benchmark of the calibration hot path on one MI355X.
+
+One step = one swarm iteration over the whole batch: sird_loss (RK4 over
+every particle's window, fused with the cost) then pso_step (bests, argmin,
+Philox velocity/position update).  Default workload: 512 independent
+synthetic regions of uneven window (28..365 days) and population, 1024
+particles each, 14-day beta segments, dt = 0.1 day, FP64.
+
+Prints one JSON line: particle-RK4-steps/s of the timed steps, the roofline
+of the dominant kernel (the forward integration, timed per launch with HIP
+events on the stream it runs on) and the oracle's throughput on the host
+cores on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--dtype f64|f32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Launch configuration of the integration kernel for the batched workload
+# (block size and persistent wavefronts); chosen by the autotuner.
+C3_LAUNCH = dict(block=256, persistent=0)
+
+# Algorithmic work of one particle-step of the FP64 forward: the RK4 step in
+# the (C, I, D) form issues 4 mul + 4 add + 19 fma = 27 VALU instructions =
+# 46 flops (an FMA counts 2).  The per-day cost adds < 0.4 flop per step and
+# is not counted.
+FLOPS_PER_STEP = 46
+VALU_PER_STEP = 27
+PEAK_FP64_VECTOR = 78.6e12  # MI355X, FLOP/s
+
+METRIC = "particle·RK4-steps/sec"
+UNIT = "particle·RK4-steps/s"
+
+
+def build_workload(name, dtype):
+    import synth
+    import paper_2204_12346_amd as S
+    if name == "c3":
+        wl = synth.c3()
+        launch = C3_LAUNCH
+    elif name == "c2":
+        wl = synth.c2()
+        launch = dict(block=64, persistent=0)
+    elif name == "c1":
+        wl = synth.c1()
+        launch = dict(block=64, persistent=0)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    specs = [S.ProblemSpec.from_fit(f) for f in wl.fits]
+    b = S.Batch(specs, dtype=dtype, **launch)
+    params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
+                         wl.c2, wl.seed)
+    sw = S.Swarm(b)
+    obs = b.pack_obs([f.y for f in wl.fits])
+    return wl, b, params, sw, obs
+
+
+def cpu_baseline(wl, budget_particles):
+    """Oracle throughput on the host cores: one loss evaluation of the first
+    budget_particles particles of every problem (parameters drawn uniformly
+    in each box)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(0)
+    work = 0
+    t0 = time.perf_counter()
+    for f in wl.fits:
+        n = min(budget_particles, f.n_part)
+        th = f.lo + rng.uniform(0, 1, (n, f.d)) * (f.hi - f.lo)
+        prob = oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0)
+        oracle.loss_batch(prob, th, f.y, wl.loss, nthreads=threads)
+        work += n * f.T
+    dt = time.perf_counter() - t0
+    return {"value": work / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"one loss evaluation of {budget_particles} particles of each of the "
+                      f"{len(wl.fits)} problems ({work:.3e} particle-steps, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--dtype", default="f64")
+    ap.add_argument("--cpu-particles", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent fits would shard across GPUs with no communication)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2204_12346_amd as S
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl, b, params, sw, obs = build_workload(args.workload, args.dtype)
+    stream = torch.cuda.current_stream()
+    kind = wl.loss
+
+    S.pso_init(b, params, sw)
+    for _ in range(args.warmup):
+        S.sird_pso_iterate(b, params, sw, obs, kind, 1)
+    torch.cuda.synchronize()
+    print(f"# warmup done: {args.warmup} steps", file=sys.stderr, flush=True)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        S.sird_loss(b, sw.x, obs, kind, sw.f)
+        ev[i][1].record(stream)
+        S.pso_step(b, params, sw)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    fwd_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
+
+    steps_per_iter = b.particle_steps
+    value = steps_per_iter * args.steps / (total_ms / 1e3)
+    achieved = FLOPS_PER_STEP * steps_per_iter / (fwd_ms / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": {"c3": "batched uneven fits: 512 regions x 1024 particles, "
+                               "W 28..365 days, 14-day beta segments, dt 0.1 day",
+                         "c2": "one fit: 8192 particles, 180 days, 13 beta segments, dt 0.1",
+                         "c1": "one fit: 256 particles, 60 days, constant beta, dt 0.1"
+                         }[args.workload],
+            "problems": b.n_prob,
+            "particles": b.total_particles,
+            "particle_steps_per_step": steps_per_iter,
+            "loss": kind,
+            "launch": {"block": b.c.block, "persistent": b.c.persistent},
+        },
+        "roofline": {
+            "kernel": "k_forward (sird_loss)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP64_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VECTOR,
+            "traffic": None,
+            "kernel_ms": fwd_ms,
+            "flops_per_particle_step": FLOPS_PER_STEP,
+            "valu_issue_frac": (VALU_PER_STEP * steps_per_iter / (fwd_ms / 1e3)) /
+                               (256 * 4 * 16 * 2.4e9),
+        },
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_particles)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

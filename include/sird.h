@@ -1,0 +1,324 @@
+/*
+ * sird.h -- C ABI of the gfx950 library for batched calibration of the SIRD
+ * model (Blaszczyk, Klimczak, Mahdi, Oprocha, "On automatic calibration of
+ * the SIRD epidemiological model for COVID-19 data in Poland").
+ *
+ * What the calls compute
+ *   The model is eq. (SIRD) of Sec. 2.2:
+ *       S' = -(beta/N) S I,  I' = (beta/N) S I - (gamma + mu) I,
+ *       R' = gamma I,        D' = mu I.
+ *   A calibration window (Sec. 3.1) is W days with W+1 daily observations
+ *   y_0..y_W of cumulative deaths.  The transmission rate is
+ *   piecewise constant: beta_k on days [k*seg_days, (k+1)*seg_days), the last
+ *   segment extending to the window end (this replaces the two-level ramp of
+ *   eq. (beta); the segment of a step is fixed by the step index, so all four
+ *   stages of a step use one beta).  The integrator is classical RK4 with a
+ *   fixed step h = 1/steps_per_day (the paper's Euler scheme, Sec. 3.1 and
+ *   3.3, is replaced by a fourth-order one).  The cost (Sec. 3.1) compares the
+ *   model's deceased compartment with y; the optimiser is particle swarm
+ *   optimisation with box clamping (Sec. 3.3).
+ *
+ * Parameter vector of one particle, d = K + 3 values:
+ *       theta = (beta_1, ..., beta_K, gamma, mu, I0)
+ *   Initial state: S = N - I0 - R0 - D0, I = I0, R = R0, D = D0.
+ *   A fixed parameter is a degenerate box dimension (lo == hi).
+ *
+ * Conventions for every call
+ *   - Array arguments are DEVICE pointers owned by the caller; the library
+ *     never allocates, frees or retains them.  Host structs are read during
+ *     the call only.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *     void*; NULL = the null stream) and the call does not synchronise.
+ *   - Every call returns SIRD_OK or a negative status.  Host-side argument
+ *     checks run before any HIP call, so a rejected call has enqueued
+ *     nothing.  sird_last_error() gives a thread-local message.
+ *   - A batch holds n_prob independent problems ("fits"); a single fit is the
+ *     n_prob = 1 case of the same code path.
+ *   - Particle-indexed arrays (loss, pbest_f) have total_particles entries;
+ *     problem r owns [p_off, p_off + n_part).
+ *   - theta-shaped arrays (theta, x, v, pbest_x, grad_theta) hold, per
+ *     problem, a structure-of-arrays block [d][n_part] starting at
+ *     theta_off: parameter j of local particle p is at
+ *     theta_off + j*n_part + p.
+ *   - Box-shaped arrays (lo, hi, gbest_x) hold d values per problem starting
+ *     at box_off.
+ *   - Non-finite losses are not errors; the swarm treats NaN as +inf.
+ *   - Calls sharing a batch's scheduler counters, or the same output
+ *     buffers, must be ordered on one stream.
+ */
+#ifndef SIRD_H
+#define SIRD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define SIRD_OK 0
+#define SIRD_EINVAL (-1)   /* bad host-side argument (null, size, descriptor) */
+#define SIRD_ENOSPACE (-2) /* workspace or output too small */
+#define SIRD_EHIP (-3)     /* HIP runtime error while enqueueing */
+
+/* ------------------------------------------------------ ODE state precision */
+#define SIRD_F64 0 /* state and arithmetic in double */
+#define SIRD_F32 1 /* state (C = N - S, I, D) and arithmetic in float;
+                      theta, losses and the swarm stay double */
+
+/* ------------------------------------------------ costs of Sec. 3.1 on D */
+/* e_i = y_i - Dhat_i over days i = 0..W, n = W + 1, g_i = max(y_i, 1) */
+#define SIRD_LOSS_SSRE 0 /* sum_{i=1..W} ((Dhat_i - y_i)/g_i)^2           */
+#define SIRD_LOSS_MSE 1  /* (1/n) sum e_i^2                                */
+#define SIRD_LOSS_MXSE 2 /* max e_i^2                                      */
+#define SIRD_LOSS_MAE 3  /* (1/n) sum |e_i|                                */
+#define SIRD_LOSS_MAPE 4 /* (100/n) sum |e_i / g_i|                        */
+
+/* ------------------------------------------------------------ descriptors */
+/* One calibration window (Sec. 3.1).  96 bytes, naturally aligned. */
+typedef struct sird_problem {
+    int32_t n_days;        /* W >= 1: observations on days 0..W            */
+    int32_t steps_per_day; /* RK4 steps per day >= 1, h = 1/steps_per_day  */
+    int32_t seg_days;      /* days per beta segment >= 1                   */
+    int32_t n_seg;         /* K >= 1 beta segments; d = K + 3              */
+    int32_t n_part;        /* particles (parameter vectors) >= 0           */
+    int32_t reserved;      /* must be 0                                    */
+    double N;              /* population > 0                               */
+    double R0;             /* removed (recovered) at day 0, >= 0           */
+    double D0;             /* deceased at day 0, >= 0                      */
+    int64_t p_off;         /* first entry in particle-indexed arrays       */
+    int64_t theta_off;     /* first double of the [d][n_part] block        */
+    int64_t obs_off;       /* first of the W+1 observations in obs         */
+    int64_t traj_off;      /* first double of the [4][W+1][n_part] block   */
+    int64_t box_off;       /* first of the d values in lo, hi, gbest_x     */
+    uint64_t stream;       /* Philox key word 1 of this problem            */
+} sird_problem;
+
+/* 64 consecutive particles of one problem: the unit a wavefront integrates. */
+typedef struct sird_tile {
+    int32_t prob; /* problem index                      */
+    int32_t p0;   /* first local particle, multiple of 64 */
+} sird_tile;
+
+/* A batch of problems plus its launch plan.  Host struct; the pointers are
+ * device memory owned by the caller.  Fill it with sird_batch_plan(). */
+typedef struct sird_batch {
+    int32_t n_prob;          /* problems >= 1                                  */
+    int32_t n_tiles;         /* entries of tiles                               */
+    int32_t max_days;        /* max W over problems                            */
+    int32_t max_d;           /* max d over problems                            */
+    int64_t max_steps;       /* max W*steps_per_day over problems              */
+    int64_t total_particles; /* sum of n_part; length of particle arrays       */
+    int64_t theta_len;       /* doubles in theta-shaped arrays                 */
+    int64_t obs_len;         /* doubles in obs                                 */
+    int64_t traj_len;        /* doubles in traj                                */
+    int64_t box_len;         /* doubles in box-shaped arrays                   */
+    const sird_problem *probs; /* device copy of the problem table            */
+    const sird_tile *tiles;    /* device copy of the tile table (LPT order)   */
+    int32_t *sched;          /* device, 2 int32 zero-initialised scheduler
+                                counters; needed only when persistent > 0      */
+    int32_t dtype;           /* SIRD_F64 or SIRD_F32                           */
+    int32_t block;           /* threads per block of the integration kernels:
+                                64..1024, multiple of 64; 0 = 256               */
+    int32_t persistent;      /* 0: one wavefront per tile, tiles dispatched in
+                                table order; > 0: this many resident
+                                wavefronts pull tiles from a device counter   */
+    int32_t reserved;        /* must be 0                                      */
+} sird_batch;
+
+/* Coefficients of the swarm, Sec. 3.3 (inertia, cognitive, social), the
+ * Philox key word 0, and the search box (device, box-shaped). */
+typedef struct pso_params {
+    double w;
+    double c1;
+    double c2;
+    uint64_t seed;
+    const double *lo;
+    const double *hi;
+} pso_params;
+
+/* Swarm state, all device memory owned by the caller. */
+typedef struct pso_state {
+    double *x;          /* positions, theta-shaped                           */
+    double *v;          /* velocities, theta-shaped                          */
+    double *pbest_x;    /* personal bests, theta-shaped                      */
+    double *pbest_f;    /* personal best losses, particle-indexed            */
+    double *gbest_x;    /* global best per problem, box-shaped               */
+    double *gbest_f;    /* [n_prob]                                          */
+    int64_t *gbest_idx; /* [n_prob], local particle index, -1 before any     */
+    uint64_t *iter;     /* [2]: iteration counter and an internal counter;
+                           pso_init sets both to 0                           */
+    double *f;          /* losses of the current positions, particle-indexed */
+    double *hist_f;     /* optional [hist_len][n_prob] gbest_f per iteration */
+    int64_t *hist_idx;  /* optional [hist_len][n_prob] gbest_idx             */
+    int64_t hist_len;   /* rows of hist_*; iterations >= hist_len are not
+                           recorded                                           */
+} pso_state;
+
+/* Adam coefficients (Kingma & Ba 2015) for the projected refinement. */
+typedef struct adam_params {
+    double lr;
+    double beta1;
+    double beta2;
+    double eps;
+} adam_params;
+
+/* ------------------------------------------------------------ host helpers */
+
+/* Message for a status code.  Never NULL. */
+const char *sird_status_string(int status);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *sird_last_error(void);
+
+/* Check a host problem table against the array lengths it indexes:
+ * W, steps_per_day, seg_days, n_seg >= 1; n_part >= 0; N > 0; R0, D0 >= 0;
+ * reserved == 0; each problem's blocks lie inside [0, len) of their arrays and
+ * particle ranges inside [0, total_particles).  Pure host code.
+ * Returns SIRD_OK or SIRD_EINVAL. */
+int sird_problem_validate(const sird_problem *probs, int n_prob, int64_t total_particles,
+                          int64_t theta_len, int64_t obs_len, int64_t traj_len,
+                          int64_t box_len);
+
+/* Build the tile table of a problem table: ceil(n_part/64) tiles per
+ * problem, ordered by decreasing W*steps_per_day (longest first, so that
+ * dispatch order is a longest-processing-time schedule), ties by problem and
+ * first particle.  Writes at most max_tiles entries to tiles_out (host) and
+ * returns the tile count, or a negative status (SIRD_ENOSPACE if max_tiles is
+ * too small, SIRD_EINVAL for a bad table).  Pure host code. */
+int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile *tiles_out,
+                    int max_tiles);
+
+/* Fill the scalar fields of *batch from a host problem table (validated as
+ * in sird_problem_validate) and the given device pointers.  traj_len may be
+ * 0 if sird_integrate is not used.  block/persistent/dtype are left as the
+ * caller set them.  Pure host code. */
+int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,
+                    int64_t total_particles, int64_t theta_len, int64_t obs_len,
+                    int64_t traj_len, int64_t box_len, int n_tiles,
+                    const sird_problem *probs_dev, const sird_tile *tiles_dev,
+                    int32_t *sched_dev);
+
+/* ---------------------------------------------------------- device calls */
+
+/* RK4 trajectories (eq. (SIRD), Sec. 2.2) of every particle of every
+ * problem: S, I, R, D at days 0..W.
+ *   theta: theta-shaped input.
+ *   traj:  output, per problem a block [4][W+1][n_part] at traj_off
+ *          (compartment, day, particle); traj_len must cover every block.
+ * Errors: SIRD_EINVAL for null pointers or a bad batch, SIRD_EHIP. */
+int sird_integrate(const sird_batch *batch, const double *theta, double *traj,
+                   void *stream);
+
+/* Cost of Sec. 3.1 of every particle: RK4 over the window, the deceased
+ * compartment sampled at every day and compared with the observations.
+ *   theta: theta-shaped input.
+ *   obs:   per problem W+1 observed cumulative deaths at obs_off.
+ *   loss_kind: one of SIRD_LOSS_*.
+ *   loss:  output, particle-indexed.
+ * Errors: SIRD_EINVAL (null pointer, bad kind or batch), SIRD_EHIP. */
+int sird_loss(const sird_batch *batch, const double *theta, const double *obs,
+              int loss_kind, double *loss, void *stream);
+
+/* Initialise the swarm (Sec. 3.3): x = lo + u (hi - lo) with u from
+ * Philox4x64-10 (Salmon et al. 2011) under key (seed, problem.stream) and
+ * counter (0, local particle, j/2, 0), word 2*(j%2); v = 0; pbest_x = x;
+ * pbest_f = +inf; gbest_x = lo; gbest_f = +inf; gbest_idx = -1; iter = 0.
+ * Errors: SIRD_EINVAL (null pointer, bad batch), SIRD_EHIP. */
+int pso_init(const sird_batch *batch, const pso_params *params, const pso_state *state,
+             void *stream);
+
+/* One swarm iteration (Sec. 3.3) given state->f = loss(state->x) of
+ * iteration it = state->iter[0]:
+ *   1. personal bests: NaN f counts as +inf; f < pbest_f replaces (f, x);
+ *   2. global best per problem: argmin of pbest_f, lowest index on ties,
+ *      replacing gbest only on strict improvement; recorded in hist_* row it;
+ *   3. velocity and position with r1, r2 from Philox counter
+ *      (it, local particle, j/2, 1), words 2*(j%2) and 2*(j%2)+1:
+ *        t = w v; t = t + (c1 r1)(pbest - x); t = t + (c2 r2)(gbest - x);
+ *        v = t;   x = min(max(x + v, lo), hi)
+ *      each operation a single rounded IEEE multiply or add (no fusion);
+ *   4. iter[0] = it + 1.
+ * Errors: SIRD_EINVAL (null pointer, bad batch), SIRD_EHIP. */
+int pso_step(const sird_batch *batch, const pso_params *params, const pso_state *state,
+             void *stream);
+
+/* n_iters iterations of [sird_loss(state->x) -> state->f; pso_step], the
+ * whole hot path of one calibration iteration, enqueued eagerly. */
+int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
+                     const pso_state *state, const double *obs, int loss_kind,
+                     int n_iters, void *stream);
+
+/* Gradient of the cost with respect to theta by the discrete adjoint of the
+ * RK4 scheme (reverse mode through every stage).  The forward pass stores
+ * the state every ckpt_interval steps in the workspace; the reverse sweep
+ * recomputes each interval from its checkpoint.  The result does not depend
+ * on ckpt_interval (bitwise).
+ *   grad_loss: optional particle-indexed upstream gradient (NULL = 1).
+ *   grad_theta: output, theta-shaped: grad_loss[p] * dL/dtheta.
+ *   loss_out: optional particle-indexed output of the loss itself.
+ *   ckpt_interval: steps between checkpoints, 0 = ceil(sqrt(max_steps)).
+ *   workspace: device scratch of at least
+ *       sird_loss_backward_workspace(batch, ckpt_interval) bytes, 256-byte
+ *       aligned; contents on entry are ignored.
+ * The deceased-count costs are piecewise smooth: MXSE takes the first day
+ * attaining the maximum, MAE/MAPE take sign(0) = 0.
+ * Errors: SIRD_EINVAL, SIRD_ENOSPACE (workspace too small), SIRD_EHIP.
+ * Only SIRD_F64 batches are supported (SIRD_EINVAL otherwise). */
+int sird_loss_backward(const sird_batch *batch, const double *theta, const double *obs,
+                       int loss_kind, const double *grad_loss, double *grad_theta,
+                       double *loss_out, int ckpt_interval, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* Workspace bytes needed by sird_loss_backward (0 on a bad batch). */
+size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval);
+
+/* Indices (local to each problem) of the k particles with the smallest
+ * pbest_f, ordered by (pbest_f, index), NaN last.  idx_out: device [n_prob][k];
+ * problems with fewer than k particles pad with -1.
+ * Errors: SIRD_EINVAL (k < 1 or k > 1024, null pointer), SIRD_EHIP. */
+int pso_topk(const sird_batch *batch, const double *pbest_f, int k, int64_t *idx_out,
+             void *stream);
+
+/* Gather columns of a theta-shaped source array into the theta-shaped
+ * array of another batch: dst problem r, particle q takes source problem r,
+ * local particle idx[r*k + q] (q < k, dst n_part == k for every problem,
+ * same d); idx -1 copies the source box lower bound lo.
+ * Errors: SIRD_EINVAL, SIRD_EHIP. */
+int sird_gather(const sird_batch *src, const double *src_theta, const double *src_lo,
+                const sird_batch *dst, double *dst_theta, const int64_t *idx, int k,
+                void *stream);
+
+/* One projected Adam step (Kingma & Ba 2015) on every particle, in
+ * box-normalised coordinates u = (theta - lo)/(hi - lo) (lo, hi box-shaped):
+ *   g_u = grad (hi - lo); m = b1 m + (1-b1) g_u; v = b2 v + (1-b2) g_u^2;
+ *   u = clamp(u - lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps), 0, 1);
+ *   theta = lo + u (hi - lo).   Dimensions with hi == lo are left alone.
+ * theta, grad, m, v: theta-shaped.  t >= 1 is the step number.
+ * Errors: SIRD_EINVAL, SIRD_EHIP. */
+int sird_adam_step(const sird_batch *batch, double *theta, const double *grad, double *m,
+                   double *v, const double *lo, const double *hi, int64_t t,
+                   const adam_params *params, void *stream);
+
+/* Capture iters_per_launch iterations of sird_pso_iterate into a HIP graph
+ * (captured on an internal stream; no memset nodes).  Every array the
+ * iterations touch must stay allocated while the graph exists; the swarm
+ * iteration counter lives in device memory so replays continue the run.
+ * *graph_out receives an opaque handle.
+ * Errors: SIRD_EINVAL, SIRD_EHIP. */
+int sird_graph_create(const sird_batch *batch, const pso_params *params,
+                      const pso_state *state, const double *obs, int loss_kind,
+                      int iters_per_launch, void **graph_out);
+
+/* Launch a captured graph n_launches times on stream. */
+int sird_graph_launch(void *graph, int n_launches, void *stream);
+
+/* Release a captured graph (NULL is accepted). */
+int sird_graph_destroy(void *graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIRD_H */

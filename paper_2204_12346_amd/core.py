@@ -1,0 +1,330 @@
+"""Python face of the C ABI: batches of calibration problems, swarm state,
+and one function per entry point with the C name.
+
+Only argument marshalling happens here; the arithmetic of every call runs in
+the HIP kernels of ``libsird.so``.  PyTorch provides device memory and the
+stream (torch's current stream unless one is given).
+
+Layouts (see ``include/sird.h``):
+  * theta-shaped arrays: per problem a ``[d][n_part]`` block at ``theta_off``;
+  * particle-indexed arrays: ``total_particles`` entries, problem r at
+    ``[p_off, p_off + n_part)``;
+  * box-shaped arrays: ``d`` values per problem at ``box_off``.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import LOSS, SIRD_F32, SIRD_F64, check, lib, ptr, stream_handle
+
+
+def _kind(kind):
+    return LOSS[kind] if isinstance(kind, str) else int(kind)
+
+
+class ProblemSpec:
+    """One calibration window.  theta = (beta_1..beta_K, gamma, mu, I0)."""
+
+    def __init__(self, W, spd, seg_days, K, N, R0=0.0, D0=0.0, n_part=0, stream=0):
+        self.W, self.spd, self.seg_days, self.K = int(W), int(spd), int(seg_days), int(K)
+        self.N, self.R0, self.D0 = float(N), float(R0), float(D0)
+        self.n_part, self.stream = int(n_part), int(stream)
+
+    @property
+    def d(self):
+        return self.K + 3
+
+    @property
+    def T(self):
+        return self.W * self.spd
+
+    @classmethod
+    def from_fit(cls, f, n_part=None):
+        return cls(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0,
+                   f.n_part if n_part is None else n_part, f.stream)
+
+
+class Batch:
+    """A planned batch of problems resident on one device."""
+
+    def __init__(self, specs: Sequence[ProblemSpec], dtype="f64", block=0, persistent=0,
+                 with_traj=False, device="cuda"):
+        specs = list(specs)
+        n = len(specs)
+        tab = np.zeros(n, dtype=_lib.PROBLEM_DTYPE)
+        p_off = theta_off = obs_off = traj_off = box_off = 0
+        for r, s in enumerate(specs):
+            tab[r] = (s.W, s.spd, s.seg_days, s.K, s.n_part, 0, s.N, s.R0, s.D0,
+                      p_off, theta_off, obs_off, traj_off if with_traj else 0, box_off, s.stream)
+            p_off += s.n_part
+            theta_off += s.d * s.n_part
+            obs_off += s.W + 1
+            if with_traj:
+                traj_off += 4 * (s.W + 1) * s.n_part
+            box_off += s.d
+        self.specs = specs
+        self.table = tab
+        self.total_particles = p_off
+        self.theta_len = theta_off
+        self.obs_len = obs_off
+        self.traj_len = traj_off
+        self.box_len = box_off
+        n_tiles_max = sum((s.n_part + 63) // 64 for s in specs)
+        tiles = np.zeros(max(n_tiles_max, 1), dtype=_lib.TILE_DTYPE)
+        nt = lib().sird_plan_tiles(tab.ctypes.data, n, tiles.ctypes.data, len(tiles))
+        check(nt if nt < 0 else 0, "sird_plan_tiles")
+        self.n_tiles = nt
+        self.tiles_host = tiles[:nt]
+        self.device = torch.device(device)
+        self.probs_dev = torch.from_numpy(tab.view(np.uint8).copy()).to(self.device)
+        self.tiles_dev = torch.from_numpy(tiles.view(np.uint8).copy()).to(self.device)
+        self.sched_dev = torch.zeros(2, dtype=torch.int32, device=self.device)
+        b = _lib.sird_batch()
+        b.dtype = SIRD_F32 if dtype in ("f32", SIRD_F32) else SIRD_F64
+        b.block = int(block)
+        b.persistent = int(persistent)
+        b.reserved = 0
+        check(lib().sird_batch_plan(ctypes.byref(b), tab.ctypes.data, n, p_off, theta_off,
+                                    obs_off, traj_off, box_off, nt, ptr(self.probs_dev),
+                                    ptr(self.tiles_dev), ptr(self.sched_dev)),
+              "sird_batch_plan")
+        self.c = b
+
+    # ------------------------------------------------------------ config
+    def configure(self, block=None, persistent=None, dtype=None):
+        if block is not None:
+            self.c.block = int(block)
+        if persistent is not None:
+            self.c.persistent = int(persistent)
+        if dtype is not None:
+            self.c.dtype = SIRD_F32 if dtype in ("f32", SIRD_F32) else SIRD_F64
+        return self
+
+    @property
+    def n_prob(self):
+        return len(self.specs)
+
+    @property
+    def particle_steps(self):
+        return sum(s.n_part * s.T for s in self.specs)
+
+    # ------------------------------------------------------------ layout
+    def pack_theta(self, per_problem: Sequence[np.ndarray]) -> torch.Tensor:
+        """List of (n_part, d) arrays -> theta-shaped device tensor."""
+        out = np.zeros(self.theta_len)
+        for s, row, a in zip(self.specs, self.table, per_problem):
+            a = np.asarray(a, dtype=np.float64)
+            assert a.shape == (s.n_part, s.d), (a.shape, s.n_part, s.d)
+            o = int(row["theta_off"])
+            out[o:o + s.d * s.n_part] = a.T.reshape(-1)
+        return torch.from_numpy(out).to(self.device)
+
+    def unpack_theta(self, t: torch.Tensor) -> List[np.ndarray]:
+        h = t.detach().cpu().numpy()
+        res = []
+        for s, row in zip(self.specs, self.table):
+            o = int(row["theta_off"])
+            res.append(h[o:o + s.d * s.n_part].reshape(s.d, s.n_part).T.copy())
+        return res
+
+    def pack_obs(self, per_problem: Sequence[np.ndarray]) -> torch.Tensor:
+        out = np.zeros(self.obs_len)
+        for s, row, y in zip(self.specs, self.table, per_problem):
+            y = np.asarray(y, dtype=np.float64)
+            assert y.shape == (s.W + 1,)
+            o = int(row["obs_off"])
+            out[o:o + s.W + 1] = y
+        return torch.from_numpy(out).to(self.device)
+
+    def pack_box(self, per_problem: Sequence[np.ndarray]) -> torch.Tensor:
+        out = np.zeros(self.box_len)
+        for s, row, v in zip(self.specs, self.table, per_problem):
+            v = np.asarray(v, dtype=np.float64)
+            assert v.shape == (s.d,)
+            o = int(row["box_off"])
+            out[o:o + s.d] = v
+        return torch.from_numpy(out).to(self.device)
+
+    def unpack_box(self, t: torch.Tensor) -> List[np.ndarray]:
+        h = t.detach().cpu().numpy()
+        return [h[int(r["box_off"]):int(r["box_off"]) + s.d].copy()
+                for s, r in zip(self.specs, self.table)]
+
+    def split_particles(self, t: torch.Tensor) -> List[np.ndarray]:
+        h = t.detach().cpu().numpy()
+        return [h[int(r["p_off"]):int(r["p_off"]) + s.n_part].copy()
+                for s, r in zip(self.specs, self.table)]
+
+    def unpack_traj(self, t: torch.Tensor) -> List[np.ndarray]:
+        """traj tensor -> list of (n_part, 4, W+1) arrays."""
+        h = t.detach().cpu().numpy()
+        res = []
+        for s, row in zip(self.specs, self.table):
+            o = int(row["traj_off"])
+            blk = h[o:o + 4 * (s.W + 1) * s.n_part].reshape(4, s.W + 1, s.n_part)
+            res.append(np.transpose(blk, (2, 0, 1)).copy())
+        return res
+
+    def empty_theta(self):
+        return torch.empty(self.theta_len, dtype=torch.float64, device=self.device)
+
+    def empty_particles(self):
+        return torch.empty(max(self.total_particles, 1), dtype=torch.float64,
+                           device=self.device)
+
+
+class Swarm:
+    """Device swarm state of a batch (pso_state)."""
+
+    def __init__(self, batch: Batch, hist_len=0):
+        dev = batch.device
+        th = max(batch.theta_len, 1)
+        P = max(batch.total_particles, 1)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.x = torch.zeros(th, **f64)
+        self.v = torch.zeros(th, **f64)
+        self.pbest_x = torch.zeros(th, **f64)
+        self.pbest_f = torch.zeros(P, **f64)
+        self.gbest_x = torch.zeros(max(batch.box_len, 1), **f64)
+        self.gbest_f = torch.zeros(batch.n_prob, **f64)
+        self.gbest_idx = torch.zeros(batch.n_prob, dtype=torch.int64, device=dev)
+        self.iter = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.f = torch.zeros(P, **f64)
+        self.hist_len = int(hist_len)
+        if hist_len:
+            self.hist_f = torch.full((hist_len, batch.n_prob), float("nan"), **f64)
+            self.hist_idx = torch.full((hist_len, batch.n_prob), -2, dtype=torch.int64,
+                                       device=dev)
+        else:
+            self.hist_f = self.hist_idx = None
+        s = _lib.pso_state()
+        s.x, s.v, s.pbest_x, s.pbest_f = ptr(self.x), ptr(self.v), ptr(self.pbest_x), ptr(self.pbest_f)
+        s.gbest_x, s.gbest_f, s.gbest_idx = ptr(self.gbest_x), ptr(self.gbest_f), ptr(self.gbest_idx)
+        s.iter, s.f = ptr(self.iter), ptr(self.f)
+        s.hist_f, s.hist_idx, s.hist_len = ptr(self.hist_f), ptr(self.hist_idx), self.hist_len
+        self.c = s
+
+
+class PsoParams:
+    def __init__(self, batch: Batch, lo, hi, w=0.7, c1=1.5, c2=1.5, seed=0):
+        """lo, hi: box-shaped device tensors (or per-problem lists)."""
+        self.lo = lo if isinstance(lo, torch.Tensor) else batch.pack_box(lo)
+        self.hi = hi if isinstance(hi, torch.Tensor) else batch.pack_box(hi)
+        p = _lib.pso_params()
+        p.w, p.c1, p.c2, p.seed = float(w), float(c1), float(c2), int(seed)
+        p.lo, p.hi = ptr(self.lo), ptr(self.hi)
+        self.c = p
+
+
+# ------------------------------------------------------------------ calls
+def sird_integrate(batch: Batch, theta, traj=None, stream=None):
+    if traj is None:
+        traj = torch.empty(max(batch.traj_len, 1), dtype=torch.float64, device=batch.device)
+    check(lib().sird_integrate(ctypes.byref(batch.c), ptr(theta), ptr(traj),
+                               stream_handle(stream)), "sird_integrate")
+    return traj
+
+
+def sird_loss(batch: Batch, theta, obs, kind="ssre", loss=None, stream=None):
+    if loss is None:
+        loss = batch.empty_particles()
+    check(lib().sird_loss(ctypes.byref(batch.c), ptr(theta), ptr(obs), _kind(kind), ptr(loss),
+                          stream_handle(stream)), "sird_loss")
+    return loss
+
+
+def pso_init(batch: Batch, params: PsoParams, swarm: Swarm, stream=None):
+    check(lib().pso_init(ctypes.byref(batch.c), ctypes.byref(params.c), ctypes.byref(swarm.c),
+                         stream_handle(stream)), "pso_init")
+
+
+def pso_step(batch: Batch, params: PsoParams, swarm: Swarm, stream=None):
+    check(lib().pso_step(ctypes.byref(batch.c), ctypes.byref(params.c), ctypes.byref(swarm.c),
+                         stream_handle(stream)), "pso_step")
+
+
+def sird_pso_iterate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre",
+                     n_iters=1, stream=None):
+    check(lib().sird_pso_iterate(ctypes.byref(batch.c), ctypes.byref(params.c),
+                                 ctypes.byref(swarm.c), ptr(obs), _kind(kind), int(n_iters),
+                                 stream_handle(stream)), "sird_pso_iterate")
+
+
+def sird_loss_backward_workspace(batch: Batch, ckpt_interval=0):
+    return int(lib().sird_loss_backward_workspace(ctypes.byref(batch.c), int(ckpt_interval)))
+
+
+def sird_loss_backward(batch: Batch, theta, obs, kind="ssre", grad_loss=None,
+                       grad_theta=None, loss_out=None, ckpt_interval=0, workspace=None,
+                       stream=None):
+    """Returns (grad_theta, loss_out)."""
+    if grad_theta is None:
+        grad_theta = batch.empty_theta()
+    if workspace is None:
+        nbytes = sird_loss_backward_workspace(batch, ckpt_interval)
+        workspace = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=batch.device)
+    check(lib().sird_loss_backward(ctypes.byref(batch.c), ptr(theta), ptr(obs), _kind(kind),
+                                   ptr(grad_loss), ptr(grad_theta), ptr(loss_out),
+                                   int(ckpt_interval), ptr(workspace), workspace.numel(),
+                                   stream_handle(stream)), "sird_loss_backward")
+    return grad_theta, loss_out
+
+
+def pso_topk(batch: Batch, pbest_f, k, idx_out=None, stream=None):
+    if idx_out is None:
+        idx_out = torch.empty((batch.n_prob, k), dtype=torch.int64, device=batch.device)
+    check(lib().pso_topk(ctypes.byref(batch.c), ptr(pbest_f), int(k), ptr(idx_out),
+                         stream_handle(stream)), "pso_topk")
+    return idx_out
+
+
+def sird_gather(src: Batch, src_theta, src_lo, dst: Batch, idx, k, dst_theta=None,
+                stream=None):
+    if dst_theta is None:
+        dst_theta = dst.empty_theta()
+    check(lib().sird_gather(ctypes.byref(src.c), ptr(src_theta), ptr(src_lo), ctypes.byref(dst.c),
+                            ptr(dst_theta), ptr(idx), int(k), stream_handle(stream)),
+          "sird_gather")
+    return dst_theta
+
+
+def sird_adam_step(batch: Batch, theta, grad, m, v, lo, hi, t, lr=1e-3, beta1=0.9,
+                   beta2=0.999, eps=1e-8, stream=None):
+    p = _lib.adam_params(lr, beta1, beta2, eps)
+    check(lib().sird_adam_step(ctypes.byref(batch.c), ptr(theta), ptr(grad), ptr(m), ptr(v),
+                               ptr(lo), ptr(hi), int(t), ctypes.byref(p),
+                               stream_handle(stream)), "sird_adam_step")
+
+
+class Graph:
+    """HIP graph of iters_per_launch [sird_loss -> pso_step] iterations."""
+
+    def __init__(self, batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre",
+                 iters_per_launch=1):
+        h = ctypes.c_void_p()
+        check(lib().sird_graph_create(ctypes.byref(batch.c), ctypes.byref(params.c),
+                                      ctypes.byref(swarm.c), ptr(obs), _kind(kind),
+                                      int(iters_per_launch), ctypes.byref(h)),
+              "sird_graph_create")
+        self.h = h
+        self.iters_per_launch = int(iters_per_launch)
+        self._keep = (batch, params, swarm, obs)
+
+    def launch(self, n=1, stream=None):
+        check(lib().sird_graph_launch(self.h, int(n), stream_handle(stream)), "sird_graph_launch")
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            check(lib().sird_graph_destroy(self.h), "sird_graph_destroy")
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

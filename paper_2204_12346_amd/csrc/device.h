@@ -1,0 +1,223 @@
+// Device-side building blocks of the gfx950 SIRD library: the RK4 step of
+// eq. (SIRD), Philox4x64-10, wavefront helpers and the per-day cost
+// accumulation of Sec. 3.1.
+//
+// Everything here is wave64 (CDNA4).  Control flow that depends on the
+// problem (days, steps, segments) is uniform across a wavefront because a
+// wavefront integrates 64 particles of one problem.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sird.h"
+
+namespace sird {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- RK4 step
+// State (S, I, R, D) as in eq. (SIRD).  With b = beta/N the infection term
+// is p = b S I and the right-hand side is (-p, p - lam I, gamma I, mu I),
+// lam = gamma + mu.  Classical RK4 with stages Y1 = y, Y2 = y + h/2 k1,
+// Y3 = y + h/2 k2, Y4 = y + h k3 and y+ = y + h/6 (k1 + 2k2 + 2k3 + k4).
+// Only S and I feed back, so the update needs two sums,
+//     P = p1 + 2p2 + 2p3 + p4,   J = I1 + 2I2 + 2I3 + I4,
+// with S+ = S - h/6 P, I+ = I + h/6 (P - lam J), R+ = R + h/6 gamma J,
+// D+ = D + h/6 mu J.  In double: 27 VALU operations per step without R
+// (4 mul, 4 add, 19 fma), 28 with R.
+template <typename R>
+struct StepConst {
+    R b;      // beta / N of the current segment
+    R lam;    // gamma + mu
+    R h;      // step
+    R h2;     // h / 2
+    R h6;     // h / 6
+    R h6lam;  // h/6 * lam
+    R h6mu;   // h/6 * mu
+    R h6g;    // h/6 * gamma
+};
+
+// The state of one particle.  In float, each component carries the running
+// compensation of Kahan's summation (W. Kahan, "Further remarks on reducing
+// truncation errors", CACM 1965): a step's increments are small next to the
+// state (S is close to N early in an epidemic), and without compensation
+// their rounding accumulates to ~1e-5 over 1800 steps.  In double the
+// compensation fields stay zero and are never touched.
+template <typename R>
+struct SirdState {
+    R S, I, Rr, D;
+    R eS, eI, eR, eD;
+};
+
+template <typename R>
+__device__ __forceinline__ void kahan_add(R &s, R &e, R inc)
+{
+    const R y = inc - e;
+    const R t = s + y;
+    e = (t - s) - y;
+    s = t;
+}
+
+// Compensated value of a state component, in double.
+template <typename R>
+__device__ __forceinline__ double state_value(R s, R e)
+{
+    return (double)s - (double)e;
+}
+
+template <typename R, bool WITH_R>
+__device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
+{
+    const R S = y.S, I = y.I;
+    const R p1 = (k.b * S) * I;
+    const R q1 = fma(-k.lam, I, p1);
+    const R S2 = fma(-k.h2, p1, S);
+    const R I2 = fma(k.h2, q1, I);
+
+    const R p2 = (k.b * S2) * I2;
+    const R q2 = fma(-k.lam, I2, p2);
+    const R S3 = fma(-k.h2, p2, S);
+    const R I3 = fma(k.h2, q2, I);
+
+    const R p3 = (k.b * S3) * I3;
+    const R q3 = fma(-k.lam, I3, p3);
+    const R S4 = fma(-k.h, p3, S);
+    const R I4 = fma(k.h, q3, I);
+
+    const R p4 = (k.b * S4) * I4;
+
+    const R P = fma(R(2), p2 + p3, p1 + p4);
+    const R J = fma(R(2), I2 + I3, I + I4);
+    if constexpr (sizeof(R) == 8) {
+        y.S = fma(-k.h6, P, S);
+        y.I = fma(k.h6, P, fma(-k.h6lam, J, I));
+        if (WITH_R) y.Rr = fma(k.h6g, J, y.Rr);
+        y.D = fma(k.h6mu, J, y.D);
+    } else {
+        kahan_add(y.S, y.eS, -(k.h6 * P));
+        kahan_add(y.I, y.eI, fma(k.h6, P, -(k.h6lam * J)));
+        if (WITH_R) kahan_add(y.Rr, y.eR, k.h6g * J);
+        kahan_add(y.D, y.eD, k.h6mu * J);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ StepConst<R> step_const(double gamma, double mu, int spd)
+{
+    const double h = 1.0 / (double)spd;
+    const double h6 = h / 6.0;
+    StepConst<R> k;
+    k.b = R(0);
+    k.lam = (R)(gamma + mu);
+    k.h = (R)h;
+    k.h2 = (R)(0.5 * h);
+    k.h6 = (R)h6;
+    k.h6lam = (R)(h6 * (gamma + mu));
+    k.h6mu = (R)(h6 * mu);
+    k.h6g = (R)(h6 * gamma);
+    return k;
+}
+
+// ------------------------------------------------------------ costs (3.1)
+// One day's contribution of the deceased-count cost; y the observation,
+// w = 1/max(y, 1), i the day index (SSRE skips day 0).
+__device__ __forceinline__ void cost_accum(int kind, double &acc, double D, double y,
+                                           double w, int i)
+{
+    switch (kind) {
+    case SIRD_LOSS_SSRE:
+        if (i > 0) {
+            const double r = (D - y) * w;
+            acc = fma(r, r, acc);
+        }
+        break;
+    case SIRD_LOSS_MSE: {
+        const double e = y - D;
+        acc = fma(e, e, acc);
+        break;
+    }
+    case SIRD_LOSS_MXSE: {
+        const double e = y - D;
+        const double sq = e * e;
+        if (i == 0 || sq > acc || sq != sq) acc = sq;  // a NaN sticks
+        break;
+    }
+    case SIRD_LOSS_MAE: acc += fabs(y - D); break;
+    case SIRD_LOSS_MAPE: acc += fabs((y - D) * w); break;
+    default: break;
+    }
+}
+
+__device__ __forceinline__ double cost_finish(int kind, double acc, int W)
+{
+    const double n = (double)(W + 1);
+    if (kind == SIRD_LOSS_MSE || kind == SIRD_LOSS_MAE) return acc / n;
+    if (kind == SIRD_LOSS_MAPE) return 100.0 * acc / n;
+    return acc;
+}
+
+// --------------------------------------------------------- Philox4x64-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): ten rounds of two 64x64->128 products with fixed multipliers,
+// xor with the key, key bumped by Weyl constants between rounds.
+struct Philox4x64 {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                    uint64_t c3, uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull;
+    constexpr uint64_t M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull;
+    constexpr uint64_t W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    Philox4x64 out;
+    out.w[0] = c0;
+    out.w[1] = c1;
+    out.w[2] = c2;
+    out.w[3] = c3;
+    return out;
+}
+
+// Top 53 bits scaled to [0, 1): exact in double.
+__device__ __forceinline__ double u01(uint64_t x)
+{
+    return (double)(x >> 11) * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------- wave helpers
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_uniform(T v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Index of this wavefront's tile in a launch of one wavefront per tile,
+// made wavefront-uniform so that everything derived from it lives in SGPRs.
+__device__ __forceinline__ int wave_tile_index()
+{
+    return wave_uniform((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+}
+
+}  // namespace sird

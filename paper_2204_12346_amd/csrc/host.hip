@@ -1,0 +1,172 @@
+// Host-side part of the C ABI: status strings, problem-table validation,
+// the longest-first tile plan and the per-call batch checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/sird.h"
+#include "internal.h"
+
+namespace sird {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int status, const std::string &msg)
+{
+    set_error(msg);
+    return status;
+}
+
+int hip_status(hipError_t e, const char *who)
+{
+    if (e == hipSuccess) return SIRD_OK;
+    return fail(SIRD_EHIP, std::string(who) + ": " + hipGetErrorString(e));
+}
+
+int check_batch(const sird_batch *b, const char *who)
+{
+    const std::string w(who);
+    if (!b) return fail(SIRD_EINVAL, w + ": batch is NULL");
+    if (b->n_prob < 1) return fail(SIRD_EINVAL, w + ": n_prob < 1");
+    if (b->n_tiles < 0) return fail(SIRD_EINVAL, w + ": n_tiles < 0");
+    if (b->max_days < 1 || b->max_d < 4 || b->max_steps < 1)
+        return fail(SIRD_EINVAL, w + ": batch not planned (max_days/max_d/max_steps)");
+    if (!b->probs) return fail(SIRD_EINVAL, w + ": probs is NULL");
+    if (b->n_tiles > 0 && !b->tiles) return fail(SIRD_EINVAL, w + ": tiles is NULL");
+    if (b->dtype != SIRD_F64 && b->dtype != SIRD_F32)
+        return fail(SIRD_EINVAL, w + ": dtype must be SIRD_F64 or SIRD_F32");
+    if (b->block != 0 && (b->block < 64 || b->block > 1024 || b->block % 64 != 0))
+        return fail(SIRD_EINVAL, w + ": block must be 0 or a multiple of 64 in [64, 1024]");
+    if (b->persistent < 0) return fail(SIRD_EINVAL, w + ": persistent < 0");
+    if (b->persistent > 0 && !b->sched)
+        return fail(SIRD_EINVAL, w + ": persistent launch needs sched counters");
+    if (b->reserved != 0) return fail(SIRD_EINVAL, w + ": reserved must be 0");
+    return SIRD_OK;
+}
+
+int integ_block(const sird_batch *b) { return b->block ? b->block : 256; }
+
+}  // namespace sird
+
+using namespace sird;
+
+extern "C" const char *sird_status_string(int status)
+{
+    switch (status) {
+    case SIRD_OK: return "SIRD_OK: success";
+    case SIRD_EINVAL: return "SIRD_EINVAL: invalid argument";
+    case SIRD_ENOSPACE: return "SIRD_ENOSPACE: workspace or output too small";
+    case SIRD_EHIP: return "SIRD_EHIP: HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *sird_last_error(void) { return g_last_error.c_str(); }
+
+static bool range_ok(int64_t off, int64_t count, int64_t len)
+{
+    return off >= 0 && count >= 0 && off <= len && count <= len - off;
+}
+
+extern "C" int sird_problem_validate(const sird_problem *probs, int n_prob,
+                                     int64_t total_particles, int64_t theta_len,
+                                     int64_t obs_len, int64_t traj_len, int64_t box_len)
+{
+    if (!probs) return fail(SIRD_EINVAL, "sird_problem_validate: probs is NULL");
+    if (n_prob < 1) return fail(SIRD_EINVAL, "sird_problem_validate: n_prob < 1");
+    for (int r = 0; r < n_prob; ++r) {
+        const sird_problem &p = probs[r];
+        char buf[160];
+        auto bad = [&](const char *what) {
+            std::snprintf(buf, sizeof buf, "sird_problem_validate: problem %d: %s", r, what);
+            return fail(SIRD_EINVAL, buf);
+        };
+        if (p.n_days < 1) return bad("n_days < 1");
+        if (p.steps_per_day < 1) return bad("steps_per_day < 1");
+        if (p.seg_days < 1) return bad("seg_days < 1");
+        if (p.n_seg < 1) return bad("n_seg < 1");
+        if (p.n_part < 0) return bad("n_part < 0");
+        if (p.reserved != 0) return bad("reserved != 0");
+        if ((int64_t)p.n_days * p.steps_per_day > (int64_t)1 << 30)
+            return bad("n_days * steps_per_day too large");
+        if (p.n_days > (1 << 20) || p.n_seg > (1 << 20)) return bad("n_days or n_seg too large");
+        if (!(p.N > 0.0) || !std::isfinite(p.N)) return bad("N must be finite and > 0");
+        if (!(p.R0 >= 0.0) || !(p.D0 >= 0.0) || !std::isfinite(p.R0) || !std::isfinite(p.D0))
+            return bad("R0 and D0 must be finite and >= 0");
+        const int64_t d = (int64_t)p.n_seg + 3;
+        if (!range_ok(p.p_off, p.n_part, total_particles)) return bad("particle range");
+        if (!range_ok(p.theta_off, d * p.n_part, theta_len)) return bad("theta block");
+        if (obs_len > 0 && !range_ok(p.obs_off, (int64_t)p.n_days + 1, obs_len))
+            return bad("obs block");
+        if (traj_len > 0 && !range_ok(p.traj_off, 4 * ((int64_t)p.n_days + 1) * p.n_part, traj_len))
+            return bad("traj block");
+        if (!range_ok(p.box_off, d, box_len)) return bad("box block");
+    }
+    return SIRD_OK;
+}
+
+extern "C" int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile *tiles_out,
+                               int max_tiles)
+{
+    if (!probs || n_prob < 1) return fail(SIRD_EINVAL, "sird_plan_tiles: bad problem table");
+    std::vector<sird_tile> t;
+    for (int r = 0; r < n_prob; ++r) {
+        if (probs[r].n_part < 0) return fail(SIRD_EINVAL, "sird_plan_tiles: n_part < 0");
+        for (int p0 = 0; p0 < probs[r].n_part; p0 += kTileParticles) t.push_back({r, p0});
+    }
+    if ((int64_t)t.size() > (int64_t)max_tiles || (max_tiles > 0 && !tiles_out && !t.empty()))
+        return fail(SIRD_ENOSPACE, "sird_plan_tiles: tile table too small");
+    std::stable_sort(t.begin(), t.end(), [&](const sird_tile &a, const sird_tile &b) {
+        const int64_t ta = (int64_t)probs[a.prob].n_days * probs[a.prob].steps_per_day;
+        const int64_t tb = (int64_t)probs[b.prob].n_days * probs[b.prob].steps_per_day;
+        return ta > tb;
+    });
+    for (size_t i = 0; i < t.size(); ++i) tiles_out[i] = t[i];
+    return (int)t.size();
+}
+
+extern "C" int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,
+                               int64_t total_particles, int64_t theta_len, int64_t obs_len,
+                               int64_t traj_len, int64_t box_len, int n_tiles,
+                               const sird_problem *probs_dev, const sird_tile *tiles_dev,
+                               int32_t *sched_dev)
+{
+    if (!batch) return fail(SIRD_EINVAL, "sird_batch_plan: batch is NULL");
+    int st = sird_problem_validate(probs_host, n_prob, total_particles, theta_len, obs_len,
+                                   traj_len, box_len);
+    if (st != SIRD_OK) return st;
+    int64_t tiles = 0;
+    int max_days = 0, max_d = 0;
+    int64_t max_steps = 0;
+    for (int r = 0; r < n_prob; ++r) {
+        const sird_problem &p = probs_host[r];
+        tiles += (p.n_part + kTileParticles - 1) / kTileParticles;
+        max_days = std::max(max_days, p.n_days);
+        max_d = std::max(max_d, p.n_seg + 3);
+        max_steps = std::max(max_steps, (int64_t)p.n_days * p.steps_per_day);
+    }
+    if (tiles != n_tiles)
+        return fail(SIRD_EINVAL, "sird_batch_plan: n_tiles does not match the problem table");
+    if (!probs_dev) return fail(SIRD_EINVAL, "sird_batch_plan: probs_dev is NULL");
+    if (n_tiles > 0 && !tiles_dev) return fail(SIRD_EINVAL, "sird_batch_plan: tiles_dev is NULL");
+    batch->n_prob = n_prob;
+    batch->n_tiles = n_tiles;
+    batch->max_days = max_days;
+    batch->max_d = max_d;
+    batch->max_steps = max_steps;
+    batch->total_particles = total_particles;
+    batch->theta_len = theta_len;
+    batch->obs_len = obs_len;
+    batch->traj_len = traj_len;
+    batch->box_len = box_len;
+    batch->probs = probs_dev;
+    batch->tiles = tiles_dev;
+    batch->sched = sched_dev;
+    return SIRD_OK;
+}

@@ -1,0 +1,33 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/sird.h"
+
+namespace sird {
+
+// Particles per tile: one wavefront of 64 lanes, one particle per lane.
+constexpr int kTileParticles = 64;
+
+// Thread-local error message behind sird_last_error().
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+
+// Scalar checks of a batch that every device call repeats (cheap; the table
+// itself is checked by sird_batch_plan).
+int check_batch(const sird_batch *b, const char *who);
+
+// Map a HIP status after enqueueing to SIRD_OK / SIRD_EHIP.
+int hip_status(hipError_t e, const char *who);
+
+// Threads per block of the integration kernels for this batch.
+int integ_block(const sird_batch *b);
+
+// Launch geometry of the per-tile kernels: blocks of 256 threads, one
+// wavefront per tile.
+inline int tile_blocks(int n_tiles) { return (n_tiles + 3) / 4; }
+
+}  // namespace sird

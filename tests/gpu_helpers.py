@@ -1,0 +1,109 @@
+"""Helpers of the GPU parity tests: building batches from synthetic fits,
+random parameter vectors in a box, and the parity criteria.
+
+Parity criteria (FP64 unless stated):
+  * trajectories, FP64: |x_gpu - x_ref| <= 1e-12 |x_ref| per compartment and
+    day;
+  * trajectories, FP32 state: |x_gpu - x_ref| <= 1e-5 max_{t' <= t} |x_ref(t')|
+    per compartment, i.e. relative to the largest value the compartment has
+    held so far.  Float rounding is relative to the values the state passed
+    through: a compartment that has decayed by dozens of e-folds (I of a
+    dying epidemic) carries the rounding of its earlier, larger values, and
+    no float evaluation matches it per value to 1e-5;
+  * losses: |L_gpu - L_ref| <= eps max(L_ref, kappa), where kappa is the
+    first-order sensitivity of the cost to relative changes of the model's
+    deceased values (sum of |dl/dDhat_i| |Dhat_i|), so that a loss near zero
+    (a noise-free fit) is judged by the size of its terms, not by itself.
+"""
+import numpy as np
+import torch
+
+import oracle
+import paper_2204_12346_amd as S
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def need_gpu():
+    import pytest
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def oracle_problem(f):
+    return oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0)
+
+
+def random_theta(f, n, seed):
+    rng = np.random.default_rng(seed)
+    return f.lo + rng.uniform(0, 1, (n, f.d)) * (f.hi - f.lo)
+
+
+def kappa(kind, Dhat, y):
+    """Sum over days of |dl/dDhat_i| |Dhat_i| for the cost of this kind."""
+    Dhat = np.asarray(Dhat, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(y)
+    e = y - Dhat
+    g = np.maximum(y, 1.0)
+    if kind == "ssre":
+        t = 2 * np.abs(Dhat - y) / g / g * np.abs(Dhat)
+        t[0] = 0.0
+        return float(t.sum())
+    if kind == "mse":
+        return float((2 * np.abs(e) * np.abs(Dhat)).sum() / n)
+    if kind == "mxse":
+        i = int(np.argmax(e * e))
+        return float(2 * abs(e[i]) * abs(Dhat[i]))
+    if kind == "mae":
+        return float(np.abs(Dhat).sum() / n)
+    if kind == "mape":
+        return float(100 * (np.abs(Dhat) / g).sum() / n)
+    raise ValueError(kind)
+
+
+def assert_loss_close(got, ref, kap, eps, what=""):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    kap = np.asarray(kap)
+    bound = eps * np.maximum(np.abs(ref), kap)
+    bad = ~(np.abs(got - ref) <= bound)
+    # identical non-finite values agree
+    bad &= ~((~np.isfinite(ref)) & (np.isnan(got) == np.isnan(ref)) &
+             ((got == ref) | np.isnan(ref)))
+    if bad.any():
+        i = int(np.argmax(bad))
+        raise AssertionError(f"{what}: {bad.sum()} losses off, first #{i}: gpu={got[i]!r} "
+                             f"ref={ref[i]!r} kappa={kap[i]!r} bound={bound[i]!r}")
+
+
+def assert_traj_close(got, ref, eps, what=""):
+    """got/ref: (4, W+1); relative per compartment over days with ref != 0."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    nz = ref != 0
+    rel = np.zeros_like(ref)
+    rel[nz] = np.abs(got[nz] - ref[nz]) / np.abs(ref[nz])
+    assert np.all(got[~nz] == 0) or np.all(np.abs(got[~nz]) < 1e-300 + eps), what
+    worst = rel.max()
+    assert worst <= eps, f"{what}: worst relative error {worst:.3e} > {eps:.0e}"
+
+
+def assert_traj_close_running_max(got, ref, eps, what=""):
+    """got/ref: (4, W+1); error relative to each compartment's running max."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    scale = np.maximum.accumulate(np.abs(ref), axis=1)
+    err = np.abs(got - ref)
+    ok = err <= eps * scale
+    if not ok.all():
+        c, t = np.argwhere(~ok)[0]
+        raise AssertionError(f"{what}: compartment {'SIRD'[c]} day {t}: gpu={got[c, t]!r} "
+                             f"ref={ref[c, t]!r} running max={scale[c, t]!r}")
+
+
+def make_batch(fits, n_parts=None, **kw):
+    specs = [S.ProblemSpec.from_fit(f, None if n_parts is None else n_parts[i])
+             for i, f in enumerate(fits)]
+    return S.Batch(specs, **kw)

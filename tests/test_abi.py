@@ -1,0 +1,201 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/sird.h declares, its structs have the layout the binding assumes,
+and host-side argument checks reject bad input before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sird.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2204_12346_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2204_12346_amd import build
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(n for n in set(names) if n not in ("defined",))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("sird_integrate", "sird_loss", "pso_step", "sird_loss_backward"):
+        assert required in names
+    assert len(names) == 18, names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(L.SIGNATURES)
+
+
+def test_struct_layout_matches_binding(tmp_path, L):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "sird.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sird_problem), sizeof(sird_tile),
+         sizeof(sird_batch), sizeof(pso_params), sizeof(pso_state), sizeof(adam_params));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(sird_problem, N), offsetof(sird_problem, p_off),
+         offsetof(sird_problem, stream), offsetof(sird_batch, probs), offsetof(sird_batch, dtype));
+  printf("%zu %zu\n", offsetof(pso_state, f), offsetof(pso_state, hist_len));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    vals = [int(x) for x in out]
+    assert vals[0] == L.PROBLEM_DTYPE.itemsize == 96
+    assert vals[1] == L.TILE_DTYPE.itemsize == 8
+    assert vals[2] == ctypes.sizeof(L.sird_batch)
+    assert vals[3] == ctypes.sizeof(L.pso_params)
+    assert vals[4] == ctypes.sizeof(L.pso_state)
+    assert vals[5] == ctypes.sizeof(L.adam_params)
+    assert vals[6] == L.PROBLEM_DTYPE.fields["N"][1]
+    assert vals[7] == L.PROBLEM_DTYPE.fields["p_off"][1]
+    assert vals[8] == L.PROBLEM_DTYPE.fields["stream"][1]
+    assert vals[9] == L.sird_batch.probs.offset
+    assert vals[10] == L.sird_batch.dtype.offset
+    assert vals[11] == L.pso_state.f.offset
+    assert vals[12] == L.pso_state.hist_len.offset
+
+
+def _table(rows):
+    from paper_2204_12346_amd import _lib
+    t = np.zeros(len(rows), dtype=_lib.PROBLEM_DTYPE)
+    for i, r in enumerate(rows):
+        for k, v in r.items():
+            t[i][k] = v
+    return t
+
+
+def _good(**kw):
+    r = dict(n_days=10, steps_per_day=4, seg_days=7, n_seg=2, n_part=70, N=1e6,
+             p_off=0, theta_off=0, obs_off=0, traj_off=0, box_off=0)
+    r.update(kw)
+    return r
+
+
+def test_status_strings_and_last_error(L):
+    lib = L.lib()
+    for s in (0, -1, -2, -3, 7):
+        assert lib.sird_status_string(s)
+    assert lib.sird_status_string(-2).startswith(b"SIRD_ENOSPACE")
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(n_days=0), b"n_days"), (dict(steps_per_day=0), b"steps_per_day"),
+    (dict(seg_days=0), b"seg_days"), (dict(n_seg=0), b"n_seg"), (dict(n_part=-1), b"n_part"),
+    (dict(N=0.0), b"N must"), (dict(N=float("nan")), b"N must"), (dict(R0=-1.0), b"R0"),
+    (dict(reserved=3), b"reserved"), (dict(p_off=1), b"particle"),
+    (dict(theta_off=1), b"theta"), (dict(obs_off=1), b"obs"), (dict(box_off=1), b"box"),
+])
+def test_validate_rejects(L, bad, msg):
+    lib = L.lib()
+    t = _table([_good(**bad)])
+    st = lib.sird_problem_validate(t.ctypes.data, 1, 70, 5 * 70, 11, 0, 5)
+    assert st == L.SIRD_EINVAL
+    assert msg in lib.sird_last_error()
+
+
+def test_validate_accepts_and_checks_lengths(L):
+    lib = L.lib()
+    t = _table([_good(), _good(p_off=70, theta_off=350, obs_off=11, box_off=5, n_part=0)])
+    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 350, 22, 0, 10) == 0
+    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 349, 22, 0, 10) == L.SIRD_EINVAL
+    assert lib.sird_problem_validate(None, 2, 70, 350, 22, 0, 10) == L.SIRD_EINVAL
+    assert lib.sird_problem_validate(t.ctypes.data, 0, 70, 350, 22, 0, 10) == L.SIRD_EINVAL
+
+
+def test_plan_tiles_longest_first(L):
+    lib = L.lib()
+    t = _table([_good(n_days=10, n_part=130), _good(n_days=30, n_part=64),
+                _good(n_days=20, n_part=1), _good(n_days=50, n_part=0)])
+    out = np.zeros(10, dtype=L.TILE_DTYPE)
+    n = lib.sird_plan_tiles(t.ctypes.data, 4, out.ctypes.data, 10)
+    assert n == 5
+    got = [(int(a), int(b)) for a, b in out[:n]]
+    assert got == [(1, 0), (2, 0), (0, 0), (0, 64), (0, 128)]
+    assert lib.sird_plan_tiles(t.ctypes.data, 4, out.ctypes.data, 4) == L.SIRD_ENOSPACE
+
+
+def test_device_calls_reject_bad_arguments_without_a_gpu(L):
+    lib = L.lib()
+    null = ctypes.c_void_p()
+    # NULL batch
+    assert lib.sird_loss(None, null, null, 0, null, None) == L.SIRD_EINVAL
+    assert lib.sird_integrate(None, null, null, None) == L.SIRD_EINVAL
+    assert lib.pso_step(None, None, None, None) == L.SIRD_EINVAL
+    assert lib.sird_loss_backward(None, null, null, 0, null, null, null, 0, null, 0,
+                                  None) == L.SIRD_EINVAL
+    assert lib.sird_graph_launch(None, 1, None) == L.SIRD_EINVAL
+    assert lib.sird_graph_destroy(None) == 0
+    # an unplanned batch
+    b = L.sird_batch()
+    assert lib.sird_loss(ctypes.byref(b), null, null, 0, null, None) == L.SIRD_EINVAL
+    assert b"not planned" in lib.sird_last_error() or b"n_prob" in lib.sird_last_error()
+    assert lib.sird_loss_backward_workspace(ctypes.byref(b), 0) == 0
+
+
+def test_batch_plan_and_per_call_checks_on_host(L):
+    import torch
+    from paper_2204_12346_amd import core
+    specs = [core.ProblemSpec(30, 10, 14, 3, 1e6, n_part=100, stream=0),
+             core.ProblemSpec(12, 5, 7, 2, 1e5, n_part=0, stream=1),
+             core.ProblemSpec(45, 2, 14, 4, 1e7, n_part=65, stream=2)]
+    b = core.Batch(specs, device="cpu", with_traj=True)
+    assert b.n_tiles == 2 + 0 + 2
+    assert b.c.max_days == 45 and b.c.max_d == 7 and b.c.max_steps == 300
+    assert b.total_particles == 165 and b.theta_len == 6 * 100 + 7 * 65
+    assert b.obs_len == 31 + 13 + 46 and b.box_len == 6 + 5 + 7
+    lib = L.lib()
+    dummy = torch.zeros(8, dtype=torch.float64)
+    for kind in (-1, 5):
+        assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), kind,
+                             dummy.data_ptr(), None) == L.SIRD_EINVAL
+    b.c.dtype = 7
+    assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
+                         dummy.data_ptr(), None) == L.SIRD_EINVAL
+    b.c.dtype = 0
+    b.c.block = 96
+    assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
+                         dummy.data_ptr(), None) == L.SIRD_EINVAL
+    b.c.block = 0
+    ws = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 0)
+    s = int(np.ceil(np.sqrt(300)))
+    assert ws == (2 * int(np.ceil(300 / s)) + 2 * s + 46) * 165 * 8
+    # too small a workspace is reported before anything is enqueued
+    st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
+                                dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 16, None)
+    assert st == L.SIRD_ENOSPACE
+
+
+def test_layout_round_trip_on_host():
+    from paper_2204_12346_amd import core
+    specs = [core.ProblemSpec(5, 2, 3, 2, 1e4, n_part=7), core.ProblemSpec(4, 1, 2, 1, 1e4, n_part=3)]
+    b = core.Batch(specs, device="cpu")
+    rng = np.random.default_rng(0)
+    th = [rng.normal(size=(7, 5)), rng.normal(size=(3, 4))]
+    t = b.pack_theta(th)
+    back = b.unpack_theta(t)
+    for a, c in zip(th, back):
+        np.testing.assert_array_equal(a, c)
+    # SoA: parameter j of particle p of problem 0 is at j*7 + p
+    assert t[2 * 7 + 4].item() == th[0][4, 2]

@@ -1,0 +1,123 @@
+"""GPU parity of the discrete-adjoint gradient (sird_loss_backward) against
+the oracle's forward-mode gradient and against central differences of the
+GPU's own loss; bitwise independence of the checkpoint interval."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2204_12346_amd as S
+from gpu_helpers import make_batch, need_gpu, oracle_problem, random_theta
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def assert_grad_close(got, ref, what=""):
+    """|g - g_ref| <= 1e-6 |g_ref| + 1e-9 max|g_ref| per component."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    tol = GRAD_RTOL * np.abs(ref) + 1e-9 * np.max(np.abs(ref))
+    bad = ~(np.abs(got - ref) <= tol)
+    if bad.any():
+        j = int(np.argmax(bad))
+        raise AssertionError(f"{what}: component {j}: gpu={got[j]!r} ref={ref[j]!r}")
+
+
+@pytest.mark.parametrize("shape", ["c1", "c2"])
+@pytest.mark.parametrize("kind", ["ssre", "mse", "mxse", "mae", "mape"])
+def test_adjoint_matches_forward_mode(shape, kind):
+    f = (synth.c1() if shape == "c1" else synth.c2()).fits[0]
+    P = 70
+    th = random_theta(f, P, seed=3)
+    th[:, :f.K] *= 0.5  # keep most trajectories away from total burn-out
+    b = make_batch([f], [P])
+    g, L = S.sird_loss_backward(b, b.pack_theta([th]), b.pack_obs([f.y]), kind,
+                                loss_out=b.empty_particles())
+    gg = b.unpack_theta(g)[0]
+    LL = L.cpu().numpy()
+    lf = S.sird_loss(b, b.pack_theta([th]), b.pack_obs([f.y]), kind).cpu().numpy()
+    assert np.array_equal(LL[:P], lf[:P])  # the backward's own forward is the forward
+    prob = oracle_problem(f)
+    for p in range(0, P, 3):
+        Lr, gr = oracle.loss_grad_fwd(prob, th[p], f.y, kind)
+        assert_grad_close(gg[p], gr, f"{shape}/{kind}/particle {p}")
+
+
+def test_checkpoint_interval_is_bitwise_irrelevant():
+    f = synth.c2().fits[0]
+    th = random_theta(f, 100, seed=4)
+    b = make_batch([f], [100])
+    theta, obs = b.pack_theta([th]), b.pack_obs([f.y])
+    ref = None
+    for s in (0, 1, 7, 43, 1800, 5000):
+        g, _ = S.sird_loss_backward(b, theta, obs, "ssre", ckpt_interval=s)
+        h = g.cpu().numpy()
+        if ref is None:
+            ref = h
+        assert np.array_equal(h, ref), s
+
+
+def test_grad_loss_scales_and_batched_uneven():
+    wl = synth.c3(regions=list(range(10)))
+    n_parts = [33, 64, 1, 90, 0, 128, 65, 5, 40, 70]
+    ths = [random_theta(f, n, seed=r) for r, (f, n) in enumerate(zip(wl.fits, n_parts))]
+    b = make_batch(wl.fits, n_parts)
+    theta, obs = b.pack_theta(ths), b.pack_obs([f.y for f in wl.fits])
+    scale = torch.linspace(-2, 3, b.total_particles, dtype=torch.float64, device=theta.device)
+    g1, _ = S.sird_loss_backward(b, theta, obs, "mse")
+    g2, _ = S.sird_loss_backward(b, theta, obs, "mse", grad_loss=scale)
+    G1, G2 = b.unpack_theta(g1), b.unpack_theta(g2)
+    sc = b.split_particles(scale)
+    for r, f in enumerate(wl.fits):
+        if n_parts[r] == 0:
+            continue
+        np.testing.assert_array_equal(G2[r], G1[r] * sc[r][:, None])
+        prob = oracle_problem(f)
+        for p in {0, n_parts[r] - 1}:
+            assert_grad_close(G1[r][p], oracle.loss_grad_fwd(prob, ths[r][p], f.y, "mse")[1],
+                              f"region {r} particle {p}")
+
+
+def test_adjoint_matches_central_differences_of_gpu_loss():
+    f = synth.c2().fits[0]
+    th0 = random_theta(f, 1, seed=8)[0]
+    th0[:f.K] *= 0.6
+    d = f.d
+    # rows: theta, then theta +- h e_j
+    h = np.where(th0 != 0, 1e-6 * np.abs(th0), 1e-6 * (f.hi - f.lo))
+    rows = [th0]
+    for j in range(d):
+        for sgn in (1, -1):
+            t = th0.copy()
+            t[j] += sgn * h[j]
+            rows.append(t)
+    rows = np.array(rows)
+    b = make_batch([f], [len(rows)])
+    theta, obs = b.pack_theta([rows]), b.pack_obs([f.y])
+    L = S.sird_loss(b, theta, obs, "ssre").cpu().numpy()
+    g, _ = S.sird_loss_backward(b, theta, obs, "ssre")
+    g0 = b.unpack_theta(g)[0][0]
+    fd = np.array([(L[1 + 2 * j] - L[2 + 2 * j]) / (2 * h[j]) for j in range(d)])
+    np.testing.assert_allclose(g0, fd, rtol=1e-5, atol=1e-7 * np.abs(fd).max())
+
+
+def test_full_size_gradient_workload_sampled():
+    """65536 parameter vectors on a 365-day window at dt = 0.05 (7300 steps),
+    sqrt(T) checkpoints; a sample checked against the oracle."""
+    wl, thetas = synth.c4()
+    f = wl.fits[0]
+    b = make_batch([f])
+    theta, obs = b.pack_theta([thetas]), b.pack_obs([f.y])
+    g, L = S.sird_loss_backward(b, theta, obs, "ssre", loss_out=b.empty_particles())
+    gg = b.unpack_theta(g)[0]
+    prob = oracle_problem(f)
+    for p in (0, 12345, 65535):
+        Lr, gr = oracle.loss_grad_fwd(prob, thetas[p], f.y, "ssre")
+        assert_grad_close(gg[p], gr, f"particle {p}")

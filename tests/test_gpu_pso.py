@@ -1,0 +1,180 @@
+"""GPU parity of the swarm (pso_init, pso_step, sird_pso_iterate, graphs)
+against the oracle: bitwise in lockstep, and the global-best sequence of
+whole runs up to the first near-tie the oracle reports."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2204_12346_amd as S
+from gpu_helpers import make_batch, need_gpu, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+NEAR_TIE = 1e-9  # relative margin below which a swarm decision is a near-tie
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _swarm_to_oracle(b, sw, r=0):
+    """Copy problem r of a device swarm into an oracle Swarm."""
+    s = b.specs[r]
+    o = oracle.Swarm(s.n_part, s.d)
+    o.x[:] = b.unpack_theta(sw.x)[r]
+    o.v[:] = b.unpack_theta(sw.v)[r]
+    o.pbest_x[:] = b.unpack_theta(sw.pbest_x)[r]
+    o.pbest_f[:] = b.split_particles(sw.pbest_f)[r]
+    o.gbest_x[:] = b.unpack_box(sw.gbest_x)[r]
+    o.gbest_f[0] = sw.gbest_f[r].item()
+    o.gbest_idx[0] = sw.gbest_idx[r].item()
+    return o
+
+
+def test_init_bitwise():
+    wl = synth.c3(regions=[0, 1, 2])
+    n_parts = [70, 1, 130]
+    b = make_batch(wl.fits, n_parts)
+    params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], seed=wl.seed)
+    sw = S.Swarm(b)
+    S.pso_init(b, params, sw)
+    torch.cuda.synchronize()
+    for r, f in enumerate(wl.fits):
+        ref = oracle.pso_init(n_parts[r], f.lo, f.hi, wl.seed, f.stream)
+        got = _swarm_to_oracle(b, sw, r)
+        assert np.array_equal(got.x, ref.x) and np.array_equal(got.pbest_x, ref.x)
+        assert np.all(got.v == 0) and np.all(np.isinf(got.pbest_f))
+        assert np.array_equal(got.gbest_x, f.lo) and got.gbest_idx[0] == -1
+    assert sw.iter.cpu().tolist() == [0, 0]
+
+
+def test_step_lockstep_bitwise():
+    """Same f and state on both sides -> bitwise equal bests and moves."""
+    wl = synth.c3(regions=[3, 4])
+    n_parts = [200, 77]
+    b = make_batch(wl.fits, n_parts)
+    params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], w=0.7, c1=1.5,
+                         c2=1.5, seed=wl.seed)
+    sw = S.Swarm(b, hist_len=8)
+    S.pso_init(b, params, sw)
+    rng = np.random.default_rng(0)
+    refs = [oracle.pso_init(n, f.lo, f.hi, wl.seed, f.stream) for f, n in zip(wl.fits, n_parts)]
+    for it in range(6):
+        fs = [rng.uniform(0, 10, n) for n in n_parts]
+        for r in range(2):
+            fs[r][rng.integers(0, n_parts[r], 5)] = np.nan
+            fs[r][:3] = fs[r][3]  # exact ties
+        f_all = np.concatenate(fs)
+        sw.f.copy_(torch.from_numpy(f_all).to(sw.f.device))
+        S.pso_step(b, params, sw)
+        torch.cuda.synchronize()
+        for r, f in enumerate(wl.fits):
+            oracle.pso_bests(refs[r], fs[r])
+            oracle.pso_move(refs[r], it, 0.7, 1.5, 1.5, f.lo, f.hi, wl.seed, f.stream)
+            got = _swarm_to_oracle(b, sw, r)
+            assert np.array_equal(got.pbest_f, refs[r].pbest_f), (it, r)
+            assert np.array_equal(got.pbest_x, refs[r].pbest_x), (it, r)
+            assert got.gbest_idx[0] == refs[r].gbest_idx[0] and got.gbest_f[0] == refs[r].gbest_f[0]
+            assert np.array_equal(got.gbest_x, refs[r].gbest_x)
+            assert np.array_equal(got.v, refs[r].v), (it, r)
+            assert np.array_equal(got.x, refs[r].x), (it, r)
+        assert sw.iter[0].item() == it + 1 and sw.iter[1].item() == 0
+    hf = sw.hist_f.cpu().numpy()
+    assert np.all(np.isfinite(hf[:6])) and np.all(np.isnan(hf[6:]))
+
+
+def _run_compare(wl, fits, n_parts, iters, kind="ssre"):
+    b = make_batch(fits, n_parts)
+    params = S.PsoParams(b, [f.lo for f in fits], [f.hi for f in fits], wl.w, wl.c1, wl.c2,
+                         wl.seed)
+    sw = S.Swarm(b, hist_len=iters)
+    obs = b.pack_obs([f.y for f in fits])
+    S.pso_init(b, params, sw)
+    S.sird_pso_iterate(b, params, sw, obs, kind, iters)
+    torch.cuda.synchronize()
+    gh_f = sw.hist_f.cpu().numpy()
+    gh_i = sw.hist_idx.cpu().numpy()
+    for r, f in enumerate(fits):
+        hf, hidx, hm, _ = oracle.pso_run(oracle_problem(f), f.y, kind, n_parts[r], f.lo, f.hi,
+                                         wl.w, wl.c1, wl.c2, wl.seed, f.stream, iters,
+                                         nthreads=8)
+        tie = np.nonzero(hm < NEAR_TIE)[0]
+        upto = int(tie[0]) if len(tie) else iters
+        print(f"problem {r}: comparing {upto} of {iters} iterations", flush=True)
+        assert upto >= min(iters, 20), f"oracle near-tie too early ({upto})"
+        np.testing.assert_array_equal(gh_i[:upto, r], hidx[:upto])
+        np.testing.assert_allclose(gh_f[:upto, r], hf[:upto], rtol=1e-11, atol=0)
+    return b, sw
+
+
+def test_full_run_constant_beta_workload():
+    wl = synth.c1()  # 256 particles x 200 iterations
+    _run_compare(wl, wl.fits, [256], wl.iters)
+
+
+def test_run_segmented_beta_workload_reduced():
+    wl = synth.c2()
+    _run_compare(wl, wl.fits, [1024], 25)
+
+
+def test_run_batched_uneven_workload_reduced():
+    wl = synth.c3(regions=list(range(12)))
+    _run_compare(wl, wl.fits, [64 + 37 * r for r in range(12)], 15)
+
+
+def test_graph_replay_equals_eager():
+    wl = synth.c3(regions=list(range(8)))
+    n_parts = [128] * 8
+    results = []
+    for mode in ("eager", "graph"):
+        b = make_batch(wl.fits, n_parts)
+        params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
+                             wl.c2, wl.seed)
+        sw = S.Swarm(b, hist_len=12)
+        obs = b.pack_obs([f.y for f in wl.fits])
+        S.pso_init(b, params, sw)
+        if mode == "eager":
+            S.sird_pso_iterate(b, params, sw, obs, "ssre", 12)
+        else:
+            g = S.Graph(b, params, sw, obs, "ssre", iters_per_launch=3)
+            for _ in range(4):  # replays with host work and syncs between them
+                g.launch(1)
+                torch.cuda.synchronize()
+                _ = sw.gbest_f.cpu()
+            g.close()
+        torch.cuda.synchronize()
+        results.append([t.cpu().numpy().copy() for t in
+                        (sw.x, sw.v, sw.pbest_f, sw.gbest_f, sw.hist_f, sw.hist_idx, sw.iter)])
+    for a, c in zip(*results):
+        assert np.array_equal(a, c, equal_nan=True)
+
+
+def test_resume_is_bitwise():
+    wl = synth.c1(n_part=128)
+    f = wl.fits[0]
+    outs = []
+    for split in (None, 7):
+        b = make_batch([f], [128])
+        params = S.PsoParams(b, [f.lo], [f.hi], wl.w, wl.c1, wl.c2, wl.seed)
+        sw = S.Swarm(b)
+        obs = b.pack_obs([f.y])
+        S.pso_init(b, params, sw)
+        if split is None:
+            S.sird_pso_iterate(b, params, sw, obs, "ssre", 14)
+        else:
+            S.sird_pso_iterate(b, params, sw, obs, "ssre", split)
+            torch.cuda.synchronize()
+            saved = {k: getattr(sw, k).clone() for k in
+                     ("x", "v", "pbest_x", "pbest_f", "gbest_x", "gbest_f", "gbest_idx", "iter")}
+            sw2 = S.Swarm(b)
+            for k, v in saved.items():
+                getattr(sw2, k).copy_(v)
+            S.sird_pso_iterate(b, params, sw2, obs, "ssre", 14 - split)
+            sw = sw2
+        torch.cuda.synchronize()
+        outs.append((sw.x.cpu().numpy(), sw.pbest_f.cpu().numpy(), sw.gbest_idx.cpu().numpy()))
+    for a, c in zip(*outs):
+        assert np.array_equal(a, c)
