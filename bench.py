@@ -30,16 +30,32 @@ sys.path.insert(0, ROOT)
 # (block size and persistent wavefronts); chosen by the autotuner.
 C3_LAUNCH = dict(block=256, persistent=0)
 
-# Algorithmic work of one particle-step of the FP64 forward: the RK4 step in
-# the (C, I, D) form issues 4 mul + 4 add + 19 fma = 27 VALU instructions =
-# 46 flops (an FMA counts 2).  The per-day cost adds < 0.4 flop per step and
+# Algorithmic work of one particle-step of the FP64 forward: the RK4 step of
+# the (S, I, D) state issues 8 mul + 4 add + 15 fma = 27 VALU instructions =
+# 42 flops (an FMA counts 2).  The per-day cost adds < 0.4 flop per step and
 # is not counted.
-FLOPS_PER_STEP = 46
+FLOPS_PER_STEP = 42
 VALU_PER_STEP = 27
 PEAK_FP64_VECTOR = 78.6e12  # MI355X, FLOP/s
 
+# HBM bytes per k_forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (scaled by the copy-probe factors 2.0 / 1.0), recorded with the hash of the
+# kernel sources they were taken on; reported only while the sources match.
+MEASURED_TRAFFIC = {
+    "c3": {"bytes": 2.0 * 36978.9 * 1024 + 1.0 * 4096.0 * 1024,
+           "sources": "f84f6ab73ae039d1",
+           "summary": "profiles/k_forward_batched_512x1024.md"},
+}
+
 METRIC = "particle·RK4-steps/sec"
 UNIT = "particle·RK4-steps/s"
+
+
+def kernel_source_hash():
+    import hashlib
+    files = [os.path.join(ROOT, "paper_2204_12346_amd", "csrc", f)
+             for f in ("forward.hip", "device.h")]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in files)).hexdigest()[:16]
 
 
 def build_workload(name, dtype):
@@ -65,25 +81,45 @@ def build_workload(name, dtype):
     return wl, b, params, sw, obs
 
 
-def cpu_baseline(wl, budget_particles):
-    """Oracle throughput on the host cores: one loss evaluation of the first
-    budget_particles particles of every problem (parameters drawn uniformly
-    in each box)."""
+def cpu_baseline(wl, budget_s):
+    """Oracle throughput on the host cores (OpenMP over particles, as the
+    oracle stands): whole-batch loss evaluations of the workload (every
+    particle of every problem, parameters uniform in each box), repeated
+    while the elapsed time is below budget_s (at least one)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rng = np.random.default_rng(0)
+    thetas = [f.lo + rng.uniform(0, 1, (f.n_part, f.d)) * (f.hi - f.lo) for f in wl.fits]
+    probs = [oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0) for f in wl.fits]
     work = 0
+    reps = 0
     t0 = time.perf_counter()
-    for f in wl.fits:
-        n = min(budget_particles, f.n_part)
-        th = f.lo + rng.uniform(0, 1, (n, f.d)) * (f.hi - f.lo)
-        prob = oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0)
-        oracle.loss_batch(prob, th, f.y, wl.loss, nthreads=threads)
-        work += n * f.T
+    while True:
+        for f, th, prob in zip(wl.fits, thetas, probs):
+            oracle.loss_batch(prob, th, f.y, wl.loss, nthreads=threads)
+            work += f.n_part * f.T
+            if time.perf_counter() - t0 > budget_s:
+                break
+        reps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
     dt = time.perf_counter() - t0
     return {"value": work / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"one loss evaluation of {budget_particles} particles of each of the "
-                      f"{len(wl.fits)} problems ({work:.3e} particle-steps, {dt:.1f} s)"}
+            "sample": f"whole-batch loss evaluations of the same workload, stopped after "
+                      f"{budget_s:.0f} s: {work:.3e} particle-steps in {dt:.1f} s"}
+
+
+def copy_probe(mib):
+    """A plain device copy of known size (for scaling HBM byte counters)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "launches": 3}))
 
 
 def main():
@@ -93,9 +129,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--dtype", default="f64")
-    ap.add_argument("--cpu-particles", type=int, default=96)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="search the launch shape before timing instead of the recorded one")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(independent fits would shard across GPUs with no communication)",
@@ -111,6 +153,11 @@ def main():
     kind = wl.loss
 
     S.pso_init(b, params, sw)
+    tuned = None
+    if args.autotune:
+        from paper_2204_12346_amd import autotune
+        tuned = autotune.autotune(b, sw.x, obs, kind, use_cache=False, verbose=True)
+        print(f"# autotuned launch: {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         S.sird_pso_iterate(b, params, sw, obs, kind, 1)
     torch.cuda.synchronize()
@@ -136,6 +183,11 @@ def main():
 
     steps_per_iter = b.particle_steps
     value = steps_per_iter * args.steps / (total_ms / 1e3)
+    alg_bytes = 8 * (b.theta_len + b.total_particles + b.obs_len)
+    meas = MEASURED_TRAFFIC.get(args.workload)
+    traffic = None
+    if meas and meas["sources"] == kernel_source_hash() and args.dtype == "f64":
+        traffic = meas["bytes"]
     achieved = FLOPS_PER_STEP * steps_per_iter / (fwd_ms / 1e3)
     out = {
         "metric": METRIC,
@@ -169,7 +221,9 @@ def main():
             "peak": PEAK_FP64_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VECTOR,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch",
+            "algorithmic_bytes": alg_bytes,
             "kernel_ms": fwd_ms,
             "flops_per_particle_step": FLOPS_PER_STEP,
             "valu_issue_frac": (VALU_PER_STEP * steps_per_iter / (fwd_ms / 1e3)) /
@@ -179,7 +233,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_particles)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -1,0 +1,110 @@
+"""Calibration drivers built on the C ABI: a whole swarm run (Sec. 3.3) with
+graph-captured iterations, gradient refinement of the swarm's best
+particles, and the forecast that extends a fitted window (Sec. 4.2).
+
+Every arithmetic step runs in the library's kernels; these functions only
+sequence the calls and read back small results (losses, indices).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from .core import (Batch, Graph, ProblemSpec, PsoParams, Swarm, pso_init, pso_topk,
+                   sird_adam_step, sird_gather, sird_integrate, sird_loss, sird_loss_backward,
+                   sird_loss_backward_workspace, sird_pso_iterate)
+
+
+def run_swarm(batch: Batch, params: PsoParams, obs, kind="ssre", iters=100, hist=True,
+              graph_chunk=0, swarm: Optional[Swarm] = None, init=True) -> Swarm:
+    """iters swarm iterations from pso_init.  graph_chunk > 0 replays a HIP
+    graph of graph_chunk iterations (the remainder runs eagerly)."""
+    sw = swarm if swarm is not None else Swarm(batch, hist_len=iters if hist else 0)
+    if init:
+        pso_init(batch, params, sw)
+    done = 0
+    if graph_chunk > 0 and iters >= graph_chunk:
+        g = Graph(batch, params, sw, obs, kind, iters_per_launch=graph_chunk)
+        n = iters // graph_chunk
+        g.launch(n)
+        done = n * graph_chunk
+        torch.cuda.current_stream().synchronize()
+        g.close()
+    if iters > done:
+        sird_pso_iterate(batch, params, sw, obs, kind, iters - done)
+    return sw
+
+
+@dataclasses.dataclass
+class Refined:
+    batch: Batch          # k particles per problem
+    theta: torch.Tensor   # theta-shaped, refined parameters
+    loss: torch.Tensor    # particle-indexed losses at theta
+    idx: torch.Tensor     # [n_prob, k] source particles (local indices)
+    steps: int
+
+
+def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre", k=32,
+                max_steps=2000, lr=1e-3, rel_tol=1e-12, check_every=25,
+                ckpt_interval=0) -> Refined:
+    """Projected Adam (Kingma & Ba 2015) from the k best personal bests of
+    every problem, in box-normalised coordinates, with gradients from the
+    discrete adjoint.  Stops after max_steps, or when no refined particle's
+    loss changed by more than rel_tol (relative) over check_every steps."""
+    idx = pso_topk(batch, swarm.pbest_f, k)
+    specs = [ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, k, s.stream)
+             for s in batch.specs]
+    rb = Batch(specs, dtype="f64", device=batch.device)
+    theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    grad = torch.empty_like(theta)
+    loss = rb.empty_particles()
+    ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
+                     device=batch.device)
+    prev = None
+    t = 0
+    for t in range(1, max_steps + 1):
+        sird_loss_backward(rb, theta, obs, kind, grad_theta=grad, loss_out=loss,
+                           ckpt_interval=ckpt_interval, workspace=ws)
+        sird_adam_step(rb, theta, grad, m, v, params.lo, params.hi, t, lr=lr)
+        if t % check_every == 0:
+            cur = loss.clone()
+            if prev is not None:
+                change = ((cur - prev).abs() <= rel_tol * cur.abs()) | ~torch.isfinite(cur)
+                if bool(change.all().item()):
+                    break
+            prev = cur
+    final = sird_loss(rb, theta, obs, kind)
+    return Refined(rb, theta, final, idx, t)
+
+
+def best_per_problem(batch: Batch, theta: torch.Tensor, loss: torch.Tensor):
+    """(theta_best (n_prob, d) list, loss_best array) of the lowest loss of
+    every problem (lowest index on ties, NaN never wins)."""
+    th = batch.unpack_theta(theta)
+    ls = batch.split_particles(loss)
+    outs, vals = [], []
+    for a, l in zip(th, ls):
+        l = np.where(np.isnan(l), np.inf, l)
+        i = int(np.argmin(l)) if len(l) else -1
+        outs.append(a[i] if i >= 0 else None)
+        vals.append(l[i] if i >= 0 else np.inf)
+    return outs, np.array(vals)
+
+
+def forecast(specs: Sequence[ProblemSpec], thetas: Sequence[np.ndarray], horizon_days: int,
+             device="cuda") -> List[np.ndarray]:
+    """Integrate every parameter vector over its window plus horizon_days
+    (the last beta segment continues past the window, as the paper extends
+    a window with its last transmission rate); returns per problem an array
+    (n, 4, W + horizon + 1) of S, I, R, D."""
+    ext = [ProblemSpec(s.W + horizon_days, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0,
+                       len(th), s.stream) for s, th in zip(specs, thetas)]
+    # segments are anchored at the window start; the last one extends
+    b = Batch(ext, with_traj=True, device=device)
+    traj = sird_integrate(b, b.pack_theta([np.asarray(t) for t in thetas]))
+    return b.unpack_traj(traj)

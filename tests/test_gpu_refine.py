@@ -1,0 +1,136 @@
+"""GPU checks of the refinement pieces: top-k selection, gather, projected
+Adam, the autograd Function, the refinement driver, the forecast, and the
+autotuner's bitwise invariance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2204_12346_amd as S
+from paper_2204_12346_amd import autotune, fit
+from paper_2204_12346_amd.autograd import SirdLoss
+from gpu_helpers import TOL64, assert_traj_close, make_batch, need_gpu, oracle_problem, random_theta
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def test_topk_order_ties_and_nan():
+    specs = [S.ProblemSpec(10, 2, 5, 2, 1e5, n_part=n) for n in (300, 5, 1000, 0)]
+    b = S.Batch(specs)
+    rng = np.random.default_rng(0)
+    fs = [np.round(rng.uniform(0, 5, s.n_part), 1) for s in specs]  # many exact ties
+    fs[0][[3, 7]] = np.nan
+    fs[2][[10, 20, 30]] = np.inf
+    f_all = torch.from_numpy(np.concatenate(fs)).cuda()
+    k = 8
+    idx = S.pso_topk(b, f_all, k).cpu().numpy()
+    for r, f in enumerate(fs):
+        key = np.where(np.isnan(f), np.inf, f)
+        order = np.lexsort((np.arange(len(f)), key))[:k]
+        exp = list(order) + [-1] * (k - len(order))
+        assert list(idx[r]) == exp, r
+
+
+def test_gather_and_adam_match_oracle():
+    wl = synth.c3(regions=[0, 1, 2])
+    n_parts = [100, 40, 64]
+    b = make_batch(wl.fits, n_parts)
+    ths = [random_theta(f, n, seed=r) for r, (f, n) in enumerate(zip(wl.fits, n_parts))]
+    src = b.pack_theta(ths)
+    lo = b.pack_box([f.lo for f in wl.fits])
+    hi = b.pack_box([f.hi for f in wl.fits])
+    k = 6
+    idx_np = np.array([[5, 0, 99, -1, 7, 3], [39, 1, 2, 3, 4, 5], [63, 62, 0, 1, -1, 9]])
+    idx = torch.from_numpy(idx_np).cuda()
+    rb = make_batch(wl.fits, [k] * 3)
+    dst = S.sird_gather(b, src, lo, rb, idx, k)
+    got = rb.unpack_theta(dst)
+    for r in range(3):
+        for q in range(k):
+            exp = ths[r][idx_np[r, q]] if idx_np[r, q] >= 0 else wl.fits[r].lo
+            assert np.array_equal(got[r][q], exp)
+    # Adam: several steps against the oracle
+    rng = np.random.default_rng(1)
+    m = torch.zeros_like(dst)
+    v = torch.zeros_like(dst)
+    th_o = [g.copy() for g in got]
+    m_o = [np.zeros_like(g) for g in got]
+    v_o = [np.zeros_like(g) for g in got]
+    for t in range(1, 6):
+        grads = [rng.normal(0, 1, g.shape) for g in got]
+        S.sird_adam_step(rb, dst, rb.pack_theta(grads), m, v, lo, hi, t, lr=1e-2)
+        for r, f in enumerate(wl.fits):
+            oracle.adam_step(th_o[r], grads[r], m_o[r], v_o[r], f.lo, f.hi, t, lr=1e-2)
+    back = rb.unpack_theta(dst)
+    for r in range(3):
+        np.testing.assert_allclose(back[r], th_o[r], rtol=1e-14, atol=1e-14)
+        assert np.all(back[r] >= wl.fits[r].lo) and np.all(back[r] <= wl.fits[r].hi)
+
+
+def test_autograd_function_matches_oracle_gradient():
+    f = synth.c2().fits[0]
+    P = 16
+    th = random_theta(f, P, seed=6)
+    th[:, :f.K] *= 0.5
+    b = make_batch([f], [P])
+    theta = b.pack_theta([th]).requires_grad_(True)
+    obs = b.pack_obs([f.y])
+    loss = SirdLoss.apply(theta, b, obs, "ssre", 0)
+    w = torch.linspace(0.5, 2.0, P, dtype=torch.float64, device=theta.device)
+    (loss[:P] * w).sum().backward()
+    g = b.unpack_theta(theta.grad)[0]
+    prob = oracle_problem(f)
+    for p in range(P):
+        gr = oracle.loss_grad_fwd(prob, th[p], f.y, "ssre")[1] * w[p].item()
+        np.testing.assert_allclose(g[p], gr, rtol=1e-6, atol=1e-9 * np.abs(gr).max())
+
+
+def test_refine_topk_lowers_the_loss_on_noise_free_data():
+    wl = synth.c1(n_part=128, iters=30)
+    f = wl.fits[0]
+    y = oracle.integrate(oracle_problem(f), f.truth)[3]
+    b = make_batch([f], [128])
+    params = S.PsoParams(b, [f.lo], [f.hi], wl.w, wl.c1, wl.c2, wl.seed)
+    obs = b.pack_obs([y])
+    sw = fit.run_swarm(b, params, obs, "ssre", iters=30, graph_chunk=10)
+    g0 = sw.gbest_f[0].item()
+    ref = fit.refine_topk(b, sw, params, obs, "ssre", k=8, max_steps=300, lr=1e-3)
+    th, L = fit.best_per_problem(ref.batch, ref.theta, ref.loss)
+    assert L[0] < g0
+    # the refined losses are the oracle's losses at the refined parameters
+    l_o = oracle.loss_batch(oracle_problem(f), ref.batch.unpack_theta(ref.theta)[0], y, "ssre")
+    np.testing.assert_allclose(ref.loss.cpu().numpy()[:8], l_o, rtol=1e-10, atol=1e-14)
+
+
+def test_forecast_extends_with_last_segment():
+    wl = synth.c5(restarts=1, windows=[3])
+    f = wl.fits[0]
+    spec = S.ProblemSpec.from_fit(f, 5)
+    th = random_theta(f, 5, seed=2)
+    out = fit.forecast([spec], [th], 14)[0]
+    assert out.shape == (5, 4, f.W + 15)
+    for p in range(5):
+        prob = oracle.Problem(f.W + 14, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0)
+        assert_traj_close(out[p], oracle.integrate(prob, th[p]), TOL64)
+
+
+def test_autotuner_candidates_agree_bitwise(tmp_path, monkeypatch):
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "cache.json"))
+    wl = synth.c3(regions=list(range(64)))
+    b = make_batch(wl.fits, [256] * 64)
+    ths = [random_theta(f, 256, seed=r) for r, f in enumerate(wl.fits)]
+    theta, obs = b.pack_theta(ths), b.pack_obs([f.y for f in wl.fits])
+    b.configure(block=256, persistent=0)
+    ref = S.sird_loss(b, theta, obs, "ssre").cpu().numpy()
+    best = autotune.autotune(b, theta, obs, "ssre", reps=2, verbose=True)
+    assert best in autotune.candidates(torch.cuda.get_device_properties(0).multi_processor_count)
+    assert np.array_equal(S.sird_loss(b, theta, obs, "ssre").cpu().numpy(), ref)
+    # a second call is served from the cache
+    again = autotune.autotune(b, theta, obs, "ssre")
+    assert again == best
