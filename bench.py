@@ -1,8 +1,10 @@
 """Throughput benchmark of the calibration hot path on one MI355X.
 
-One step = one swarm iteration over the whole batch: sird_loss (RK4 over
-every particle's window, fused with the cost) then pso_step (bests, argmin,
-Philox velocity/position update).  Default workload: 512 independent
+One step = one swarm iteration over the whole batch, as sird_pso_iterate
+runs it: pso_evaluate (the previous iteration's Philox velocity/position
+update, RK4 over every particle's window fused with the cost, personal
+bests -- one kernel) then pso_gbest (per-problem argmin, iteration
+advance).  Default workload: 512 independent
 synthetic regions of uneven window (28..365 days) and population, 1024
 particles each, 14-day beta segments, dt = 0.1 day, FP64.
 
@@ -28,14 +30,14 @@ sys.path.insert(0, ROOT)
 
 # Launch configuration of the integration kernel for the batched workload
 # (block size and persistent wavefronts); chosen by the autotuner.
-C3_LAUNCH = dict(block=256, persistent=0)
+C3_LAUNCH = dict(block=256, persistent=2048)
 
-# Algorithmic work of one particle-step of the FP64 forward: the RK4 step of
-# the (S, I, D) state issues 8 mul + 4 add + 15 fma = 27 VALU instructions =
-# 42 flops (an FMA counts 2).  The per-day cost adds < 0.4 flop per step and
-# is not counted.
-FLOPS_PER_STEP = 42
-VALU_PER_STEP = 27
+# Algorithmic work of one particle-step of the FP64 forward: the RK4 step
+# (stages on the scaled susceptible b S) issues 4 mul + 4 add + 16 fma = 24
+# VALU instructions = 40 flops (an FMA counts 2).  The per-day cost and
+# rescale and the swarm update fused into the same kernel are not counted.
+FLOPS_PER_STEP = 40
+VALU_PER_STEP = 24
 PEAK_FP64_VECTOR = 78.6e12  # MI355X, FLOP/s
 
 # HBM bytes per k_forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
@@ -158,8 +160,7 @@ def main():
         from paper_2204_12346_amd import autotune
         tuned = autotune.autotune(b, sw.x, obs, kind, use_cache=False, verbose=True)
         print(f"# autotuned launch: {tuned}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        S.sird_pso_iterate(b, params, sw, obs, kind, 1)
+    S.sird_pso_iterate(b, params, sw, obs, kind, args.warmup)
     torch.cuda.synchronize()
     print(f"# warmup done: {args.warmup} steps", file=sys.stderr, flush=True)
 
@@ -172,9 +173,10 @@ def main():
     start.record(stream)
     for i in range(args.steps):
         ev[i][0].record(stream)
-        S.sird_loss(b, sw.x, obs, kind, sw.f)
+        S.pso_evaluate(b, params, sw, obs, kind, move_first=(i > 0))
         ev[i][1].record(stream)
-        S.pso_step(b, params, sw)
+        S.pso_gbest(b, params, sw)
+    S.pso_complete_move(b, params, sw)
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -215,7 +217,7 @@ def main():
             "launch": {"block": b.c.block, "persistent": b.c.persistent},
         },
         "roofline": {
-            "kernel": "k_forward (sird_loss)",
+            "kernel": "k_forward fused (pso_evaluate: move + RK4 + cost + pbest)",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP64_VECTOR / 1e12,

@@ -64,8 +64,9 @@ extern "C" {
 
 /* ------------------------------------------------------ ODE state precision */
 #define SIRD_F64 0 /* state and arithmetic in double */
-#define SIRD_F32 1 /* state (C = N - S, I, D) and arithmetic in float;
-                      theta, losses and the swarm stay double */
+#define SIRD_F32 1 /* state (S, I, R, D) and arithmetic in float, state
+                      updates Kahan-compensated; theta, losses and the
+                      swarm stay double */
 
 /* ------------------------------------------------ costs of Sec. 3.1 on D */
 /* e_i = y_i - Dhat_i over days i = 0..W, n = W + 1, g_i = max(y_i, 1) */
@@ -244,8 +245,32 @@ int pso_init(const sird_batch *batch, const pso_params *params, const pso_state 
 int pso_step(const sird_batch *batch, const pso_params *params, const pso_state *state,
              void *stream);
 
+/* The two halves of a swarm iteration with the swarm update fused into the
+ * integration (Sec. 3.3).  pso_evaluate: if move_first, first complete the
+ * previous iteration's velocity/position update (counter iter[0] - 1,
+ * operations as in pso_step step 3); then integrate every particle and
+ * write state->f = loss(state->x) as sird_loss does; then update the
+ * personal bests as in pso_step step 1.  pso_gbest: pso_step step 2 for
+ * iteration it = iter[0] (global best, history row it), then iter[0] = it+1.
+ * The sequence
+ *     pso_evaluate(0); pso_gbest; { pso_evaluate(1); pso_gbest; } x (n-1);
+ *     pso_complete_move
+ * is bitwise n x [sird_loss; pso_step].
+ * Errors: SIRD_EINVAL (null pointer, bad kind or batch), SIRD_EHIP. */
+int pso_evaluate(const sird_batch *batch, const pso_params *params, const pso_state *state,
+                 const double *obs, int loss_kind, int move_first, void *stream);
+int pso_gbest(const sird_batch *batch, const pso_params *params, const pso_state *state,
+              void *stream);
+
+/* The velocity/position update of the last finished iteration (counter
+ * iter[0] - 1), without advancing iter: ends a pso_evaluate/pso_gbest
+ * sequence so that the swarm state equals the one pso_step leaves. */
+int pso_complete_move(const sird_batch *batch, const pso_params *params,
+                      const pso_state *state, void *stream);
+
 /* n_iters iterations of [sird_loss(state->x) -> state->f; pso_step], the
- * whole hot path of one calibration iteration, enqueued eagerly. */
+ * whole hot path of one calibration iteration, enqueued as the fused
+ * pso_evaluate / pso_gbest sequence above (same result bitwise). */
 int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
                      const pso_state *state, const double *obs, int loss_kind,
                      int n_iters, void *stream);

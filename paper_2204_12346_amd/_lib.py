@@ -93,6 +93,9 @@ SIGNATURES = {
     "pso_init": (_I, [_B, _PP, _PS, _P]),
     "pso_step": (_I, [_B, _PP, _PS, _P]),
     "sird_pso_iterate": (_I, [_B, _PP, _PS, _P, _I, _I, _P]),
+    "pso_evaluate": (_I, [_B, _PP, _PS, _P, _I, _I, _P]),
+    "pso_gbest": (_I, [_B, _PP, _PS, _P]),
+    "pso_complete_move": (_I, [_B, _PP, _PS, _P]),
     "sird_loss_backward": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _P, ctypes.c_size_t, _P]),
     "sird_loss_backward_workspace": (ctypes.c_size_t, [_B, _I]),
     "pso_topk": (_I, [_B, _P, _I, _P, _P]),

@@ -37,8 +37,9 @@ def candidates(n_cu: int) -> List[Dict[str, int]]:
     out = []
     for block in (64, 128, 256, 512):
         out.append(dict(block=block, persistent=0))
-    for wpc in (8, 12, 16, 20, 24):
+    for wpc in (4, 6, 8, 10, 12, 16):  # resident wavefronts per CU
         out.append(dict(block=64, persistent=n_cu * wpc))
+    out.append(dict(block=256, persistent=n_cu * 8))
     return out
 
 

@@ -255,6 +255,24 @@ def sird_pso_iterate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="s
                                  stream_handle(stream)), "sird_pso_iterate")
 
 
+def pso_evaluate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre",
+                 move_first=False, stream=None):
+    check(lib().pso_evaluate(ctypes.byref(batch.c), ctypes.byref(params.c),
+                             ctypes.byref(swarm.c), ptr(obs), _kind(kind), int(bool(move_first)),
+                             stream_handle(stream)), "pso_evaluate")
+
+
+def pso_gbest(batch: Batch, params: PsoParams, swarm: Swarm, stream=None):
+    check(lib().pso_gbest(ctypes.byref(batch.c), ctypes.byref(params.c), ctypes.byref(swarm.c),
+                          stream_handle(stream)), "pso_gbest")
+
+
+def pso_complete_move(batch: Batch, params: PsoParams, swarm: Swarm, stream=None):
+    check(lib().pso_complete_move(ctypes.byref(batch.c), ctypes.byref(params.c),
+                                  ctypes.byref(swarm.c), stream_handle(stream)),
+          "pso_complete_move")
+
+
 def sird_loss_backward_workspace(batch: Batch, ckpt_interval=0):
     return int(lib().sird_loss_backward_workspace(ctypes.byref(batch.c), int(ckpt_interval)))
 

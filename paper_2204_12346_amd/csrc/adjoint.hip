@@ -3,7 +3,8 @@
 //
 // Per particle (one lane, one tile per wavefront):
 //   1. forward pass: RK4 over the window, the cost, Dhat_i of every day and
-//      the state (S, I) every s steps (checkpoints) -> workspace;
+//      the state (S, I, and the stages' scaled susceptible) every s steps
+//      (checkpoints) -> workspace;
 //   2. reverse sweep over the checkpoint intervals, last to first: recompute
 //      the interval's step-start states from its checkpoint into the
 //      workspace, then walk the steps backwards.  For step n with stages
@@ -68,29 +69,6 @@ __device__ __forceinline__ double cost_grad(int kind, int i, int W, double D, do
     case SIRD_LOSS_MAPE: return -100.0 * sg * w / n;
     default: return 0.0;
     }
-}
-
-// RK4 step of (S, I) only (R and D do not feed back); the same operations
-// as rk4_step in double.
-__device__ __forceinline__ void rk4_step_si(double &S, double &I, const StepConst<double> &k)
-{
-    const double p1 = (k.b * S) * I;
-    const double q1 = fma(-k.lam, I, p1);
-    const double S2 = fma(-k.h2, p1, S);
-    const double I2 = fma(k.h2, q1, I);
-    const double p2 = (k.b * S2) * I2;
-    const double q2 = fma(-k.lam, I2, p2);
-    const double S3 = fma(-k.h2, p2, S);
-    const double I3 = fma(k.h2, q2, I);
-    const double p3 = (k.b * S3) * I3;
-    const double q3 = fma(-k.lam, I3, p3);
-    const double S4 = fma(-k.h, p3, S);
-    const double I4 = fma(k.h, q3, I);
-    const double p4 = (k.b * S4) * I4;
-    const double Pp = fma(2.0, p2 + p3, p1 + p4);
-    const double J = fma(2.0, I2 + I3, I + I4);
-    S = fma(-k.h6, Pp, S);
-    I = fma(k.h6, Pp, fma(-k.h6lam, J, I));
 }
 
 struct Grad {
@@ -192,8 +170,8 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     const double *th = a.theta + P.theta_off + pc;
     const size_t PS = (size_t)a.P;
     double *wsp = a.ws + (size_t)(P.p_off + pc);
-    const int ck_base = 0;
-    const int sc_base = 2 * a.n_ck_max;
+    const int ck_base = 0;  // checkpoint m: slots 3m (S), 3m+1 (I), 3m+2 (s)
+    const int sc_base = 3 * a.n_ck_max;
     const int day_base = sc_base + 2 * a.s;
 
     {
@@ -220,15 +198,18 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     y.I = I0;
     y.Rr = P.R0;
     y.D = P.D0;
+    y.s = 0.0;
     y.eS = y.eI = y.eR = y.eD = 0.0;
     double acc = 0.0;
     int imax = 0;
     cost_accum(a.kind, acc, y.D, ly[0], lw[0], 0);
     if (active) wsp[(size_t)day_base * PS] = y.D;
     {
+        // the same sequence of operations as the forward kernel: set_beta at
+        // a segment start, rescale at a day start, then the step
         int k = 0;
         long next_seg = (K > 1) ? (long)SS : T + 1;
-        sc.b = th[0] / N;
+        set_beta(sc, th[0], N);
         long next_ck = 0;
         int m = 0;
         int sd = 0, day = 0;
@@ -236,12 +217,14 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             if (st == next_seg) {
                 ++k;
                 next_seg = (k < K - 1) ? next_seg + SS : T + 1;
-                sc.b = th[(size_t)k * ld] / N;
+                set_beta(sc, th[(size_t)k * ld], N);
             }
+            if (sd == 0) rescale(y, sc);
             if (st == next_ck) {
                 if (active) {
-                    wsp[(size_t)(ck_base + 2 * m) * PS] = y.S;
-                    wsp[(size_t)(ck_base + 2 * m + 1) * PS] = y.I;
+                    wsp[(size_t)(ck_base + 3 * m) * PS] = y.S;
+                    wsp[(size_t)(ck_base + 3 * m + 1) * PS] = y.I;
+                    wsp[(size_t)(ck_base + 3 * m + 2) * PS] = y.s;
                 }
                 ++m;
                 next_ck += a.s;
@@ -272,32 +255,40 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     double aD = cost_grad(a.kind, W, W, DW, ly[W], lw[W], imax);
     Grad g{0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
-    sc.b = th[(size_t)kr * ld] / N;
+    set_beta(sc, th[(size_t)kr * ld], N);
     long seg_lo = (long)kr * SS;  // first step of segment kr
 
     const int n_ck = (int)((T + a.s - 1) / a.s);
     for (int m = n_ck - 1; m >= 0; --m) {
         const long n0 = (long)m * a.s;
         const long n1 = (n0 + a.s < T) ? n0 + a.s : T;
-        // recompute the interval's step-start states
-        double Sr = active ? wsp[(size_t)(ck_base + 2 * m) * PS] : 0.0;
-        double Ir = active ? wsp[(size_t)(ck_base + 2 * m + 1) * PS] : 0.0;
+        // recompute the interval's step-start states with exactly the
+        // forward pass's operations, from the stored (S, I, s)
         {
+            SirdState<double> yr;
+            yr.S = active ? wsp[(size_t)(ck_base + 3 * m) * PS] : 0.0;
+            yr.I = active ? wsp[(size_t)(ck_base + 3 * m + 1) * PS] : 0.0;
+            yr.s = active ? wsp[(size_t)(ck_base + 3 * m + 2) * PS] : 0.0;
+            yr.Rr = yr.D = 0.0;
+            yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
             int kf = seg_of(n0, SS, K);
             StepConst<double> sf = sc;
-            sf.b = th[(size_t)kf * ld] / N;
+            set_beta(sf, th[(size_t)kf * ld], N);
             long next_seg = (kf < K - 1) ? (long)(kf + 1) * SS : T + 1;
+            int sd = (int)(n0 % spd);
             for (long st = n0; st < n1; ++st) {
                 if (st == next_seg) {
                     ++kf;
                     next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
-                    sf.b = th[(size_t)kf * ld] / N;
+                    set_beta(sf, th[(size_t)kf * ld], N);
                 }
+                if (sd == 0) rescale(yr, sf);
                 if (active) {
-                    wsp[(size_t)(sc_base + 2 * (st - n0)) * PS] = Sr;
-                    wsp[(size_t)(sc_base + 2 * (st - n0) + 1) * PS] = Ir;
+                    wsp[(size_t)(sc_base + 2 * (st - n0)) * PS] = yr.S;
+                    wsp[(size_t)(sc_base + 2 * (st - n0) + 1) * PS] = yr.I;
                 }
-                rk4_step_si(Sr, Ir, sf);
+                rk4_step<double, false>(yr, sf);
+                if (++sd == spd) sd = 0;
             }
         }
         // walk the interval backwards; the state of step st-1 is loaded
@@ -310,7 +301,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                 g.beta = 0.0;
                 --kr;
                 seg_lo = (long)kr * SS;
-                sc.b = th[(size_t)kr * ld] / N;
+                set_beta(sc, th[(size_t)kr * ld], N);
             }
             double Sn = 0.0, In = 0.0;
             if (active && st > n0) {
@@ -342,10 +333,12 @@ static int resolve_interval(const sird_batch *b, int ckpt_interval)
     return s < 1 ? 1 : s;
 }
 
+// Workspace slots per particle: 3 per checkpoint (S, I, s), 2 per step of
+// one recomputed interval (S, I), and Dhat of every day.
 static size_t ws_slots(const sird_batch *b, int s)
 {
     const int64_t n_ck = (b->max_steps + s - 1) / s;
-    return (size_t)(2 * n_ck + 2 * (int64_t)s + b->max_days + 1);
+    return (size_t)(3 * n_ck + 2 * (int64_t)s + b->max_days + 1);
 }
 
 }  // namespace sird

@@ -24,8 +24,12 @@ constexpr int kWave = 64;
 // Only S and I feed back, so the update needs two sums,
 //     P = p1 + 2p2 + 2p3 + p4,   J = I1 + 2I2 + 2I3 + I4,
 // with S+ = S - h/6 P, I+ = I + h/6 (P - lam J), R+ = R + h/6 gamma J,
-// D+ = D + h/6 mu J.  In double: 27 VALU operations per step without R
-// (4 mul, 4 add, 19 fma), 28 with R.
+// D+ = D + h/6 mu J.
+// The stages use the scaled susceptible s = b S, so p_s = s_s I_s costs one
+// multiply; s is carried next to S (s+ = s - b h/6 P) and reset to b S at
+// the start of every day, which bounds its drift from b S to one day of
+// rounding.  In double: 24 VALU operations per step without R (4 mul,
+// 4 add, 16 fma), 25 with R.
 template <typename R>
 struct StepConst {
     R b;      // beta / N of the current segment
@@ -36,9 +40,12 @@ struct StepConst {
     R h6lam;  // h/6 * lam
     R h6mu;   // h/6 * mu
     R h6g;    // h/6 * gamma
+    R hb;     // b h
+    R h2b;    // b h / 2
+    R h6b;    // b h / 6
 };
 
-// The state of one particle.  In float, each component carries the running
+// The state of one particle.  In float, S, I, R and D carry the running
 // compensation of Kahan's summation (W. Kahan, "Further remarks on reducing
 // truncation errors", CACM 1965): a step's increments are small next to the
 // state (S is close to N early in an epidemic), and without compensation
@@ -47,6 +54,7 @@ struct StepConst {
 template <typename R>
 struct SirdState {
     R S, I, Rr, D;
+    R s;  // b S, the stages' scaled susceptible
     R eS, eI, eR, eD;
 };
 
@@ -66,31 +74,50 @@ __device__ __forceinline__ double state_value(R s, R e)
     return (double)s - (double)e;
 }
 
+// New segment: b = beta/N and the step constants that depend on it.
+template <typename R>
+__device__ __forceinline__ void set_beta(StepConst<R> &k, double beta, double N)
+{
+    const double b = beta / N;
+    k.b = (R)b;
+    k.hb = (R)((double)k.h * b);
+    k.h2b = (R)((double)k.h2 * b);
+    k.h6b = (R)((double)k.h6 * b);
+}
+
+// Start of a day (and of a segment): s = b S.
+template <typename R>
+__device__ __forceinline__ void rescale(SirdState<R> &y, const StepConst<R> &k)
+{
+    y.s = k.b * y.S;
+}
+
 template <typename R, bool WITH_R>
 __device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
 {
-    const R S = y.S, I = y.I;
-    const R p1 = (k.b * S) * I;
+    const R s = y.s, I = y.I;
+    const R p1 = s * I;
     const R q1 = fma(-k.lam, I, p1);
-    const R S2 = fma(-k.h2, p1, S);
+    const R s2 = fma(-k.h2b, p1, s);
     const R I2 = fma(k.h2, q1, I);
 
-    const R p2 = (k.b * S2) * I2;
+    const R p2 = s2 * I2;
     const R q2 = fma(-k.lam, I2, p2);
-    const R S3 = fma(-k.h2, p2, S);
+    const R s3 = fma(-k.h2b, p2, s);
     const R I3 = fma(k.h2, q2, I);
 
-    const R p3 = (k.b * S3) * I3;
+    const R p3 = s3 * I3;
     const R q3 = fma(-k.lam, I3, p3);
-    const R S4 = fma(-k.h, p3, S);
+    const R s4 = fma(-k.hb, p3, s);
     const R I4 = fma(k.h, q3, I);
 
-    const R p4 = (k.b * S4) * I4;
+    const R p4 = s4 * I4;
 
     const R P = fma(R(2), p2 + p3, p1 + p4);
     const R J = fma(R(2), I2 + I3, I + I4);
+    y.s = fma(-k.h6b, P, s);
     if constexpr (sizeof(R) == 8) {
-        y.S = fma(-k.h6, P, S);
+        y.S = fma(-k.h6, P, y.S);
         y.I = fma(k.h6, P, fma(-k.h6lam, J, I));
         if (WITH_R) y.Rr = fma(k.h6g, J, y.Rr);
         y.D = fma(k.h6mu, J, y.D);
@@ -108,7 +135,6 @@ __device__ __forceinline__ StepConst<R> step_const(double gamma, double mu, int 
     const double h = 1.0 / (double)spd;
     const double h6 = h / 6.0;
     StepConst<R> k;
-    k.b = R(0);
     k.lam = (R)(gamma + mu);
     k.h = (R)h;
     k.h2 = (R)(0.5 * h);
@@ -116,6 +142,7 @@ __device__ __forceinline__ StepConst<R> step_const(double gamma, double mu, int 
     k.h6lam = (R)(h6 * (gamma + mu));
     k.h6mu = (R)(h6 * mu);
     k.h6g = (R)(h6 * gamma);
+    k.b = k.hb = k.h2b = k.h6b = R(0);
     return k;
 }
 
@@ -199,6 +226,44 @@ __device__ __forceinline__ double u01(uint64_t x)
     return (double)(x >> 11) * 0x1.0p-53;
 }
 
+// ------------------------------------------------------- swarm, Sec. 3.3
+// Everything the velocity/position update of one particle needs.
+struct PsoMove {
+    double w, c1, c2;
+    uint64_t seed;
+    const double *lo;       // box-shaped
+    const double *hi;       // box-shaped
+    double *x;              // theta-shaped
+    double *v;              // theta-shaped
+    const double *pbest_x;  // theta-shaped
+    const double *gbest_x;  // box-shaped
+};
+
+// Velocity and position update of local particle pl of problem P at swarm
+// iteration it: r1, r2 from Philox counter (it, pl, j/2, 1), words 2(j%2)
+// and 2(j%2)+1; every operation a single rounded multiply or add (the
+// library is built without contraction):
+//   t = w v; t = t + (c1 r1)(pb - x); t = t + (c2 r2)(g - x);
+//   v = t;   x = min(max(x + v, lo), hi).
+__device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_problem &P,
+                                                  int pl, uint64_t it);
+
+// Personal best of local particle pl given its loss f (NaN counts as +inf):
+// strict improvement replaces pbest_f and copies x into pbest_x.
+__device__ __forceinline__ void pso_pbest_particle(double f, const sird_problem &P, int pl,
+                                                   double *pbest_f, double *pbest_x,
+                                                   const double *x)
+{
+    if (f != f) f = INFINITY;
+    if (f < pbest_f[P.p_off + pl]) {
+        pbest_f[P.p_off + pl] = f;
+        const int d = P.n_seg + 3;
+        const size_t n = (size_t)P.n_part;
+        const size_t base = (size_t)P.theta_off + pl;
+        for (int j = 0; j < d; ++j) pbest_x[base + (size_t)j * n] = x[base + (size_t)j * n];
+    }
+}
+
 // ---------------------------------------------------------- wave helpers
 __device__ __forceinline__ void wave_sync()
 {
@@ -211,6 +276,42 @@ template <typename T>
 __device__ __forceinline__ T wave_uniform(T v)
 {
     return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_problem &P,
+                                                  int pl, uint64_t it)
+{
+    const int d = P.n_seg + 3;
+    const size_t n = (size_t)P.n_part;
+    const double *lo = m.lo + P.box_off;
+    const double *hi = m.hi + P.box_off;
+    const double *g = m.gbest_x + P.box_off;
+    const size_t base = (size_t)P.theta_off + pl;
+    for (int q = 0; 2 * q < d; ++q) {
+        const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
+        for (int jj = 0; jj < 2; ++jj) {
+            const int j = 2 * q + jj;
+            if (j >= d) break;
+            const double r1 = u01(r.w[2 * jj]);
+            const double r2 = u01(r.w[2 * jj + 1]);
+            const size_t o = base + (size_t)j * n;
+            const double xo = m.x[o];
+            double tv = m.w * m.v[o];
+            const double a1 = m.c1 * r1;
+            const double d1 = m.pbest_x[o] - xo;
+            const double a2 = m.c2 * r2;
+            const double d2 = g[j] - xo;
+            const double m1 = a1 * d1;
+            tv = tv + m1;
+            const double m2 = a2 * d2;
+            tv = tv + m2;
+            m.v[o] = tv;
+            double xn = xo + tv;
+            if (xn < lo[j]) xn = lo[j];
+            if (xn > hi[j]) xn = hi[j];
+            m.x[o] = xn;
+        }
+    }
 }
 
 // Index of this wavefront's tile in a launch of one wavefront per tile,

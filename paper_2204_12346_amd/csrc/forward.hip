@@ -30,6 +30,14 @@ struct FwdArgs {
     int n_waves;   // resident wavefronts of a persistent launch, else 0
     int loss_kind;
     int lds_stride;  // doubles per wavefront slice: 2 * (max_days + 1)
+    // swarm fused into the integration (sird_pso_iterate): theta is the
+    // swarm's x, loss its f; before integrating, a particle is moved with
+    // counter iter[0] - 1 when do_move; after, its personal best is updated
+    PsoMove mv;
+    double *pbest_f;
+    double *pbest_x;
+    const uint64_t *iter;
+    int do_move;
 };
 
 // S, I, R, D of one day into a [4][W+1][n] trajectory block.
@@ -42,7 +50,7 @@ __device__ __forceinline__ void store_day(double *o, size_t comp_stride, const S
     o[3 * comp_stride] = state_value(y.D, y.eD);
 }
 
-template <typename R, bool TRAJ>
+template <typename R, bool TRAJ, bool FUSED>
 __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, double *ly,
                                          double *lw)
 {
@@ -65,6 +73,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         }
         wave_sync();
     }
+    if (FUSED && a.do_move && active) pso_move_particle(a.mv, P, pl, a.iter[0] - 1);
 
     const double gamma = th[(size_t)K * ld];
     const double mu = th[(size_t)(K + 1) * ld];
@@ -77,6 +86,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     y.I = (R)I0;
     y.Rr = (R)P.R0;
     y.D = (R)P.D0;
+    y.s = R(0);
     y.eS = y.eI = y.eR = y.eD = R(0);
 
     double acc = 0.0;
@@ -96,8 +106,9 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         if (k + 1 < K) beta_next = th[(size_t)(k + 1) * ld];  // prefetch
         const int dend = (k == K - 1) ? W : min(W, (k + 1) * seg);
         if (day >= dend) continue;
-        sc.b = (R)(beta_k / N);
+        set_beta(sc, beta_k, N);
         for (; day < dend; ++day) {
+            rescale(y, sc);
 #pragma unroll 2
             for (int s = 0; s < spd; ++s) rk4_step<R, TRAJ>(y, sc);
             const int i = day + 1;
@@ -108,11 +119,15 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             }
         }
     }
-    if (!TRAJ && active) a.loss[P.p_off + pl] = cost_finish(a.loss_kind, acc, W);
+    if (!TRAJ && active) {
+        const double L = cost_finish(a.loss_kind, acc, W);
+        a.loss[P.p_off + pl] = L;
+        if (FUSED) pso_pbest_particle(L, P, pl, a.pbest_f, a.pbest_x, a.mv.x);
+    }
     if (!TRAJ) wave_sync();  // LDS slice reads done before it is restaged
 }
 
-template <typename R, bool TRAJ>
+template <typename R, bool TRAJ, bool FUSED>
 __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
 {
     extern __shared__ double lds[];
@@ -126,7 +141,7 @@ __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
             if (lane == 0) t = atomicAdd(&a.sched[0], 1);
             t = wave_uniform(t);
             if (t >= a.n_tiles) break;
-            fwd_tile<R, TRAJ>(a, t, lane, ly, lw);
+            fwd_tile<R, TRAJ, FUSED>(a, t, lane, ly, lw);
         }
         // The last wavefront out resets the counters for the next launch.
         if (lane == 0) {
@@ -139,11 +154,11 @@ __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
         }
     } else {
         const int t = wave_tile_index();
-        if (t < a.n_tiles) fwd_tile<R, TRAJ>(a, t, lane, ly, lw);
+        if (t < a.n_tiles) fwd_tile<R, TRAJ, FUSED>(a, t, lane, ly, lw);
     }
 }
 
-template <typename R, bool TRAJ>
+template <typename R, bool TRAJ, bool FUSED = false>
 static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const char *who)
 {
     const int block = integ_block(b);
@@ -162,7 +177,7 @@ static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const c
         a.n_waves = 0;
     }
     if (grid == 0) return SIRD_OK;
-    hipLaunchKernelGGL((k_forward<R, TRAJ>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED>), dim3(grid), dim3(block), lds, s, a);
     return hip_status(hipGetLastError(), who);
 }
 
@@ -180,6 +195,27 @@ int forward_loss(const sird_batch *b, const double *theta, const double *obs, in
     a.loss_kind = kind;
     if (b->dtype == SIRD_F32) return launch_forward<float, false>(b, a, s, "sird_loss");
     return launch_forward<double, false>(b, a, s, "sird_loss");
+}
+
+int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
+                    const double *obs, int kind, bool move, hipStream_t s)
+{
+    FwdArgs a{};
+    a.probs = b->probs;
+    a.tiles = b->tiles;
+    a.sched = b->sched;
+    a.theta = st->x;
+    a.obs = obs;
+    a.loss = st->f;
+    a.n_tiles = b->n_tiles;
+    a.loss_kind = kind;
+    a.mv = mv;
+    a.pbest_f = st->pbest_f;
+    a.pbest_x = st->pbest_x;
+    a.iter = st->iter;
+    a.do_move = move ? 1 : 0;
+    if (b->dtype == SIRD_F32) return launch_forward<float, false, true>(b, a, s, "sird_pso_iterate");
+    return launch_forward<double, false, true>(b, a, s, "sird_pso_iterate");
 }
 
 }  // namespace sird

@@ -27,7 +27,26 @@ struct PsoArgs {
     const double *lo;
     const double *hi;
     pso_state st;
+    int it_back;       // the move uses counter iter[0] - it_back
+    int move_advance;  // the move kernel advances iter[0] (else it does not)
+    int gbest_advance; // the global-best kernel advances iter[0]
 };
+
+__host__ __device__ static PsoMove move_of(const PsoArgs &a)
+{
+    PsoMove m;
+    m.w = a.w;
+    m.c1 = a.c1;
+    m.c2 = a.c2;
+    m.seed = a.seed;
+    m.lo = a.lo;
+    m.hi = a.hi;
+    m.x = a.st.x;
+    m.v = a.st.v;
+    m.pbest_x = a.st.pbest_x;
+    m.gbest_x = a.st.gbest_x;
+    return m;
+}
 
 static PsoArgs make_args(const sird_batch *b, const pso_params *p, const pso_state *st)
 {
@@ -43,6 +62,9 @@ static PsoArgs make_args(const sird_batch *b, const pso_params *p, const pso_sta
     a.lo = p->lo;
     a.hi = p->hi;
     a.st = *st;
+    a.it_back = 0;
+    a.move_advance = 1;
+    a.gbest_advance = 0;
     return a;
 }
 
@@ -99,17 +121,9 @@ __global__ void __launch_bounds__(256) k_pso_pbest(PsoArgs a)
     if (t >= a.n_tiles) return;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
-    const int n = P.n_part;
     const int pl = tl.p0 + lane;
-    if (pl >= n) return;
-    double f = a.st.f[P.p_off + pl];
-    if (f != f) f = INFINITY;
-    if (f < a.st.pbest_f[P.p_off + pl]) {
-        a.st.pbest_f[P.p_off + pl] = f;
-        const int d = P.n_seg + 3;
-        const size_t base = (size_t)P.theta_off + pl;
-        for (int j = 0; j < d; ++j) a.st.pbest_x[base + (size_t)j * n] = a.st.x[base + (size_t)j * n];
-    }
+    if (pl >= P.n_part) return;
+    pso_pbest_particle(a.st.f[P.p_off + pl], P, pl, a.st.pbest_f, a.st.pbest_x, a.st.x);
 }
 
 // (f, index) lexicographic order: lowest index wins ties.
@@ -178,53 +192,33 @@ __global__ void __launch_bounds__(256) k_pso_gbest(PsoArgs a)
         for (int j = tid; j < d; j += blockDim.x)
             a.st.gbest_x[P.box_off + j] = a.st.pbest_x[(size_t)P.theta_off + (size_t)j * n + b];
     }
+    if (a.gbest_advance && tid == 0) {
+        // the last block out advances the iteration (all blocks read it)
+        __threadfence();
+        const unsigned long long done =
+            atomicAdd((unsigned long long *)&a.st.iter[1], 1ull);
+        if (done == (unsigned long long)gridDim.x - 1) {
+            atomicExch((unsigned long long *)&a.st.iter[1], 0ull);
+            atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it + 1));
+        }
+    }
 }
 
-// Velocity and position update, then the last block advances the iteration.
+// Velocity and position update with counter iter[0] - it_back; then, if
+// move_advance, the last block advances the iteration.
 __global__ void __launch_bounds__(256) k_pso_move(PsoArgs a)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int t = wave_tile_index();
-    const uint64_t it = a.st.iter[0];
+    const uint64_t it0 = a.st.iter[0];
+    const uint64_t it = it0 - (uint64_t)a.it_back;
     if (t < a.n_tiles) {
         const sird_tile tl = a.tiles[t];
         const sird_problem P = a.probs[tl.prob];
-        const int n = P.n_part;
         const int pl = tl.p0 + lane;
-        if (pl < n) {
-            const int d = P.n_seg + 3;
-            const double *lo = a.lo + P.box_off;
-            const double *hi = a.hi + P.box_off;
-            const double *g = a.st.gbest_x + P.box_off;
-            const size_t base = (size_t)P.theta_off + pl;
-            for (int m = 0; 2 * m < d; ++m) {
-                const Philox4x64 r =
-                    philox4x64_10(it, (uint64_t)pl, (uint64_t)m, 1, a.seed, P.stream);
-                for (int jj = 0; jj < 2; ++jj) {
-                    const int j = 2 * m + jj;
-                    if (j >= d) break;
-                    const double r1 = u01(r.w[2 * jj]);
-                    const double r2 = u01(r.w[2 * jj + 1]);
-                    const size_t o = base + (size_t)j * n;
-                    const double xo = a.st.x[o];
-                    double tv = a.w * a.st.v[o];
-                    const double a1 = a.c1 * r1;
-                    const double d1 = a.st.pbest_x[o] - xo;
-                    const double a2 = a.c2 * r2;
-                    const double d2 = g[j] - xo;
-                    const double m1 = a1 * d1;
-                    tv = tv + m1;
-                    const double m2 = a2 * d2;
-                    tv = tv + m2;
-                    a.st.v[o] = tv;
-                    double xn = xo + tv;
-                    if (xn < lo[j]) xn = lo[j];
-                    if (xn > hi[j]) xn = hi[j];
-                    a.st.x[o] = xn;
-                }
-            }
-        }
+        if (pl < P.n_part) pso_move_particle(move_of(a), P, pl, it);
     }
+    if (!a.move_advance) return;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -232,7 +226,7 @@ __global__ void __launch_bounds__(256) k_pso_move(PsoArgs a)
             atomicAdd((unsigned long long *)&a.st.iter[1], 1ull);
         if (done == (unsigned long long)gridDim.x - 1) {
             atomicExch((unsigned long long *)&a.st.iter[1], 0ull);
-            atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it + 1));
+            atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it0 + 1));
         }
     }
 }
@@ -268,19 +262,53 @@ int pso_step_enqueue(const sird_batch *b, const pso_params *p, const pso_state *
     return hip_status(hipGetLastError(), "pso_step");
 }
 
-int forward_loss(const sird_batch *b, const double *theta, const double *obs, int kind,
-                 double *loss, hipStream_t s);
+int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
+                    const double *obs, int kind, bool move, hipStream_t s);
+
+// n_iters iterations with the swarm fused into the integration kernel:
+// iteration i integrates x (first moving it with the previous iteration's
+// counter when i > 0) and updates the personal bests in the same kernel,
+// then the global-best kernel advances the iteration; a final move kernel
+// completes the last iteration without advancing the counter.  The result
+// is bitwise that of n_iters x [sird_loss; pso_step].
+static int evaluate_enqueue(const sird_batch *b, const pso_params *p, const pso_state *st,
+                            const double *obs, int kind, bool move_first, hipStream_t s)
+{
+    PsoArgs a = make_args(b, p, st);
+    return forward_iterate(b, move_of(a), st, obs, kind, move_first, s);
+}
+
+static int gbest_enqueue(const sird_batch *b, const pso_params *p, const pso_state *st,
+                         hipStream_t s)
+{
+    PsoArgs a = make_args(b, p, st);
+    a.gbest_advance = 1;
+    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(256), 0, s, a);
+    return hip_status(hipGetLastError(), "pso_gbest");
+}
+
+static int complete_move_enqueue(const sird_batch *b, const pso_params *p,
+                                 const pso_state *st, hipStream_t s)
+{
+    PsoArgs a = make_args(b, p, st);
+    a.it_back = 1;
+    a.move_advance = 0;
+    const int tb = tile_blocks(b->n_tiles);
+    if (tb > 0) hipLaunchKernelGGL(k_pso_move, dim3(tb), dim3(256), 0, s, a);
+    return hip_status(hipGetLastError(), "pso_complete_move");
+}
 
 int pso_iterate_enqueue(const sird_batch *b, const pso_params *p, const pso_state *st,
                         const double *obs, int kind, int n_iters, hipStream_t s)
 {
+    if (n_iters <= 0) return SIRD_OK;
     for (int i = 0; i < n_iters; ++i) {
-        int r = forward_loss(b, st->x, obs, kind, st->f, s);
+        int r = evaluate_enqueue(b, p, st, obs, kind, i > 0, s);
         if (r) return r;
-        r = pso_step_enqueue(b, p, st, s);
+        r = gbest_enqueue(b, p, st, s);
         if (r) return r;
     }
-    return SIRD_OK;
+    return complete_move_enqueue(b, p, st, s);
 }
 
 int check_iterate(const sird_batch *b, const pso_params *p, const pso_state *st,
@@ -323,6 +351,32 @@ extern "C" int pso_step(const sird_batch *batch, const pso_params *params,
     if (r) return r;
     if (!state->f) return fail(SIRD_EINVAL, "pso_step: state->f is NULL");
     return pso_step_enqueue(batch, params, state, (hipStream_t)stream);
+}
+
+extern "C" int pso_evaluate(const sird_batch *batch, const pso_params *params,
+                            const pso_state *state, const double *obs, int loss_kind,
+                            int move_first, void *stream)
+{
+    int r = check_iterate(batch, params, state, obs, loss_kind, 1, "pso_evaluate");
+    if (r) return r;
+    return evaluate_enqueue(batch, params, state, obs, loss_kind, move_first != 0,
+                            (hipStream_t)stream);
+}
+
+extern "C" int pso_gbest(const sird_batch *batch, const pso_params *params,
+                         const pso_state *state, void *stream)
+{
+    int r = check_pso(batch, params, state, "pso_gbest");
+    if (r) return r;
+    return gbest_enqueue(batch, params, state, (hipStream_t)stream);
+}
+
+extern "C" int pso_complete_move(const sird_batch *batch, const pso_params *params,
+                                 const pso_state *state, void *stream)
+{
+    int r = check_pso(batch, params, state, "pso_complete_move");
+    if (r) return r;
+    return complete_move_enqueue(batch, params, state, (hipStream_t)stream);
 }
 
 extern "C" int sird_pso_iterate(const sird_batch *batch, const pso_params *params,

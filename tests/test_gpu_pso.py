@@ -178,3 +178,40 @@ def test_resume_is_bitwise():
         outs.append((sw.x.cpu().numpy(), sw.pbest_f.cpu().numpy(), sw.gbest_idx.cpu().numpy()))
     for a, c in zip(*outs):
         assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("dtype,launch", [("f64", dict(block=256, persistent=0)),
+                                          ("f64", dict(block=64, persistent=300)),
+                                          ("f32", dict(block=128, persistent=0))])
+def test_fused_iterate_equals_loss_plus_step(dtype, launch):
+    """sird_pso_iterate (swarm fused into the integration) leaves bitwise the
+    state of n x [sird_loss; pso_step]."""
+    wl = synth.c3(regions=list(range(6)))
+    n_parts = [100, 64, 1, 150, 33, 70]
+    states = []
+    for mode in ("unfused", "fused", "halves"):
+        b = make_batch(wl.fits, n_parts, dtype=dtype, **launch)
+        params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
+                             wl.c2, wl.seed)
+        sw = S.Swarm(b, hist_len=9)
+        obs = b.pack_obs([f.y for f in wl.fits])
+        S.pso_init(b, params, sw)
+        if mode == "unfused":
+            for _ in range(9):
+                S.sird_loss(b, sw.x, obs, "ssre", sw.f)
+                S.pso_step(b, params, sw)
+        elif mode == "fused":
+            S.sird_pso_iterate(b, params, sw, obs, "ssre", 4)
+            S.sird_pso_iterate(b, params, sw, obs, "ssre", 5)
+        else:
+            for i in range(9):
+                S.pso_evaluate(b, params, sw, obs, "ssre", move_first=i > 0)
+                S.pso_gbest(b, params, sw)
+            S.pso_complete_move(b, params, sw)
+        torch.cuda.synchronize()
+        states.append([t.cpu().numpy().copy() for t in
+                       (sw.x, sw.v, sw.pbest_x, sw.pbest_f, sw.gbest_x, sw.gbest_f,
+                        sw.gbest_idx, sw.iter, sw.hist_f, sw.hist_idx, sw.f)])
+    for other in states[1:]:
+        for a, c in zip(states[0], other):
+            assert np.array_equal(a, c, equal_nan=True)
