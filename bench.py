@@ -124,6 +124,27 @@ def copy_probe(mib):
                       "launches": 3}))
 
 
+def extras():
+    """The other configurations, each measured once (see experiments.py)."""
+    import synth
+    from paper_2204_12346_amd import experiments as X
+    res = {}
+    print("# extras: single-fit swarms ...", file=sys.stderr, flush=True)
+    res["c1_constant_beta_256x60d"] = X.swarm_throughput(synth.c1(), "f64", iters=200,
+                                                         graph_chunk=20, launch=dict(block=64))
+    for dt in ("f64", "f32"):
+        res[f"c2_segmented_8192x180d_{dt}"] = X.swarm_throughput(
+            synth.c2(), dt, iters=200, graph_chunk=20, launch=dict(block=64))
+    print("# extras: gradients ...", file=sys.stderr, flush=True)
+    wl4, th4 = synth.c4()
+    res["c4_gradients_65536x7300steps"] = X.gradients_per_s(wl4, th4)
+    print("# extras: rolling windows ...", file=sys.stderr, flush=True)
+    z = synth.c5_series()
+    res["c5_rolling_52x16x4096"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,
+                                                      launch=dict(C3_LAUNCH))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +157,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="search the launch shape before timing instead of the recorded one")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (single fits, gradients, rolling windows)")
     args = ap.parse_args()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
@@ -233,6 +256,8 @@ def main():
         },
         "wall_s": wall,
     }
+    if not args.no_extras and args.workload == "c3":
+        out["extras"] = extras()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -326,6 +326,54 @@ int sird_adam_step(const sird_batch *batch, double *theta, const double *grad, d
                    double *v, const double *lo, const double *hi, int64_t t,
                    const adam_params *params, void *stream);
 
+/* State of projected L-BFGS refinement (all device memory, caller-owned).
+ * theta-shaped: theta, grad, theta_t, grad_t; particle-indexed: f, f_t,
+ * alpha, gp, count, head; S and Y: m theta-shaped arrays back to back
+ * ([m][theta_len]); rho: [m][total_particles].  Start with count = head = 0,
+ * alpha = 1, f and grad evaluated at theta. */
+typedef struct lbfgs_state {
+    double *theta;
+    double *grad;
+    double *f;
+    double *theta_t;
+    double *grad_t;
+    double *f_t;
+    double *S;
+    double *Y;
+    double *rho;
+    double *alpha;
+    double *gp;
+    int32_t *count;
+    int32_t *head;
+    int32_t m;        /* pairs kept, 1..8 */
+    int32_t log_last; /* 1: the last parameter (I0) is optimised as log I0
+                         in [log lo, log hi] (requires lo > 0) */
+} lbfgs_state;
+
+/* Projected L-BFGS (Liu & Nocedal 1989, two-loop recursion of Nocedal 1980)
+ * in box-normalised coordinates u = (theta - lo)/(hi - lo) (for the last
+ * parameter u = (log theta - log lo)/(log hi - log lo) when log_last: I0
+ * spans decades, and linear scaling would make its curvature dwarf the
+ * others'), one round in two
+ * halves around a caller's evaluation of (f_t, grad_t) at theta_t (e.g. by
+ * sird_loss_backward):
+ *   propose: r = H g_u from the stored pairs (initial H = (s.y/y.y) I of the
+ *     newest pair, I when none); p = -r with fixed dimensions and components
+ *     pushing past an active bound zeroed; if g_u.p >= 0 the memory is
+ *     dropped and p = -g_u; without stored pairs alpha is capped so that
+ *     max |alpha p| <= 0.01; theta_t = lo + clamp(u + alpha p, 0, 1)(hi - lo);
+ *     gp = g_u.p.
+ *   accept: if f_t is finite and f_t <= f + c1 alpha gp, keep the trial
+ *     (store the pair (u_t - u, g_u,t - g_u) when s.y > 0; alpha = 1), else
+ *     halve alpha (below 1e-20: drop the memory, alpha = 1).
+ * Parameter vectors are independent; d <= 64.
+ * Errors: SIRD_EINVAL (null pointer, m outside 1..8, c1 outside (0,1),
+ * log_last not 0/1), SIRD_EHIP. */
+int sird_lbfgs_propose(const sird_batch *batch, const lbfgs_state *state, const double *lo,
+                       const double *hi, void *stream);
+int sird_lbfgs_accept(const sird_batch *batch, const lbfgs_state *state, const double *lo,
+                      const double *hi, double c1, void *stream);
+
 /* Capture iters_per_launch iterations of sird_pso_iterate into a HIP graph
  * (captured on an internal stream; no memset nodes).  Every array the
  * iterations touch must stay allocated while the graph exists; the swarm

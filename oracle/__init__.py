@@ -79,6 +79,12 @@ def lib():
                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                          _D, _I64, _D, _D, _D, _D, _D, _D, ctypes.c_int]
         L.orc_loss_grad_fwd.argtypes = prob + [_D, _D, ctypes.c_int, _D, _D]
+        _IP = ctypes.POINTER(ctypes.c_int)
+        L.orc_lbfgs_propose.argtypes = [ctypes.c_int] * 4 + [_D, _D, _D, _D, _D, _D, _D, _IP,
+                                                             _IP, _D, _D, _D, _D]
+        L.orc_lbfgs_accept.argtypes = [ctypes.c_int] * 4 + [_D, _D, ctypes.c_double, _D, _D, _D,
+                                                            _D, _D, _D, _D, _D, _D, _D, _IP,
+                                                            _IP, _D]
         L.orc_adam_step.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D,
                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double]
@@ -264,3 +270,48 @@ def adam_step(theta, grad, m, v, lo, hi, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8)
     lo, hi = _f64(lo), _f64(hi)
     lib().orc_adam_step(n, d, _dp(theta), _dp(grad), _dp(m), _dp(v), _dp(lo), _dp(hi),
                         int(t), lr, b1, b2, eps)
+
+
+# --------------------------------------------------------------- L-BFGS
+class Lbfgs:
+    """State of the oracle's projected L-BFGS over n vectors of dimension d
+    (row-major [n][d]; memory [n][m][d]); log_last optimises the last
+    dimension as its logarithm within [log lo, log hi]."""
+
+    def __init__(self, theta, m=8, log_last=False):
+        self.log_last = int(bool(log_last))
+        self.theta = _f64(theta).copy()
+        n, d = self.theta.shape
+        self.m = m
+        self.grad = np.zeros((n, d))
+        self.f = np.zeros(n)
+        self.theta_t = np.zeros((n, d))
+        self.grad_t = np.zeros((n, d))
+        self.f_t = np.zeros(n)
+        self.p = np.zeros((n, d))
+        self.gp = np.zeros(n)
+        self.S = np.zeros((n, m, d))
+        self.Y = np.zeros((n, m, d))
+        self.rho = np.zeros((n, m))
+        self.alpha = np.ones(n)
+        self.count = np.zeros(n, dtype=np.intc)
+        self.head = np.zeros(n, dtype=np.intc)
+
+    def propose(self, lo, hi):
+        lo, hi = _f64(lo), _f64(hi)
+        n, d = self.theta.shape
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib().orc_lbfgs_propose(n, d, self.m, self.log_last, _dp(lo), _dp(hi), _dp(self.theta), _dp(self.grad),
+                                _dp(self.S), _dp(self.Y), _dp(self.rho),
+                                self.count.ctypes.data_as(ip), self.head.ctypes.data_as(ip),
+                                _dp(self.alpha), _dp(self.p), _dp(self.gp), _dp(self.theta_t))
+
+    def accept(self, lo, hi, c1=1e-4):
+        lo, hi = _f64(lo), _f64(hi)
+        n, d = self.theta.shape
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib().orc_lbfgs_accept(n, d, self.m, self.log_last, _dp(lo), _dp(hi), c1, _dp(self.theta),
+                               _dp(self.grad), _dp(self.f), _dp(self.theta_t), _dp(self.grad_t),
+                               _dp(self.f_t), _dp(self.gp), _dp(self.S), _dp(self.Y),
+                               _dp(self.rho), self.count.ctypes.data_as(ip),
+                               self.head.ctypes.data_as(ip), _dp(self.alpha))

@@ -559,3 +559,187 @@ void orc_adam_step(int n, int d, double *theta, const double *grad, double *m,
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Projected L-BFGS (Liu & Nocedal 1989; two-loop recursion of Nocedal  */
+/* 1980) in box-normalised coordinates u = (theta - lo)/(hi - lo) (with */
+/* log theta for the last dimension when log_last is set), for          */
+/* refining parameter vectors with gradients of the discrete loss.      */
+/* Per vector (row q of [n][d] arrays; memory arrays [n][m][d]):         */
+/*  propose: r = H g_u by the two-loop recursion over the stored pairs   */
+/*    (initial H = (s.y / y.y) I of the newest pair, I when none);       */
+/*    p = -r; components at an active bound (u = 0 and p < 0, u = 1 and */
+/*    p > 0) and fixed dimensions are zeroed; if g_u.p >= 0 the memory   */
+/*    is dropped and p = -g_u (projected); with no stored pair the step  */
+/*    is capped so that max |alpha p| <= 0.01;                           */
+/*    u_t = clamp(u + alpha p, 0, 1), theta_t = lo + u_t (hi - lo).      */
+/*  accept: Armijo f_t <= f + c1 alpha g_u.p (finite f_t) keeps the      */
+/*    trial: the pair (u_t - u, g_u,t - g_u) is stored when s.y > 0,     */
+/*    alpha = 1; otherwise alpha is halved, and below 1e-20 the memory   */
+/*    is dropped and alpha = 1.                                          */
+/* ------------------------------------------------------------------ */
+/* Box coordinate of dimension j: u = (phi(theta) - a)/w with phi the
+ * identity, or the logarithm for the last dimension when log_last is set
+ * (I0, which spans decades); w = 0 marks a fixed dimension. */
+typedef struct { double a, w; int lg; } orc_coord;
+
+static orc_coord orc_coord_of(const double *lo, const double *hi, int j, int d, int log_last)
+{
+    orc_coord c;
+    c.lg = log_last && j == d - 1;
+    if (c.lg) {
+        c.a = log(lo[j]);
+        c.w = log(hi[j]) - c.a;
+    } else {
+        c.a = lo[j];
+        c.w = hi[j] - lo[j];
+    }
+    if (!(c.w > 0.0)) c.w = 0.0;
+    return c;
+}
+
+static double orc_to_u(orc_coord c, double th)
+{
+    if (c.w == 0.0) return 0.0;
+    return ((c.lg ? log(th) : th) - c.a) / c.w;
+}
+
+static double orc_from_u(orc_coord c, double u)
+{
+    double v = c.a + u * c.w;
+    return c.lg ? exp(v) : v;
+}
+
+/* d loss / d u from d loss / d theta */
+static double orc_grad_u(orc_coord c, double th, double g)
+{
+    return c.lg ? g * th * c.w : g * c.w;
+}
+
+void orc_lbfgs_propose(int n, int d, int m, int log_last, const double *lo, const double *hi,
+                       const double *theta, const double *grad, const double *S,
+                       const double *Y, const double *rho, int *count, const int *head,
+                       double *alpha, double *p_out, double *gp_out, double *theta_t)
+{
+    for (int q = 0; q < n; ++q) {
+        const double *th = theta + (long)q * d;
+        const double *g = grad + (long)q * d;
+        double gu[64], r[64], u[64], a[64];
+        int cnt = count[q];
+        for (int j = 0; j < d; ++j) {
+            orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
+            gu[j] = orc_grad_u(c, th[j], g[j]);
+            u[j] = orc_to_u(c, th[j]);
+            r[j] = gu[j];
+        }
+        /* first loop: newest to oldest */
+        for (int k = 0; k < cnt; ++k) {
+            int slot = ((head[q] - 1 - k) % m + m) % m;
+            const double *s = S + ((long)q * m + slot) * d;
+            const double *y = Y + ((long)q * m + slot) * d;
+            double sr = 0.0;
+            for (int j = 0; j < d; ++j) sr = sr + s[j] * r[j];
+            a[k] = rho[(long)q * m + slot] * sr;
+            for (int j = 0; j < d; ++j) r[j] = r[j] - a[k] * y[j];
+        }
+        double h0 = 1.0;
+        if (cnt > 0) {
+            int slot = ((head[q] - 1) % m + m) % m;
+            const double *s = S + ((long)q * m + slot) * d;
+            const double *y = Y + ((long)q * m + slot) * d;
+            double sy = 0.0, yy = 0.0;
+            for (int j = 0; j < d; ++j) { sy = sy + s[j] * y[j]; yy = yy + y[j] * y[j]; }
+            if (yy > 0.0) h0 = sy / yy;
+        }
+        for (int j = 0; j < d; ++j) r[j] = h0 * r[j];
+        /* second loop: oldest to newest */
+        for (int k = cnt - 1; k >= 0; --k) {
+            int slot = ((head[q] - 1 - k) % m + m) % m;
+            const double *s = S + ((long)q * m + slot) * d;
+            const double *y = Y + ((long)q * m + slot) * d;
+            double yr = 0.0;
+            for (int j = 0; j < d; ++j) yr = yr + y[j] * r[j];
+            double b = rho[(long)q * m + slot] * yr;
+            for (int j = 0; j < d; ++j) r[j] = r[j] + s[j] * (a[k] - b);
+        }
+        double *p = p_out + (long)q * d;
+        double gp = 0.0;
+        for (int j = 0; j < d; ++j) {
+            double w = orc_coord_of(lo, hi, j, d, log_last).w;
+            double pj = -r[j];
+            if (w == 0.0 || (u[j] <= 0.0 && pj < 0.0) || (u[j] >= 1.0 && pj > 0.0)) pj = 0.0;
+            p[j] = pj;
+            gp = gp + gu[j] * pj;
+        }
+        if (!(gp < 0.0)) { /* not a descent direction: steepest descent */
+            cnt = 0;
+            gp = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double w = orc_coord_of(lo, hi, j, d, log_last).w;
+                double pj = -gu[j];
+                if (w == 0.0 || (u[j] <= 0.0 && pj < 0.0) || (u[j] >= 1.0 && pj > 0.0)) pj = 0.0;
+                p[j] = pj;
+                gp = gp + gu[j] * pj;
+            }
+        }
+        count[q] = cnt;
+        if (cnt == 0) {
+            double pmax = 0.0;
+            for (int j = 0; j < d; ++j) if (fabs(p[j]) > pmax) pmax = fabs(p[j]);
+            if (pmax > 0.0 && alpha[q] * pmax > 0.01) alpha[q] = 0.01 / pmax;
+        }
+        gp_out[q] = gp;
+        for (int j = 0; j < d; ++j) {
+            orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
+            if (c.w == 0.0) { theta_t[(long)q * d + j] = th[j]; continue; }
+            double ut = u[j] + alpha[q] * p[j];
+            if (ut < 0.0) ut = 0.0;
+            if (ut > 1.0) ut = 1.0;
+            theta_t[(long)q * d + j] = orc_from_u(c, ut);
+        }
+    }
+}
+
+void orc_lbfgs_accept(int n, int d, int m, int log_last, const double *lo, const double *hi,
+                      double c1,
+                      double *theta, double *grad, double *f, const double *theta_t,
+                      const double *grad_t, const double *f_t, const double *gp,
+                      double *S, double *Y, double *rho, int *count, int *head,
+                      double *alpha)
+{
+    for (int q = 0; q < n; ++q) {
+        double ft = f_t[q];
+        int ok = isfinite(ft) && ft <= f[q] + c1 * alpha[q] * gp[q];
+        if (ok) {
+            double sv[64], yv[64], sy = 0.0;
+            for (int j = 0; j < d; ++j) {
+                orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
+                double a = theta[(long)q * d + j], b = theta_t[(long)q * d + j];
+                sv[j] = orc_to_u(c, b) - orc_to_u(c, a);
+                yv[j] = orc_grad_u(c, b, grad_t[(long)q * d + j]) -
+                        orc_grad_u(c, a, grad[(long)q * d + j]);
+                sy = sy + sv[j] * yv[j];
+            }
+            if (sy > 0.0) {
+                double *s = S + ((long)q * m + head[q]) * d;
+                double *y = Y + ((long)q * m + head[q]) * d;
+                for (int j = 0; j < d; ++j) { s[j] = sv[j]; y[j] = yv[j]; }
+                rho[(long)q * m + head[q]] = 1.0 / sy;
+                head[q] = (head[q] + 1) % m;
+                if (count[q] < m) count[q] = count[q] + 1;
+            }
+            for (int j = 0; j < d; ++j) {
+                theta[(long)q * d + j] = theta_t[(long)q * d + j];
+                grad[(long)q * d + j] = grad_t[(long)q * d + j];
+            }
+            f[q] = ft;
+            alpha[q] = 1.0;
+        } else {
+            alpha[q] = 0.5 * alpha[q];
+            if (alpha[q] < 1e-20) {
+                count[q] = 0;
+                alpha[q] = 1.0;
+            }
+        }
+    }
+}

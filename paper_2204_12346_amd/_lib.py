@@ -74,6 +74,12 @@ class adam_params(ctypes.Structure):
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
+class lbfgs_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("theta", "grad", "f", "theta_t", "grad_t", "f_t", "S", "Y", "rho", "alpha",
+                 "gp", "count", "head")] + [("m", ctypes.c_int32), ("log_last", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _B = ctypes.POINTER(sird_batch)
 _PP = ctypes.POINTER(pso_params)
@@ -102,6 +108,8 @@ SIGNATURES = {
     "sird_gather": (_I, [_B, _P, _P, _B, _P, _P, _I, _P]),
     "sird_adam_step": (_I, [_B, _P, _P, _P, _P, _P, _P, _I64,
                             ctypes.POINTER(adam_params), _P]),
+    "sird_lbfgs_propose": (_I, [_B, ctypes.POINTER(lbfgs_state), _P, _P, _P]),
+    "sird_lbfgs_accept": (_I, [_B, ctypes.POINTER(lbfgs_state), _P, _P, ctypes.c_double, _P]),
     "sird_graph_create": (_I, [_B, _PP, _PS, _P, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
     "sird_graph_launch": (_I, [_P, _I, _P]),
     "sird_graph_destroy": (_I, [_P]),

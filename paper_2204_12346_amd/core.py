@@ -319,6 +319,49 @@ def sird_adam_step(batch: Batch, theta, grad, m, v, lo, hi, t, lr=1e-3, beta1=0.
                                stream_handle(stream)), "sird_adam_step")
 
 
+class LbfgsState:
+    """Device state of projected L-BFGS over the parameter vectors of a
+    batch (lbfgs_state); theta is copied in, f/grad are evaluated by the
+    caller before the first round."""
+
+    def __init__(self, batch: Batch, theta, m=8, log_last=True):
+        dev = batch.device
+        th = max(batch.theta_len, 1)
+        P = max(batch.total_particles, 1)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.m = int(m)
+        self.theta = theta.detach().clone()
+        self.grad = torch.zeros(th, **f64)
+        self.f = torch.zeros(P, **f64)
+        self.theta_t = torch.zeros(th, **f64)
+        self.grad_t = torch.zeros(th, **f64)
+        self.f_t = torch.zeros(P, **f64)
+        self.S = torch.zeros(self.m * th, **f64)
+        self.Y = torch.zeros(self.m * th, **f64)
+        self.rho = torch.zeros(self.m * P, **f64)
+        self.alpha = torch.ones(P, **f64)
+        self.gp = torch.zeros(P, **f64)
+        self.count = torch.zeros(P, dtype=torch.int32, device=dev)
+        self.head = torch.zeros(P, dtype=torch.int32, device=dev)
+        c = _lib.lbfgs_state()
+        for name in ("theta", "grad", "f", "theta_t", "grad_t", "f_t", "S", "Y", "rho",
+                     "alpha", "gp", "count", "head"):
+            setattr(c, name, ptr(getattr(self, name)))
+        c.m = self.m
+        c.log_last = int(bool(log_last))
+        self.c = c
+
+
+def sird_lbfgs_propose(batch: Batch, st: LbfgsState, lo, hi, stream=None):
+    check(lib().sird_lbfgs_propose(ctypes.byref(batch.c), ctypes.byref(st.c), ptr(lo), ptr(hi),
+                                   stream_handle(stream)), "sird_lbfgs_propose")
+
+
+def sird_lbfgs_accept(batch: Batch, st: LbfgsState, lo, hi, c1=1e-4, stream=None):
+    check(lib().sird_lbfgs_accept(ctypes.byref(batch.c), ctypes.byref(st.c), ptr(lo), ptr(hi),
+                                  float(c1), stream_handle(stream)), "sird_lbfgs_accept")
+
+
 class Graph:
     """HIP graph of iters_per_launch [sird_loss -> pso_step] iterations."""
 

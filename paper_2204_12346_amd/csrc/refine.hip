@@ -152,9 +152,293 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
     }
 }
 
+// ---------------------------------------------------------------- L-BFGS
+constexpr int kLbfgsMaxM = 8;
+
+struct LbfgsArgs {
+    const sird_problem *probs;
+    const sird_tile *tiles;
+    int n_tiles;
+    int64_t theta_len;
+    int64_t total_particles;
+    lbfgs_state st;
+    const double *lo;
+    const double *hi;
+    double c1;
+};
+
+// Box coordinate of dimension j: u = (phi(theta) - a)/w, phi the identity,
+// or the logarithm for the last dimension when log_last is set; w = 0 marks
+// a fixed dimension.
+struct Coord {
+    double a, w;
+    bool lg;
+};
+
+__device__ __forceinline__ Coord coord_of(const double *lo, const double *hi, int j, int d,
+                                          int log_last)
+{
+    Coord c;
+    c.lg = log_last && j == d - 1;
+    if (c.lg) {
+        c.a = log(lo[j]);
+        c.w = log(hi[j]) - c.a;
+    } else {
+        c.a = lo[j];
+        c.w = hi[j] - lo[j];
+    }
+    if (!(c.w > 0.0)) c.w = 0.0;
+    return c;
+}
+
+__device__ __forceinline__ double to_u(const Coord &c, double th)
+{
+    if (c.w == 0.0) return 0.0;
+    return ((c.lg ? log(th) : th) - c.a) / c.w;
+}
+
+__device__ __forceinline__ double from_u(const Coord &c, double u)
+{
+    const double v = c.a + u * c.w;
+    return c.lg ? exp(v) : v;
+}
+
+__device__ __forceinline__ double grad_u(const Coord &c, double th, double g)
+{
+    return c.lg ? g * th * c.w : g * c.w;
+}
+
+// One lane per parameter vector.  The recursion vector r lives in the lane's
+// column of theta_t until theta_t receives the trial point.
+__global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = wave_tile_index();
+    if (t >= a.n_tiles) return;
+    const sird_tile tl = a.tiles[t];
+    const sird_problem P = a.probs[tl.prob];
+    const int pl = tl.p0 + lane;
+    if (pl >= P.n_part) return;
+    const int d = P.n_seg + 3;
+    const int m = a.st.m;
+    const size_t n = (size_t)P.n_part;
+    const size_t col = (size_t)P.theta_off + pl;
+    const size_t pidx = (size_t)P.p_off + pl;
+    const double *lo = a.lo + P.box_off;
+    const double *hi = a.hi + P.box_off;
+    const double *th = a.st.theta + col;
+    const double *g = a.st.grad + col;
+    double *r = a.st.theta_t + col;
+    int cnt = a.st.count[pidx];
+    const int head = a.st.head[pidx];
+    const int lgl = a.st.log_last;
+    for (int j = 0; j < d; ++j) r[j * n] = grad_u(coord_of(lo, hi, j, d, lgl), th[j * n], g[j * n]);
+    double coef[kLbfgsMaxM];
+#pragma unroll
+    for (int k = 0; k < kLbfgsMaxM; ++k) {  // newest to oldest
+        coef[k] = 0.0;
+        if (k < cnt) {
+            const int slot = ((head - 1 - k) % m + m) % m;
+            const double *S = a.st.S + (size_t)slot * a.theta_len + col;
+            const double *Y = a.st.Y + (size_t)slot * a.theta_len + col;
+            double sr = 0.0;
+            for (int j = 0; j < d; ++j) sr = sr + S[j * n] * r[j * n];
+            coef[k] = a.st.rho[(size_t)slot * a.total_particles + pidx] * sr;
+            for (int j = 0; j < d; ++j) r[j * n] = r[j * n] - coef[k] * Y[j * n];
+        }
+    }
+    double h0 = 1.0;
+    if (cnt > 0) {
+        const int slot = ((head - 1) % m + m) % m;
+        const double *S = a.st.S + (size_t)slot * a.theta_len + col;
+        const double *Y = a.st.Y + (size_t)slot * a.theta_len + col;
+        double sy = 0.0, yy = 0.0;
+        for (int j = 0; j < d; ++j) {
+            sy = sy + S[j * n] * Y[j * n];
+            yy = yy + Y[j * n] * Y[j * n];
+        }
+        if (yy > 0.0) h0 = sy / yy;
+    }
+    for (int j = 0; j < d; ++j) r[j * n] = h0 * r[j * n];
+#pragma unroll
+    for (int k = kLbfgsMaxM - 1; k >= 0; --k) {  // oldest to newest
+        if (k < cnt) {
+            const int slot = ((head - 1 - k) % m + m) % m;
+            const double *S = a.st.S + (size_t)slot * a.theta_len + col;
+            const double *Y = a.st.Y + (size_t)slot * a.theta_len + col;
+            double yr = 0.0;
+            for (int j = 0; j < d; ++j) yr = yr + Y[j * n] * r[j * n];
+            const double b = a.st.rho[(size_t)slot * a.total_particles + pidx] * yr;
+            for (int j = 0; j < d; ++j) r[j * n] = r[j * n] + S[j * n] * (coef[k] - b);
+        }
+    }
+    // direction p = -r, projected; r[j] <- p[j]
+    double gp = 0.0, pmax = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const Coord c = coord_of(lo, hi, j, d, lgl);
+        const double u = to_u(c, th[j * n]);
+        double pj = -r[j * n];
+        if (c.w == 0.0 || (u <= 0.0 && pj < 0.0) || (u >= 1.0 && pj > 0.0)) pj = 0.0;
+        r[j * n] = pj;
+        gp = gp + grad_u(c, th[j * n], g[j * n]) * pj;
+    }
+    if (!(gp < 0.0)) {  // not a descent direction: steepest descent
+        cnt = 0;
+        gp = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const Coord c = coord_of(lo, hi, j, d, lgl);
+            const double u = to_u(c, th[j * n]);
+            const double gu = grad_u(c, th[j * n], g[j * n]);
+            double pj = -gu;
+            if (c.w == 0.0 || (u <= 0.0 && pj < 0.0) || (u >= 1.0 && pj > 0.0)) pj = 0.0;
+            r[j * n] = pj;
+            gp = gp + gu * pj;
+        }
+    }
+    a.st.count[pidx] = cnt;
+    double alpha = a.st.alpha[pidx];
+    if (cnt == 0) {
+        for (int j = 0; j < d; ++j) pmax = fmax(pmax, fabs(r[j * n]));
+        if (pmax > 0.0 && alpha * pmax > 0.01) alpha = 0.01 / pmax;
+        a.st.alpha[pidx] = alpha;
+    }
+    a.st.gp[pidx] = gp;
+    for (int j = 0; j < d; ++j) {
+        const Coord c = coord_of(lo, hi, j, d, lgl);
+        if (c.w == 0.0) {
+            r[j * n] = th[j * n];
+            continue;
+        }
+        double ut = to_u(c, th[j * n]) + alpha * r[j * n];
+        if (ut < 0.0) ut = 0.0;
+        if (ut > 1.0) ut = 1.0;
+        r[j * n] = from_u(c, ut);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = wave_tile_index();
+    if (t >= a.n_tiles) return;
+    const sird_tile tl = a.tiles[t];
+    const sird_problem P = a.probs[tl.prob];
+    const int pl = tl.p0 + lane;
+    if (pl >= P.n_part) return;
+    const int d = P.n_seg + 3;
+    const int m = a.st.m;
+    const size_t n = (size_t)P.n_part;
+    const size_t col = (size_t)P.theta_off + pl;
+    const size_t pidx = (size_t)P.p_off + pl;
+    const double *lo = a.lo + P.box_off;
+    const double *hi = a.hi + P.box_off;
+    double *th = a.st.theta + col;
+    double *g = a.st.grad + col;
+    const double *tt = a.st.theta_t + col;
+    const double *gt = a.st.grad_t + col;
+    const double ft = a.st.f_t[pidx];
+    const double alpha = a.st.alpha[pidx];
+    const bool ok = isfinite(ft) && ft <= a.st.f[pidx] + a.c1 * alpha * a.st.gp[pidx];
+    if (ok) {
+        const int lgl = a.st.log_last;
+        double sy = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const Coord c = coord_of(lo, hi, j, d, lgl);
+            const double sj = to_u(c, tt[j * n]) - to_u(c, th[j * n]);
+            const double yj = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
+            sy = sy + sj * yj;
+        }
+        if (sy > 0.0) {
+            const int head = a.st.head[pidx];
+            double *S = a.st.S + (size_t)head * a.theta_len + col;
+            double *Y = a.st.Y + (size_t)head * a.theta_len + col;
+            for (int j = 0; j < d; ++j) {
+                const Coord c = coord_of(lo, hi, j, d, lgl);
+                S[j * n] = to_u(c, tt[j * n]) - to_u(c, th[j * n]);
+                Y[j * n] = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
+            }
+            a.st.rho[(size_t)head * a.total_particles + pidx] = 1.0 / sy;
+            a.st.head[pidx] = (head + 1) % m;
+            if (a.st.count[pidx] < m) a.st.count[pidx] = a.st.count[pidx] + 1;
+        }
+        for (int j = 0; j < d; ++j) {
+            th[j * n] = tt[j * n];
+            g[j * n] = gt[j * n];
+        }
+        a.st.f[pidx] = ft;
+        a.st.alpha[pidx] = 1.0;
+    } else {
+        const double half = 0.5 * alpha;
+        if (half < 1e-20) {
+            a.st.count[pidx] = 0;
+            a.st.alpha[pidx] = 1.0;
+        } else {
+            a.st.alpha[pidx] = half;
+        }
+    }
+}
+
+static int check_lbfgs(const sird_batch *b, const lbfgs_state *st, const double *lo,
+                       const double *hi, const char *who)
+{
+    int s = check_batch(b, who);
+    if (s) return s;
+    const std::string w(who);
+    if (!st || !lo || !hi) return fail(SIRD_EINVAL, w + ": NULL argument");
+    if (!st->theta || !st->grad || !st->f || !st->theta_t || !st->grad_t || !st->f_t ||
+        !st->S || !st->Y || !st->rho || !st->alpha || !st->gp || !st->count || !st->head)
+        return fail(SIRD_EINVAL, w + ": NULL state array");
+    if (st->m < 1 || st->m > kLbfgsMaxM) return fail(SIRD_EINVAL, w + ": m must be in 1..8");
+    if (st->log_last != 0 && st->log_last != 1)
+        return fail(SIRD_EINVAL, w + ": log_last must be 0 or 1");
+    if (b->max_d > 64) return fail(SIRD_EINVAL, w + ": d > 64");
+    return SIRD_OK;
+}
+
+static LbfgsArgs lbfgs_args(const sird_batch *b, const lbfgs_state *st, const double *lo,
+                            const double *hi, double c1)
+{
+    LbfgsArgs a{};
+    a.probs = b->probs;
+    a.tiles = b->tiles;
+    a.n_tiles = b->n_tiles;
+    a.theta_len = b->theta_len;
+    a.total_particles = b->total_particles;
+    a.st = *st;
+    a.lo = lo;
+    a.hi = hi;
+    a.c1 = c1;
+    return a;
+}
+
 }  // namespace sird
 
 using namespace sird;
+
+extern "C" int sird_lbfgs_propose(const sird_batch *batch, const lbfgs_state *state,
+                                  const double *lo, const double *hi, void *stream)
+{
+    int st = check_lbfgs(batch, state, lo, hi, "sird_lbfgs_propose");
+    if (st) return st;
+    const int grid = tile_blocks(batch->n_tiles);
+    if (grid == 0) return SIRD_OK;
+    hipLaunchKernelGGL(k_lbfgs_propose, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                       lbfgs_args(batch, state, lo, hi, 0.0));
+    return hip_status(hipGetLastError(), "sird_lbfgs_propose");
+}
+
+extern "C" int sird_lbfgs_accept(const sird_batch *batch, const lbfgs_state *state,
+                                 const double *lo, const double *hi, double c1, void *stream)
+{
+    int st = check_lbfgs(batch, state, lo, hi, "sird_lbfgs_accept");
+    if (st) return st;
+    if (!(c1 > 0.0 && c1 < 1.0)) return fail(SIRD_EINVAL, "sird_lbfgs_accept: c1 outside (0,1)");
+    const int grid = tile_blocks(batch->n_tiles);
+    if (grid == 0) return SIRD_OK;
+    hipLaunchKernelGGL(k_lbfgs_accept, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                       lbfgs_args(batch, state, lo, hi, c1));
+    return hip_status(hipGetLastError(), "sird_lbfgs_accept");
+}
 
 extern "C" int pso_topk(const sird_batch *batch, const double *pbest_f, int k,
                         int64_t *idx_out, void *stream)

@@ -13,8 +13,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from .core import (Batch, Graph, ProblemSpec, PsoParams, Swarm, pso_init, pso_topk,
-                   sird_adam_step, sird_gather, sird_integrate, sird_loss, sird_loss_backward,
+from .core import (Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm, pso_init,
+                   pso_topk, sird_adam_step, sird_gather, sird_integrate, sird_lbfgs_accept,
+                   sird_lbfgs_propose, sird_loss, sird_loss_backward,
                    sird_loss_backward_workspace, sird_pso_iterate)
 
 
@@ -80,6 +81,59 @@ def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre",
             prev = cur
     final = sird_loss(rb, theta, obs, kind)
     return Refined(rb, theta, final, idx, t)
+
+
+def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre", rounds=200,
+                 c1=1e-4, ckpt_interval=0, workspace=None, callback=None, check_every=0):
+    """Run projected L-BFGS rounds on every parameter vector of rb: each
+    round is sird_lbfgs_propose, the adjoint at the trial points
+    (sird_loss_backward), sird_lbfgs_accept.  st.f / st.grad must hold the
+    loss and gradient at st.theta.  callback(round) every check_every rounds
+    may return True to stop."""
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8),
+                         dtype=torch.uint8, device=rb.device)
+    for r in range(1, rounds + 1):
+        sird_lbfgs_propose(rb, st, params.lo, params.hi)
+        sird_loss_backward(rb, st.theta_t, obs, kind, grad_theta=st.grad_t, loss_out=st.f_t,
+                           ckpt_interval=ckpt_interval, workspace=ws)
+        sird_lbfgs_accept(rb, st, params.lo, params.hi, c1)
+        if callback is not None and check_every and r % check_every == 0:
+            if callback(r):
+                return r
+    return rounds
+
+
+def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre", k=32,
+                 max_rounds=500, rel_tol=1e-12, check_every=25, m=8,
+                 ckpt_interval=0) -> Refined:
+    """Projected L-BFGS from the k best personal bests of every problem, in
+    box-normalised coordinates, with gradients from the discrete adjoint.
+    Stops after max_rounds, or when no vector's loss changed by more than
+    rel_tol (relative) over check_every rounds."""
+    idx = pso_topk(batch, swarm.pbest_f, k)
+    specs = [ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, k, s.stream)
+             for s in batch.specs]
+    rb = Batch(specs, dtype="f64", device=batch.device)
+    theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
+    st = LbfgsState(rb, theta, m=m)
+    ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
+                     device=batch.device)
+    sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f,
+                       ckpt_interval=ckpt_interval, workspace=ws)
+    prev = [st.f.clone()]
+
+    def converged(r):
+        cur = st.f.clone()
+        done = bool((((cur - prev[0]).abs() <= rel_tol * cur.abs()) |
+                     ~torch.isfinite(cur)).all().item())
+        prev[0] = cur
+        return done
+
+    steps = lbfgs_rounds(rb, st, params, obs, kind, max_rounds, ckpt_interval=ckpt_interval,
+                         workspace=ws, callback=converged, check_every=check_every)
+    return Refined(rb, st.theta, st.f.clone(), idx, steps)
 
 
 def best_per_problem(batch: Batch, theta: torch.Tensor, loss: torch.Tensor):

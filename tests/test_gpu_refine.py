@@ -134,3 +134,56 @@ def test_autotuner_candidates_agree_bitwise(tmp_path, monkeypatch):
     # a second call is served from the cache
     again = autotune.autotune(b, theta, obs, "ssre")
     assert again == best
+
+
+def test_lbfgs_rounds_match_oracle_in_lockstep():
+    """Same (f, grad) inputs on both sides -> the same proposals and updates."""
+    f = synth.c2().fits[0]
+    P = 40
+    th = random_theta(f, P, seed=11)
+    th[:, :f.K] *= 0.5
+    b = make_batch([f], [P])
+    lo, hi = b.pack_box([f.lo]), b.pack_box([f.hi])
+    st = S.LbfgsState(b, b.pack_theta([th]), m=5, log_last=True)
+    ost = oracle.Lbfgs(th, m=5, log_last=True)
+    prob = oracle_problem(f)
+
+    def fg(t):
+        return oracle.loss_grad_fwd(prob, t, f.y, "ssre")
+
+    for q in range(P):
+        ost.f[q], ost.grad[q] = fg(th[q])
+    st.f.copy_(torch.from_numpy(np.concatenate([ost.f, np.zeros(0)])).cuda())
+    st.grad.copy_(b.pack_theta([ost.grad]))
+    for rnd in range(12):
+        S.sird_lbfgs_propose(b, st, lo, hi)
+        ost.propose(f.lo, f.hi)
+        tt = b.unpack_theta(st.theta_t)[0]
+        np.testing.assert_allclose(tt, ost.theta_t, rtol=1e-13, atol=1e-300, err_msg=f"round {rnd}")
+        np.testing.assert_allclose(st.gp.cpu().numpy(), ost.gp, rtol=1e-12)
+        # evaluate at the oracle's trial points, feed both sides the same values
+        for q in range(P):
+            ost.f_t[q], ost.grad_t[q] = fg(ost.theta_t[q])
+        st.theta_t.copy_(b.pack_theta([ost.theta_t]))
+        st.f_t.copy_(torch.from_numpy(ost.f_t.copy()).cuda())
+        st.grad_t.copy_(b.pack_theta([ost.grad_t]))
+        S.sird_lbfgs_accept(b, st, lo, hi, 1e-4)
+        ost.accept(f.lo, f.hi, 1e-4)
+        np.testing.assert_allclose(b.unpack_theta(st.theta)[0], ost.theta, rtol=1e-13)
+        assert np.array_equal(st.count.cpu().numpy(), ost.count)
+        assert np.array_equal(st.head.cpu().numpy(), ost.head)
+        np.testing.assert_allclose(st.alpha.cpu().numpy(), ost.alpha, rtol=1e-13)
+
+
+def test_lbfgs_refinement_recovers_noise_free_truth():
+    wl = synth.c1(n_part=64, iters=20)
+    f = wl.fits[0]
+    y = oracle.integrate(oracle_problem(f), f.truth)[3]
+    b = make_batch([f], [64])
+    params = S.PsoParams(b, [f.lo], [f.hi], wl.w, wl.c1, wl.c2, wl.seed)
+    obs = b.pack_obs([y])
+    sw = fit.run_swarm(b, params, obs, "ssre", iters=20)
+    ref = fit.refine_lbfgs(b, sw, params, obs, "ssre", k=8, max_rounds=400)
+    th, L = fit.best_per_problem(ref.batch, ref.theta, ref.loss)
+    assert L[0] < 1e-14
+    np.testing.assert_allclose(th[0], f.truth, rtol=1e-5)
