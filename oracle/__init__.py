@@ -28,7 +28,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sird_oracle.c")
 _LIB = os.path.join(_HERE, "libsird_oracle.so")
 
-LOSS_KINDS = {"ssre": 0, "mse": 1, "mxse": 2, "mae": 3, "mape": 4}
+LOSS_KINDS = {"ssre": 0, "mse": 1, "mxse": 2, "mae": 3, "mape": 4,
+              "ird_mxse": 5, "ird_mse": 6, "ird_mae": 7, "ird_mape": 8}
 
 _D = ctypes.POINTER(ctypes.c_double)
 _U64 = ctypes.POINTER(ctypes.c_uint64)
@@ -85,6 +86,16 @@ def lib():
         L.orc_lbfgs_accept.argtypes = [ctypes.c_int] * 4 + [_D, _D, ctypes.c_double, _D, _D, _D,
                                                             _D, _D, _D, _D, _D, _D, _D, _IP,
                                                             _IP, _D]
+        L.orc_integrate_model.argtypes = [ctypes.c_int] + prob + [_D, _D]
+        L.orc_loss_ird.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D]
+        L.orc_loss_ird.restype = ctypes.c_double
+        L.orc_loss_batch_model.argtypes = [ctypes.c_int] + prob + [ctypes.c_int, _D, _D,
+                                                                   ctypes.c_int, _D, ctypes.c_int]
+        L.orc_pso_sort_pair.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
+        L.orc_pso_run_model.argtypes = [ctypes.c_int] + prob + [
+            _D, ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
+            ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _D, _I64, _D, _D,
+            _D, _D, _D, _D, ctypes.c_int]
         L.orc_adam_step.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D,
                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double]
@@ -105,13 +116,17 @@ def _kind(kind):
 
 
 class Problem:
-    """One calibration window: W days at spd RK4 steps per day, K beta
+    """One calibration window: W days at spd steps per day, population N,
+    fixed initial removed R0 and deceased D0.  model 0: RK4 with K beta
     segments of seg_days days (the last one extends to the window end),
-    population N, fixed initial removed R0 and deceased D0."""
+    theta = (beta_1..beta_K, gamma, mu, I0); model 1: forward Euler with the
+    ramp of eq. (beta), K = 4, theta = (beta1, beta2, t1, t2, gamma, mu, I0)."""
 
-    def __init__(self, W, spd, seg_days, K, N, R0=0.0, D0=0.0):
+    def __init__(self, W, spd, seg_days, K, N, R0=0.0, D0=0.0, model=0):
         self.W, self.spd, self.seg_days, self.K = int(W), int(spd), int(seg_days), int(K)
         self.N, self.R0, self.D0 = float(N), float(R0), float(D0)
+        self.model = int(model)
+        assert self.model in (0, 1) and (self.model == 0 or self.K == 4)
 
     @property
     def d(self):
@@ -315,3 +330,57 @@ class Lbfgs:
                                _dp(self.f_t), _dp(self.gp), _dp(self.S), _dp(self.Y),
                                _dp(self.rho), self.count.ctypes.data_as(ip),
                                self.head.ctypes.data_as(ip), _dp(self.alpha))
+
+
+# ------------------------------------------------ the paper's own variant
+def integrate_model(prob: Problem, theta):
+    """S, I, R, D at every day for either model, shape (4, W+1)."""
+    th = _f64(theta)
+    assert th.shape == (prob.d,)
+    days = np.zeros((4, prob.W + 1))
+    lib().orc_integrate_model(prob.model, *prob.args(), _dp(th), _dp(days))
+    return days
+
+
+def loss_ird(kind, Ihat, Rhat, Dhat, yI, yR, yD):
+    """F_IRD of Sec. 3.1 with low-level cost kind (mse, mxse, mae, mape)."""
+    arrs = [_f64(a) for a in (Ihat, Rhat, Dhat, yI, yR, yD)]
+    W = len(arrs[0]) - 1
+    return lib().orc_loss_ird(_kind(kind), W, *[_dp(a) for a in arrs])
+
+
+def loss_batch_model(prob: Problem, theta, obs, kind, nthreads=0):
+    """Losses of every row of theta for either model; obs = y_D for the
+    D-only costs, [y_I; y_R; y_D] (3 (W+1) values) for the ird_* costs."""
+    th = _f64(theta)
+    P = th.shape[0]
+    ob = _f64(obs).reshape(-1)
+    k = _kind(kind)
+    assert ob.shape == ((3 if k >= 5 else 1) * (prob.W + 1),)
+    out = np.zeros(P)
+    lib().orc_loss_batch_model(prob.model, *prob.args(), P, _dp(th), _dp(ob), k, _dp(out),
+                               int(nthreads))
+    return out
+
+
+def pso_sort_pair(s: Swarm, j=2):
+    """Order the pair (j, j+1) of every position (the ramp's t1 <= t2)."""
+    P, d = s.x.shape
+    lib().orc_pso_sort_pair(P, d, j, _dp(s.x))
+
+
+def pso_run_model(prob: Problem, obs, kind, P, lo, hi, w, c1, c2, seed, stream, iters,
+                  nthreads=0):
+    lo, hi, ob = _f64(lo), _f64(hi), _f64(obs).reshape(-1)
+    d = prob.d
+    s = Swarm(P, d)
+    hf = np.zeros(iters)
+    hi_ = np.zeros(iters, dtype=np.int64)
+    hm = np.zeros(iters)
+    lib().orc_pso_run_model(prob.model, *prob.args(), _dp(ob), _kind(kind), P, _dp(lo), _dp(hi),
+                            w, c1, c2, seed, stream, iters, _dp(hf),
+                            hi_.ctypes.data_as(_I64), _dp(hm), _dp(s.x), _dp(s.v),
+                            _dp(s.pbest_x), _dp(s.pbest_f), _dp(s.gbest_x), int(nthreads))
+    s.gbest_f[0] = hf[-1] if iters else np.inf
+    s.gbest_idx[0] = hi_[-1] if iters else -1
+    return hf, hi_, hm, s

@@ -743,3 +743,143 @@ void orc_lbfgs_accept(int n, int d, int m, int log_last, const double *lo, const
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's own variant (Sec. 2.2, 3.1, 3.3): forward Euler with the  */
+/* ramp of eq. (beta), parameter vector                                 */
+/*   theta = (beta1, beta2, t1, t2, gamma, mu, I0)   (d = 7),           */
+/* initial state S = N - I0 - R0 - D0, I0, R0, D0 (the paper takes it   */
+/* from the data on the window's first day; I0 is then a fixed box      */
+/* dimension).  beta is evaluated at the start of each step, t in days  */
+/* from the window start.                                               */
+/* ------------------------------------------------------------------ */
+void orc_integrate_model(int model, int W, int spd, int seg_days, int K, double N, double R0,
+                         double D0, const double *theta, double *days)
+{
+    if (model == 0) {
+        orc_integrate(W, spd, seg_days, K, N, R0, D0, theta, days, NULL);
+        return;
+    }
+    double th6[6] = {theta[0], theta[1], theta[2], theta[3], theta[4], theta[5]};
+    double y0[4];
+    initial_state(N, R0, D0, theta[6], y0);
+    orc_integrate_euler_ramp(W, spd, th6, y0, N, days);
+}
+
+/* F_IRD of Sec. 3.1: the maximum over I, R, D of a low-level cost.  For
+ * MXSE, MSE and MAE the errors are taken after the min-max normalisation
+ * f_Y(y) = (y - min y)/(max y - min y) of the observed series (applied to
+ * both the observation and the model value, so the error is
+ * (y - yhat)/(max y - min y)); a flat observed series (max = min) is
+ * normalised by 1.  MAPE is not normalised.  kind is the low-level cost
+ * (ORC_MSE, ORC_MXSE, ORC_MAE, ORC_MAPE); n = W + 1 days. */
+double orc_loss_ird(int kind, int W, const double *Ihat, const double *Rhat,
+                    const double *Dhat, const double *yI, const double *yR, const double *yD)
+{
+    const double *yh[3] = {Ihat, Rhat, Dhat};
+    const double *yo[3] = {yI, yR, yD};
+    double F = -INFINITY;
+    for (int c = 0; c < 3; ++c) {
+        double lo = yo[c][0], hi = yo[c][0];
+        for (int i = 1; i <= W; ++i) {
+            if (yo[c][i] < lo) lo = yo[c][i];
+            if (yo[c][i] > hi) hi = yo[c][i];
+        }
+        double range = hi - lo > 0.0 ? hi - lo : 1.0;
+        double v;
+        if (kind == ORC_MAPE) {
+            v = orc_loss(ORC_MAPE, W, yh[c], yo[c]);
+        } else {
+            double *a = (double *)malloc(sizeof(double) * (size_t)(W + 1));
+            double *b = (double *)malloc(sizeof(double) * (size_t)(W + 1));
+            for (int i = 0; i <= W; ++i) {
+                a[i] = (yh[c][i] - lo) / range;
+                b[i] = (yo[c][i] - lo) / range;
+            }
+            v = orc_loss(kind, W, a, b);
+            free(a);
+            free(b);
+        }
+        if (isnan(v)) return NAN;
+        if (v > F) F = v;
+    }
+    return F;
+}
+
+/* Losses of P parameter vectors of either model.  kind < 5: the D-only
+ * costs of orc_loss on obs = y_D; kind 5..8: F_IRD with low-level cost
+ * MXSE, MSE, MAE, MAPE on obs = [y_I; y_R; y_D] (3 (W+1) values). */
+void orc_loss_batch_model(int model, int W, int spd, int seg_days, int K, double N, double R0,
+                          double D0, int P, const double *theta, const double *obs, int kind,
+                          double *loss, int nthreads)
+{
+    int d = K + 3;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int p = 0; p < P; ++p) {
+        double *days = (double *)malloc(sizeof(double) * 4 * (size_t)(W + 1));
+        orc_integrate_model(model, W, spd, seg_days, K, N, R0, D0, theta + (long)p * d, days);
+        long n1 = W + 1;
+        double l;
+        if (kind < 5) {
+            l = orc_loss(kind, W, days + 3 * n1, obs);
+        } else {
+            static const int low[4] = {ORC_MXSE, ORC_MSE, ORC_MAE, ORC_MAPE};
+            l = orc_loss_ird(low[kind - 5], W, days + n1, days + 2 * n1, days + 3 * n1, obs,
+                             obs + n1, obs + 2 * n1);
+        }
+        loss[p] = l;
+        free(days);
+    }
+}
+
+/* After a move, keep a pair of dimensions (j, j+1) ordered (the ramp's
+ * t1 <= t2): swap the positions when x_j > x_{j+1}. */
+void orc_pso_sort_pair(int P, int d, int j, double *x)
+{
+    for (int p = 0; p < P; ++p) {
+        double *r = x + (long)p * d;
+        if (r[j] > r[j + 1]) {
+            double t = r[j];
+            r[j] = r[j + 1];
+            r[j + 1] = t;
+        }
+    }
+}
+
+/* Whole PSO run of either model: as orc_pso_run, with the losses of
+ * orc_loss_batch_model and, for the ramp model, (t1, t2) ordered after
+ * every move. */
+void orc_pso_run_model(int model, int W, int spd, int seg_days, int K, double N, double R0,
+                       double D0, const double *obs, int kind, int P, const double *lo,
+                       const double *hi, double w, double c1, double c2, uint64_t seed,
+                       uint64_t stream, int iters, double *hist_f, int64_t *hist_idx,
+                       double *hist_margin, double *x, double *v, double *pbest_x,
+                       double *pbest_f, double *gbest_x, int nthreads)
+{
+    int d = K + 3;
+    double gbest_f;
+    int64_t gbest_idx;
+    double *f = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    orc_pso_init(P, d, lo, hi, seed, stream, x, v, pbest_x, pbest_f, gbest_x, &gbest_f,
+                 &gbest_idx);
+    if (model == 1) orc_pso_sort_pair(P, d, 2, x);
+    if (model == 1) orc_pso_sort_pair(P, d, 2, pbest_x);
+    for (int it = 0; it < iters; ++it) {
+        double margin;
+        orc_loss_batch_model(model, W, spd, seg_days, K, N, R0, D0, P, x, obs, kind, f,
+                             nthreads);
+        orc_pso_bests(P, d, f, x, pbest_x, pbest_f, gbest_x, &gbest_f, &gbest_idx, &margin);
+        if (hist_f) hist_f[it] = gbest_f;
+        if (hist_idx) hist_idx[it] = gbest_idx;
+        if (hist_margin) hist_margin[it] = margin;
+        if (it < iters - 1) {
+            orc_pso_move(P, d, (uint64_t)it, w, c1, c2, lo, hi, seed, stream, pbest_x,
+                         gbest_x, x, v);
+            if (model == 1) orc_pso_sort_pair(P, d, 2, x);
+        }
+    }
+    free(f);
+}

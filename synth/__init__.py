@@ -19,6 +19,12 @@ Workloads (names follow the calibration setups they model):
   c4  65536 parameter vectors on a 365-day window at dt = 0.05 (gradients)
   c5  52 weekly-shifted 42-day windows of a 414-day series with regime
       changes, 16 restarts x 4096 x 300, then refinement and a 14-day forecast
+  paper  the paper's own timing case (Sec. 3.3): one 92-day window (93 daily
+      observations of I, R and D), forward Euler at one step per day with the
+      ramp of eq. (beta), cost F_IRD^MXSE, 10000 particles, coefficients
+      0.5/0.5/0.5, 100 iterations, box of the paper's second run
+  rep  the repetition study (Sec. 4.2): one 36-day window of the same series
+      (tau = 35) fitted 1000 times with independent Philox streams
 """
 from __future__ import annotations
 
@@ -54,6 +60,8 @@ class Fit:
     n_part: int
     stream: int                   # Philox key word 1 of this fit
     truth: Optional[np.ndarray] = None
+    obs3: Optional[np.ndarray] = None  # I, R, D observations (3 (W+1) values)
+    model: str = "rk4"                 # or "euler_ramp"
 
     @property
     def d(self):
@@ -165,6 +173,19 @@ def c5_regimes(days=414):
     return beta
 
 
+def paper_truth():
+    """Ramp parameters (beta1, beta2, t1, t2, gamma, mu, I0) of the paper
+    workload and its window-start R and D: a wave that plateaus, then
+    declines after a ramp between days 10 and 25 (R_eff from about 1.08
+    to 0.45), starting from 3e5 active cases."""
+    return np.array([0.12, 0.05, 10.0, 25.0, 0.1, 0.0025, 3.0e5]), 2.2e6, 5.5e4
+
+
+def noisy_level(x, rng):
+    """Observed level series (active cases): Poisson noise per day."""
+    return rng.poisson(np.maximum(np.asarray(x, dtype=np.float64), 0.0)).astype(np.float64)
+
+
 # ------------------------------------------------------------ loading
 def _load(name):
     path = os.path.join(SERIES_DIR, name + ".npz")
@@ -237,3 +258,36 @@ def c5(restarts=16, n_part=4096, iters=300, windows=None):
             fits.append(Fit(W=42, spd=10, seg_days=14, K=3, N=POLAND_N, R0=R0, D0=D0,
                             lo=lo, hi=hi, y=y, n_part=n_part, stream=16 * w + r))
     return Workload("c5", fits, iters=iters, seed=5)
+
+
+def paper_box(W, I0):
+    """The paper's second search box (Sec. 3.1): beta1, beta2 in [0, 2],
+    0 <= t1 <= t2 <= W - 7, gamma in [0, 1], mu in [0, 0.1]; the window's
+    initial I is taken from the data (a fixed dimension)."""
+    lo = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0, I0])
+    hi = np.array([2.0, 2.0, W - 7.0, W - 7.0, 1.0, 0.1, I0])
+    return lo, hi
+
+
+def _paper_fit(W, t0, n_part, stream):
+    z = _load("paper")
+    obs = z["obs"]  # (3, 93): I, R, D
+    I0, R0, D0 = (float(v) for v in obs[:, t0])
+    lo, hi = paper_box(W, I0)
+    o3 = obs[:, t0:t0 + W + 1].reshape(-1).copy()
+    return Fit(W=W, spd=1, seg_days=1, K=4, N=POLAND_N, R0=R0, D0=D0, lo=lo, hi=hi,
+               y=obs[2, t0:t0 + W + 1].copy(), n_part=n_part, stream=stream,
+               truth=paper_truth()[0] if t0 == 0 else None, obs3=o3, model="euler_ramp")
+
+
+def paper(n_part=10000, iters=100):
+    """One 92-day window from the observed first day (Sec. 3.3 timing)."""
+    return Workload("paper", [_paper_fit(92, 0, n_part, 0)], iters=iters, seed=6,
+                    loss="ird_mxse", w=0.5, c1=0.5, c2=0.5)
+
+
+def rep(n_rep=1000, n_part=2048, iters=100, t0=20):
+    """n_rep independent fits of the 36-day window starting on day t0, each
+    with its own Philox stream (the repetition study of Sec. 4.2)."""
+    fits = [_paper_fit(35, t0, n_part, r) for r in range(n_rep)]
+    return Workload("rep", fits, iters=iters, seed=7, loss="ird_mxse", w=0.5, c1=0.5, c2=0.5)

@@ -61,7 +61,23 @@ def make_c5():
     return dict(y=y, truth=truth, beta=beta)
 
 
-MAKERS = dict(c1=make_c1, c2=make_c2, c3=make_c3, c4=make_c4, c5=make_c5)
+def make_paper():
+    """92 days of I, R, D from the ramp model (forward Euler, one step per
+    day) with count noise: Poisson on the active cases, negative-binomial
+    on the daily increments of R and D; day 0 is observed exactly."""
+    theta, R0, D0 = synth.paper_truth()
+    prob = oracle.Problem(W=92, spd=1, seg_days=1, K=4, N=synth.POLAND_N, R0=R0, D0=D0,
+                          model=1)
+    truth = oracle.integrate_model(prob, theta)
+    rng = np.random.default_rng(6)
+    yI = synth.noisy_level(truth[1], rng)
+    yI[0] = truth[1, 0]
+    yR = synth.noisy_cumulative(truth[2], "negbin", rng)
+    yD = synth.noisy_cumulative(truth[3], "negbin", rng)
+    return dict(obs=np.stack([yI, yR, yD]), truth=truth)
+
+
+MAKERS = dict(c1=make_c1, c2=make_c2, c3=make_c3, c4=make_c4, c5=make_c5, paper=make_paper)
 
 
 def main(names=None):
