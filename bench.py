@@ -138,6 +138,13 @@ def extras():
     print("# extras: gradients ...", file=sys.stderr, flush=True)
     wl4, th4 = synth.c4()
     res["c4_gradients_65536x7300steps"] = X.gradients_per_s(wl4, th4)
+    print("# extras: time to fit ...", file=sys.stderr, flush=True)
+    res["time_to_fit_c2"] = X.time_to_fit(synth.c2())
+    print("# extras: the paper's own timing case ...", file=sys.stderr, flush=True)
+    for dt in ("f64", "f32"):
+        res[f"paper_euler_ramp_ird_mxse_10000x92d_{dt}"] = X.paper_iteration(synth.paper(), dt)
+    print("# extras: repetition study ...", file=sys.stderr, flush=True)
+    res["rep_1000x2048x36d"] = X.repetition(synth.rep())
     print("# extras: rolling windows ...", file=sys.stderr, flush=True)
     z = synth.c5_series()
     res["c5_rolling_52x16x4096"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,

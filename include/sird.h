@@ -75,6 +75,27 @@ extern "C" {
 #define SIRD_LOSS_MXSE 2 /* max e_i^2                                      */
 #define SIRD_LOSS_MAE 3  /* (1/n) sum |e_i|                                */
 #define SIRD_LOSS_MAPE 4 /* (100/n) sum |e_i / g_i|                        */
+/* F_IRD of Sec. 3.1: the maximum over Y in {I, R, D} of a low-level cost
+ * on min-max normalised errors (y_i - yhat_i)/(max y - min y) (a flat
+ * observed series is normalised by 1); MAPE is not normalised.  Needs a
+ * batch with obs_series = 3. */
+#define SIRD_LOSS_IRD_MXSE 5
+#define SIRD_LOSS_IRD_MSE 6
+#define SIRD_LOSS_IRD_MAE 7
+#define SIRD_LOSS_IRD_MAPE 8
+
+/* ------------------------------------------------------------- models */
+#define SIRD_MODEL_RK4_SEGMENTS 0 /* RK4, beta piecewise constant on K
+                                     segments; theta = (beta_1..beta_K,
+                                     gamma, mu, I0)                      */
+#define SIRD_MODEL_EULER_RAMP 1   /* the paper's own scheme (Sec. 3.1, 3.3):
+                                     forward Euler with the ramp of
+                                     eq. (beta) evaluated at the start of
+                                     each step; K = 4 and theta = (beta1,
+                                     beta2, t1, t2, gamma, mu, I0), t in
+                                     days from the window start; the swarm
+                                     keeps t1 <= t2 by swapping after
+                                     every move (and at initialisation)  */
 
 /* ------------------------------------------------------------ descriptors */
 /* One calibration window (Sec. 3.1).  96 bytes, naturally aligned. */
@@ -84,13 +105,14 @@ typedef struct sird_problem {
     int32_t seg_days;      /* days per beta segment >= 1                   */
     int32_t n_seg;         /* K >= 1 beta segments; d = K + 3              */
     int32_t n_part;        /* particles (parameter vectors) >= 0           */
-    int32_t reserved;      /* must be 0                                    */
+    int32_t model;         /* SIRD_MODEL_*                                 */
     double N;              /* population > 0                               */
     double R0;             /* removed (recovered) at day 0, >= 0           */
     double D0;             /* deceased at day 0, >= 0                      */
     int64_t p_off;         /* first entry in particle-indexed arrays       */
     int64_t theta_off;     /* first double of the [d][n_part] block        */
-    int64_t obs_off;       /* first of the W+1 observations in obs         */
+    int64_t obs_off;       /* first of the obs_series x (W+1) observations
+                              (I, R, D when obs_series = 3; D when 1)     */
     int64_t traj_off;      /* first double of the [4][W+1][n_part] block   */
     int64_t box_off;       /* first of the d values in lo, hi, gbest_x     */
     uint64_t stream;       /* Philox key word 1 of this problem            */
@@ -125,7 +147,10 @@ typedef struct sird_batch {
     int32_t persistent;      /* 0: one wavefront per tile, tiles dispatched in
                                 table order; > 0: this many resident
                                 wavefronts pull tiles from a device counter   */
-    int32_t reserved;        /* must be 0                                      */
+    int32_t obs_series;      /* observed series per problem: 1 (D) or 3
+                                (I, R, D); set by sird_batch_plan          */
+    int32_t models;          /* bit m set when some problem has model m;
+                                set by sird_batch_plan                     */
 } sird_batch;
 
 /* Coefficients of the swarm, Sec. 3.3 (inertia, cognitive, social), the
@@ -175,12 +200,13 @@ const char *sird_last_error(void);
 
 /* Check a host problem table against the array lengths it indexes:
  * W, steps_per_day, seg_days, n_seg >= 1; n_part >= 0; N > 0; R0, D0 >= 0;
- * reserved == 0; each problem's blocks lie inside [0, len) of their arrays and
- * particle ranges inside [0, total_particles).  Pure host code.
- * Returns SIRD_OK or SIRD_EINVAL. */
+ * model is a SIRD_MODEL_* (the ramp model needs n_seg = 4); obs_series is
+ * 1 or 3; each problem's blocks lie inside [0, len) of their arrays
+ * (obs blocks are obs_series x (W+1) long) and particle ranges inside
+ * [0, total_particles).  Pure host code.  Returns SIRD_OK or SIRD_EINVAL. */
 int sird_problem_validate(const sird_problem *probs, int n_prob, int64_t total_particles,
                           int64_t theta_len, int64_t obs_len, int64_t traj_len,
-                          int64_t box_len);
+                          int64_t box_len, int obs_series);
 
 /* Build the tile table of a problem table: ceil(n_part/64) tiles per
  * problem, ordered by decreasing W*steps_per_day (longest first, so that
@@ -197,7 +223,7 @@ int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile *tiles_out,
  * caller set them.  Pure host code. */
 int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,
                     int64_t total_particles, int64_t theta_len, int64_t obs_len,
-                    int64_t traj_len, int64_t box_len, int n_tiles,
+                    int64_t traj_len, int64_t box_len, int obs_series, int n_tiles,
                     const sird_problem *probs_dev, const sird_tile *tiles_dev,
                     int32_t *sched_dev);
 
@@ -215,8 +241,9 @@ int sird_integrate(const sird_batch *batch, const double *theta, double *traj,
 /* Cost of Sec. 3.1 of every particle: RK4 over the window, the deceased
  * compartment sampled at every day and compared with the observations.
  *   theta: theta-shaped input.
- *   obs:   per problem W+1 observed cumulative deaths at obs_off.
- *   loss_kind: one of SIRD_LOSS_*.
+ *   obs:   per problem obs_series x (W+1) observations at obs_off: cumulative
+ *          deaths (obs_series = 1), or I, R and cumulative D (3).
+ *   loss_kind: one of SIRD_LOSS_* (the IRD kinds need obs_series = 3).
  *   loss:  output, particle-indexed.
  * Errors: SIRD_EINVAL (null pointer, bad kind or batch), SIRD_EHIP. */
 int sird_loss(const sird_batch *batch, const double *theta, const double *obs,
@@ -290,7 +317,8 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
  * The deceased-count costs are piecewise smooth: MXSE takes the first day
  * attaining the maximum, MAE/MAPE take sign(0) = 0.
  * Errors: SIRD_EINVAL, SIRD_ENOSPACE (workspace too small), SIRD_EHIP.
- * Only SIRD_F64 batches are supported (SIRD_EINVAL otherwise). */
+ * Only SIRD_F64 batches of the RK4 model with a D-only cost are supported
+ * (SIRD_EINVAL otherwise). */
 int sird_loss_backward(const sird_batch *batch, const double *theta, const double *obs,
                        int loss_kind, const double *grad_loss, double *grad_theta,
                        double *loss_out, int ckpt_interval, void *workspace,

@@ -20,7 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libsird.so")
 
 SIRD_OK, SIRD_EINVAL, SIRD_ENOSPACE, SIRD_EHIP = 0, -1, -2, -3
 SIRD_F64, SIRD_F32 = 0, 1
-LOSS = {"ssre": 0, "mse": 1, "mxse": 2, "mae": 3, "mape": 4}
+LOSS = {"ssre": 0, "mse": 1, "mxse": 2, "mae": 3, "mape": 4,
+        "ird_mxse": 5, "ird_mse": 6, "ird_mae": 7, "ird_mape": 8}
+MODEL = {"rk4": 0, "euler_ramp": 1}
 
 
 class SirdError(RuntimeError):
@@ -32,7 +34,7 @@ class SirdError(RuntimeError):
 # numpy mirror of struct sird_problem (96 bytes)
 PROBLEM_DTYPE = np.dtype([
     ("n_days", "<i4"), ("steps_per_day", "<i4"), ("seg_days", "<i4"), ("n_seg", "<i4"),
-    ("n_part", "<i4"), ("reserved", "<i4"),
+    ("n_part", "<i4"), ("model", "<i4"),
     ("N", "<f8"), ("R0", "<f8"), ("D0", "<f8"),
     ("p_off", "<i8"), ("theta_off", "<i8"), ("obs_off", "<i8"), ("traj_off", "<i8"),
     ("box_off", "<i8"), ("stream", "<u8"),
@@ -51,7 +53,8 @@ class sird_batch(ctypes.Structure):
         ("traj_len", ctypes.c_int64), ("box_len", ctypes.c_int64),
         ("probs", ctypes.c_void_p), ("tiles", ctypes.c_void_p), ("sched", ctypes.c_void_p),
         ("dtype", ctypes.c_int32), ("block", ctypes.c_int32),
-        ("persistent", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("persistent", ctypes.c_int32), ("obs_series", ctypes.c_int32),
+        ("models", ctypes.c_int32),
     ]
 
 
@@ -91,9 +94,9 @@ _I64 = ctypes.c_int64
 SIGNATURES = {
     "sird_status_string": (ctypes.c_char_p, [_I]),
     "sird_last_error": (ctypes.c_char_p, []),
-    "sird_problem_validate": (_I, [_P, _I, _I64, _I64, _I64, _I64, _I64]),
+    "sird_problem_validate": (_I, [_P, _I, _I64, _I64, _I64, _I64, _I64, _I]),
     "sird_plan_tiles": (_I, [_P, _I, _P, _I]),
-    "sird_batch_plan": (_I, [_B, _P, _I, _I64, _I64, _I64, _I64, _I64, _I, _P, _P, _P]),
+    "sird_batch_plan": (_I, [_B, _P, _I, _I64, _I64, _I64, _I64, _I64, _I, _I, _P, _P, _P]),
     "sird_integrate": (_I, [_B, _P, _P, _P]),
     "sird_loss": (_I, [_B, _P, _P, _I, _P, _P]),
     "pso_init": (_I, [_B, _PP, _PS, _P]),

@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import LOSS, SIRD_F32, SIRD_F64, check, lib, ptr, stream_handle
+from ._lib import LOSS, MODEL, SIRD_F32, SIRD_F64, check, lib, ptr, stream_handle
 
 
 def _kind(kind):
@@ -28,12 +28,22 @@ def _kind(kind):
 
 
 class ProblemSpec:
-    """One calibration window.  theta = (beta_1..beta_K, gamma, mu, I0)."""
+    """One calibration window.  model "rk4": theta = (beta_1..beta_K, gamma,
+    mu, I0) with beta piecewise constant on K segments of seg_days;
+    model "euler_ramp" (K = 4): theta = (beta1, beta2, t1, t2, gamma, mu,
+    I0), forward Euler with the ramp of eq. (beta)."""
 
-    def __init__(self, W, spd, seg_days, K, N, R0=0.0, D0=0.0, n_part=0, stream=0):
+    def __init__(self, W, spd, seg_days, K, N, R0=0.0, D0=0.0, n_part=0, stream=0,
+                 model="rk4"):
         self.W, self.spd, self.seg_days, self.K = int(W), int(spd), int(seg_days), int(K)
         self.N, self.R0, self.D0 = float(N), float(R0), float(D0)
         self.n_part, self.stream = int(n_part), int(stream)
+        self.model = MODEL[model] if isinstance(model, str) else int(model)
+
+    def with_particles(self, n_part, W=None):
+        """Same window (or one of W days) with n_part parameter vectors."""
+        return ProblemSpec(self.W if W is None else W, self.spd, self.seg_days, self.K, self.N,
+                           self.R0, self.D0, n_part, self.stream, self.model)
 
     @property
     def d(self):
@@ -46,24 +56,27 @@ class ProblemSpec:
     @classmethod
     def from_fit(cls, f, n_part=None):
         return cls(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0,
-                   f.n_part if n_part is None else n_part, f.stream)
+                   f.n_part if n_part is None else n_part, f.stream,
+                   getattr(f, "model", "rk4"))
 
 
 class Batch:
-    """A planned batch of problems resident on one device."""
+    """A planned batch of problems resident on one device.  obs_series = 3
+    lays out I, R and D observations per problem (the F_IRD costs)."""
 
     def __init__(self, specs: Sequence[ProblemSpec], dtype="f64", block=0, persistent=0,
-                 with_traj=False, device="cuda"):
+                 with_traj=False, device="cuda", obs_series=1):
         specs = list(specs)
         n = len(specs)
+        self.obs_series = int(obs_series)
         tab = np.zeros(n, dtype=_lib.PROBLEM_DTYPE)
         p_off = theta_off = obs_off = traj_off = box_off = 0
         for r, s in enumerate(specs):
-            tab[r] = (s.W, s.spd, s.seg_days, s.K, s.n_part, 0, s.N, s.R0, s.D0,
+            tab[r] = (s.W, s.spd, s.seg_days, s.K, s.n_part, s.model, s.N, s.R0, s.D0,
                       p_off, theta_off, obs_off, traj_off if with_traj else 0, box_off, s.stream)
             p_off += s.n_part
             theta_off += s.d * s.n_part
-            obs_off += s.W + 1
+            obs_off += self.obs_series * (s.W + 1)
             if with_traj:
                 traj_off += 4 * (s.W + 1) * s.n_part
             box_off += s.d
@@ -88,9 +101,9 @@ class Batch:
         b.dtype = SIRD_F32 if dtype in ("f32", SIRD_F32) else SIRD_F64
         b.block = int(block)
         b.persistent = int(persistent)
-        b.reserved = 0
         check(lib().sird_batch_plan(ctypes.byref(b), tab.ctypes.data, n, p_off, theta_off,
-                                    obs_off, traj_off, box_off, nt, ptr(self.probs_dev),
+                                    obs_off, traj_off, box_off, self.obs_series, nt,
+                                    ptr(self.probs_dev),
                                     ptr(self.tiles_dev), ptr(self.sched_dev)),
               "sird_batch_plan")
         self.c = b
@@ -133,12 +146,14 @@ class Batch:
         return res
 
     def pack_obs(self, per_problem: Sequence[np.ndarray]) -> torch.Tensor:
+        """Per problem obs_series x (W+1) values: D, or I, R, D concatenated."""
         out = np.zeros(self.obs_len)
         for s, row, y in zip(self.specs, self.table, per_problem):
-            y = np.asarray(y, dtype=np.float64)
-            assert y.shape == (s.W + 1,)
+            y = np.asarray(y, dtype=np.float64).reshape(-1)
+            n = self.obs_series * (s.W + 1)
+            assert y.shape == (n,), (y.shape, n)
             o = int(row["obs_off"])
-            out[o:o + s.W + 1] = y
+            out[o:o + n] = y
         return torch.from_numpy(out).to(self.device)
 
     def pack_box(self, per_problem: Sequence[np.ndarray]) -> torch.Tensor:

@@ -49,6 +49,7 @@ struct BwdArgs {
     int64_t P;  // slot stride of the workspace (total particles)
     int n_tiles;
     int kind;
+    int obs_series;  // 1 or 3; the deceased counts are the last series
     int s;          // checkpoint interval in steps
     int n_ck_max;   // checkpoints per particle
     int lds_stride;
@@ -175,7 +176,8 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     const int day_base = sc_base + 2 * a.s;
 
     {
-        const double *y = a.obs + P.obs_off;
+        // deceased counts: the last of the obs_series blocks of W+1 values
+        const double *y = a.obs + P.obs_off + (size_t)(a.obs_series - 1) * (W + 1);
         for (int i = lane; i <= W; i += kWave) {
             const double yi = y[i];
             ly[i] = yi;
@@ -365,7 +367,9 @@ extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
     if (batch->dtype != SIRD_F64)
         return fail(SIRD_EINVAL, "sird_loss_backward: only SIRD_F64 batches are supported");
     if (loss_kind < SIRD_LOSS_SSRE || loss_kind > SIRD_LOSS_MAPE)
-        return fail(SIRD_EINVAL, "sird_loss_backward: unknown loss_kind");
+        return fail(SIRD_EINVAL, "sird_loss_backward: loss_kind must be a deceased-count cost");
+    if (batch->models != 1 << SIRD_MODEL_RK4_SEGMENTS)
+        return fail(SIRD_EINVAL, "sird_loss_backward: only the RK4 segment model is supported");
     if (ckpt_interval < 0) return fail(SIRD_EINVAL, "sird_loss_backward: ckpt_interval < 0");
     if (batch->obs_len < 1)
         return fail(SIRD_EINVAL, "sird_loss_backward: batch planned without obs");
@@ -386,6 +390,7 @@ extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
     a.P = batch->total_particles;
     a.n_tiles = batch->n_tiles;
     a.kind = loss_kind;
+    a.obs_series = batch->obs_series;
     a.s = s;
     a.n_ck_max = (int)((batch->max_steps + s - 1) / s);
     a.lds_stride = 2 * (batch->max_days + 1);

@@ -146,6 +146,67 @@ __device__ __forceinline__ StepConst<R> step_const(double gamma, double mu, int 
     return k;
 }
 
+// ------------------------------------------------ Euler with the ramp of eq. (beta)
+// The paper's own scheme (Sec. 3.1, 3.3): forward Euler, beta evaluated at
+// the start of every step from the ramp beta1 -> beta2 over [t1, t2) (t in
+// days from the window start), y+ = y + h f(t, y).  Per particle the
+// constants beta1/N, beta2/N and the slope/N are formed once; a step costs
+// the ramp (two compares, one fma, two selects) and 2 mul + 4 fma.  The ramp
+// is evaluated in double for either state type: which side of t1 and t2 a
+// step falls on must not depend on rounding t1, t2 to float.
+template <typename R>
+struct RampConst {
+    double b1N, b2N, slopeN;  // beta1/N, beta2/N, (beta2 - beta1)/(t2 - t1)/N
+    double t1, t2;
+    R lam, h, hg, hmu;        // gamma + mu, step, h gamma, h mu
+};
+
+template <typename R>
+__device__ __forceinline__ RampConst<R> ramp_const(double b1, double b2, double t1, double t2,
+                                                   double gamma, double mu, double N, int spd)
+{
+    const double h = 1.0 / (double)spd;
+    RampConst<R> c;
+    c.b1N = b1 / N;
+    c.b2N = b2 / N;
+    c.slopeN = (b2 - b1) / (t2 - t1) / N;  // unused when t1 >= t2
+    c.t1 = t1;
+    c.t2 = t2;
+    c.lam = (R)(gamma + mu);
+    c.h = (R)h;
+    c.hg = (R)(h * gamma);
+    c.hmu = (R)(h * mu);
+    return c;
+}
+
+// beta(t)/N of eq. (beta).
+template <typename R>
+__device__ __forceinline__ double ramp_bN(const RampConst<R> &c, double t)
+{
+    const double mid = fma(c.slopeN, t - c.t1, c.b1N);
+    return (t < c.t1) ? c.b1N : ((t < c.t2) ? mid : c.b2N);
+}
+
+template <typename R, bool WITH_R>
+__device__ __forceinline__ void euler_ramp_step(SirdState<R> &y, const RampConst<R> &c, double t)
+{
+    const R bN = (R)ramp_bN(c, t);
+    const R I = y.I;
+    const R p = bN * y.S * I;
+    const R q = fma(-c.lam, I, p);
+    if constexpr (sizeof(R) == 8) {
+        y.S = fma(-c.h, p, y.S);
+        if (WITH_R) y.Rr = fma(c.hg, I, y.Rr);
+        y.D = fma(c.hmu, I, y.D);
+        y.I = fma(c.h, q, I);
+    } else {
+        kahan_add(y.S, y.eS, -(c.h * p));
+        if (WITH_R) kahan_add(y.Rr, y.eR, c.hg * I);
+        kahan_add(y.D, y.eD, c.hmu * I);
+        kahan_add(y.I, y.eI, c.h * q);
+    }
+}
+
 // ------------------------------------------------------------ costs (3.1)
 // One day's contribution of the deceased-count cost; y the observation,
 // w = 1/max(y, 1), i the day index (SSRE skips day 0).
@@ -182,6 +243,55 @@ __device__ __forceinline__ double cost_finish(int kind, double acc, int W)
     if (kind == SIRD_LOSS_MSE || kind == SIRD_LOSS_MAE) return acc / n;
     if (kind == SIRD_LOSS_MAPE) return 100.0 * acc / n;
     return acc;
+}
+
+// F_IRD (Sec. 3.1): per series c in {I, R, D} a low-level cost of the
+// errors (y - yhat) w, where w = 1/(max y - min y) over the window (1 for a
+// flat series) for MXSE, MSE, MAE and w = 1/max(y, 1) for MAPE; the loss is
+// the largest of the three (NaN if any is NaN).  row holds one day's
+// (y_I, y_R, y_D, w_I, w_R, w_D); low is SIRD_LOSS_MXSE/MSE/MAE/MAPE.
+__device__ __forceinline__ void ird_accum(int low, double acc[3], const double yhat[3],
+                                          const double *row, int i)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double e = (row[c] - yhat[c]) * row[3 + c];
+        if (low == SIRD_LOSS_MXSE) {
+            const double sq = e * e;
+            if (i == 0 || sq > acc[c] || sq != sq) acc[c] = sq;  // a NaN sticks
+        } else if (low == SIRD_LOSS_MSE) {
+            acc[c] = fma(e, e, acc[c]);
+        } else {
+            acc[c] += fabs(e);
+        }
+    }
+}
+
+__device__ __forceinline__ double ird_finish(int low, const double acc[3], int W)
+{
+    const double n = (double)(W + 1);
+    double F = -INFINITY;
+    bool nan = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = acc[c];
+        if (low == SIRD_LOSS_MSE || low == SIRD_LOSS_MAE) v = v / n;
+        if (low == SIRD_LOSS_MAPE) v = 100.0 * v / n;
+        nan |= v != v;
+        F = v > F ? v : F;
+    }
+    return nan ? NAN : F;
+}
+
+// Low-level cost of an F_IRD kind.
+__device__ __forceinline__ int ird_low(int kind)
+{
+    switch (kind) {
+    case SIRD_LOSS_IRD_MXSE: return SIRD_LOSS_MXSE;
+    case SIRD_LOSS_IRD_MSE: return SIRD_LOSS_MSE;
+    case SIRD_LOSS_IRD_MAE: return SIRD_LOSS_MAE;
+    default: return SIRD_LOSS_MAPE;
+    }
 }
 
 // --------------------------------------------------------- Philox4x64-10
@@ -245,8 +355,22 @@ struct PsoMove {
 // library is built without contraction):
 //   t = w v; t = t + (c1 r1)(pb - x); t = t + (c2 r2)(g - x);
 //   v = t;   x = min(max(x + v, lo), hi).
+// For the ramp model the positions of t1 and t2 (dimensions 2, 3) are then
+// swapped when t1 > t2, so that every particle describes a ramp.
 __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_problem &P,
                                                   int pl, uint64_t it);
+
+// Ramp model: keep t1 <= t2 (dimensions 2 and 3) of a theta-shaped array.
+__device__ __forceinline__ void ramp_order(double *x, const sird_problem &P, int pl)
+{
+    const size_t n = (size_t)P.n_part;
+    const size_t o2 = (size_t)P.theta_off + pl + 2 * n;
+    const double a = x[o2], b = x[o2 + n];
+    if (a > b) {
+        x[o2] = b;
+        x[o2 + n] = a;
+    }
+}
 
 // Personal best of local particle pl given its loss f (NaN counts as +inf):
 // strict improvement replaces pbest_f and copies x into pbest_x.
@@ -312,6 +436,7 @@ __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_p
             m.x[o] = xn;
         }
     }
+    if (P.model == SIRD_MODEL_EULER_RAMP) ramp_order(m.x, P, pl);
 }
 
 // Index of this wavefront's tile in a launch of one wavefront per tile,

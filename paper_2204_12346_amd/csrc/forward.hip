@@ -1,14 +1,21 @@
-// Forward integration kernels: RK4 over the calibration window of every
-// particle, fused with the per-day cost (sird_loss) or writing the daily
-// trajectory (sird_integrate).
+// Forward integration kernels: the model of every particle over its
+// calibration window (RK4 with piecewise-constant beta, or the paper's
+// forward Euler with the ramp of eq. (beta)), fused with the per-day cost
+// (sird_loss, the swarm iteration) or writing the daily trajectory
+// (sird_integrate).
 //
 // Mapping: one particle per lane, one tile (64 particles of one problem) per
 // wavefront, so every loop bound is wavefront-uniform and lives in scalar
-// registers.  The whole state stays in VGPRs; per day the wavefront reads one
-// (y_i, 1/max(y_i,1)) pair that it staged in its own LDS slice at the start of
-// the tile.  Tiles are ordered longest-first; with persistent > 0 a fixed set
-// of resident wavefronts pulls tiles from a device counter instead of relying
-// on the dispatcher's order.
+// registers.  The whole state stays in VGPRs; per day the wavefront reads the
+// observations and weights that it staged in its own LDS slice at the start
+// of the tile: (y_i, 1/max(y_i,1)) for a deceased-count cost, or the six
+// values (y_I, y_R, y_D, w_I, w_R, w_D) of an F_IRD cost, whose min-max
+// ranges the wavefront reduces with cross-lane shuffles while staging.
+// Tiles are ordered longest-first; with persistent > 0 a fixed set of
+// resident wavefronts pulls tiles from a device counter instead of relying
+// on the dispatcher's order.  The kernel is specialised per model; a batch
+// that mixes models gets one launch per model, each skipping the other's
+// tiles.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -27,9 +34,10 @@ struct FwdArgs {
     double *loss;
     double *traj;
     int n_tiles;
-    int n_waves;   // resident wavefronts of a persistent launch, else 0
+    int n_waves;     // resident wavefronts of a persistent launch, else 0
     int loss_kind;
-    int lds_stride;  // doubles per wavefront slice: 2 * (max_days + 1)
+    int obs_series;  // 1 (D) or 3 (I, R, D)
+    int lds_stride;  // doubles per wavefront slice: 2 or 6 times (max_days + 1)
     // swarm fused into the integration (sird_pso_iterate): theta is the
     // swarm's x, loss its f; before integrating, a particle is moved with
     // counter iter[0] - 1 when do_move; after, its personal best is updated
@@ -50,27 +58,84 @@ __device__ __forceinline__ void store_day(double *o, size_t comp_stride, const S
     o[3 * comp_stride] = state_value(y.D, y.eD);
 }
 
-template <typename R, bool TRAJ, bool FUSED>
-__device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, double *ly,
-                                         double *lw)
+// Deceased-count costs: (y_i, 1/max(y_i, 1)) of the D series.
+__device__ __forceinline__ void stage_d(const FwdArgs &a, const sird_problem &P, int lane,
+                                        double *ly)
 {
+    const int W = P.n_days;
+    const double *y = a.obs + P.obs_off + (size_t)(a.obs_series - 1) * (W + 1);
+    double *lw = ly + a.lds_stride / 2;
+    for (int i = lane; i <= W; i += kWave) {
+        const double yi = y[i];
+        ly[i] = yi;
+        lw[i] = 1.0 / fmax(yi, 1.0);
+    }
+}
+
+// F_IRD: per day (y_I, y_R, y_D, w_I, w_R, w_D); w = 1/range of the series
+// (1 for a flat one) or 1/max(y, 1) for MAPE.
+__device__ __forceinline__ void stage_ird(const FwdArgs &a, const sird_problem &P, int lane,
+                                          double *ly, int low)
+{
+    const int W = P.n_days;
+    const double *y = a.obs + P.obs_off;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = INFINITY;
+        hi[c] = -INFINITY;
+    }
+    for (int i = lane; i <= W; i += kWave) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = y[(size_t)c * (W + 1) + i];
+            ly[6 * i + c] = v;
+            lo[c] = fmin(lo[c], v);
+            hi[c] = fmax(hi[c], v);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+            hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+        }
+    }
+    double inv_range[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double r = hi[c] - lo[c];
+        inv_range[c] = 1.0 / (r > 0.0 ? r : 1.0);
+    }
+    for (int i = lane; i <= W; i += kWave) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            ly[6 * i + 3 + c] =
+                low == SIRD_LOSS_MAPE ? 1.0 / fmax(ly[6 * i + c], 1.0) : inv_range[c];
+    }
+}
+
+template <typename R, bool TRAJ, bool FUSED, int MODEL, bool IRD>
+__device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, double *ly)
+{
+    constexpr bool WITH_R = TRAJ || IRD;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
-    const int W = P.n_days, spd = P.steps_per_day, seg = P.seg_days, K = P.n_seg;
+    if (P.model != MODEL) return;  // wavefront-uniform; the other launch has it
+    const int W = P.n_days, spd = P.steps_per_day, K = P.n_seg;
     const int n = P.n_part;
     const int pl = tl.p0 + lane;
     const bool active = pl < n;
     const int pc = active ? pl : n - 1;  // idle lanes integrate a valid column
     const size_t ld = (size_t)n;
     const double *th = a.theta + P.theta_off + pc;
+    const int low = IRD ? ird_low(a.loss_kind) : a.loss_kind;
 
     if (!TRAJ) {
-        const double *y = a.obs + P.obs_off;
-        for (int i = lane; i <= W; i += kWave) {
-            const double yi = y[i];
-            ly[i] = yi;
-            lw[i] = 1.0 / fmax(yi, 1.0);
-        }
+        if (IRD)
+            stage_ird(a, P, lane, ly, low);
+        else
+            stage_d(a, P, lane, ly);
         wave_sync();
     }
     if (FUSED && a.do_move && active) pso_move_particle(a.mv, P, pl, a.iter[0] - 1);
@@ -79,7 +144,6 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     const double mu = th[(size_t)(K + 1) * ld];
     const double I0 = th[(size_t)(K + 2) * ld];
     const double N = P.N;
-    StepConst<R> sc = step_const<R>(gamma, mu, spd);
 
     SirdState<R> y;
     y.S = (R)(N - I0 - P.R0 - P.D0);
@@ -89,59 +153,77 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     y.s = R(0);
     y.eS = y.eI = y.eR = y.eD = R(0);
 
-    double acc = 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
     double *tr = nullptr;
     const size_t comp_stride = (size_t)(W + 1) * ld;
-    if (TRAJ) {
-        tr = a.traj + P.traj_off + pc;
-        if (active) store_day(tr, comp_stride, y);
-    } else {
-        cost_accum(a.loss_kind, acc, state_value(y.D, y.eD), ly[0], lw[0], 0);
-    }
+    const double *lw = ly + a.lds_stride / 2;
+    if (TRAJ) tr = a.traj + P.traj_off + pc;
+    // the state after day i: stored, or added to the cost
+    auto emit = [&](int i) {
+        if (TRAJ) {
+            if (active) store_day(tr + (size_t)i * ld, comp_stride, y);
+        } else if (IRD) {
+            const double yh[3] = {state_value(y.I, y.eI), state_value(y.Rr, y.eR),
+                                  state_value(y.D, y.eD)};
+            ird_accum(low, acc, yh, ly + 6 * i, i);
+        } else {
+            cost_accum(low, acc[0], state_value(y.D, y.eD), ly[i], lw[i], i);
+        }
+    };
+    emit(0);
 
-    int day = 0;
-    double beta_next = th[0];
-    for (int k = 0; k < K; ++k) {
-        const double beta_k = beta_next;
-        if (k + 1 < K) beta_next = th[(size_t)(k + 1) * ld];  // prefetch
-        const int dend = (k == K - 1) ? W : min(W, (k + 1) * seg);
-        if (day >= dend) continue;
-        set_beta(sc, beta_k, N);
-        for (; day < dend; ++day) {
-            rescale(y, sc);
+    if constexpr (MODEL == SIRD_MODEL_RK4_SEGMENTS) {
+        StepConst<R> sc = step_const<R>(gamma, mu, spd);
+        const int seg = P.seg_days;
+        int day = 0;
+        double beta_next = th[0];
+        for (int k = 0; k < K; ++k) {
+            const double beta_k = beta_next;
+            if (k + 1 < K) beta_next = th[(size_t)(k + 1) * ld];  // prefetch
+            const int dend = (k == K - 1) ? W : min(W, (k + 1) * seg);
+            if (day >= dend) continue;
+            set_beta(sc, beta_k, N);
+            for (; day < dend; ++day) {
+                rescale(y, sc);
 #pragma unroll 2
-            for (int s = 0; s < spd; ++s) rk4_step<R, TRAJ>(y, sc);
-            const int i = day + 1;
-            if (TRAJ) {
-                if (active) store_day(tr + (size_t)i * ld, comp_stride, y);
-            } else {
-                cost_accum(a.loss_kind, acc, state_value(y.D, y.eD), ly[i], lw[i], i);
+                for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R>(y, sc);
+                emit(day + 1);
             }
+        }
+    } else {
+        const RampConst<R> rc =
+            ramp_const<R>(th[0], th[ld], th[2 * ld], th[3 * ld], gamma, mu, N, spd);
+        const double h = 1.0 / (double)spd;
+        int64_t step = 0;
+        for (int day = 0; day < W; ++day) {
+            // the ramp is evaluated at the start of each step, t = step h
+            for (int s = 0; s < spd; ++s, ++step)
+                euler_ramp_step<R, WITH_R>(y, rc, (double)step * h);
+            emit(day + 1);
         }
     }
     if (!TRAJ && active) {
-        const double L = cost_finish(a.loss_kind, acc, W);
+        const double L = IRD ? ird_finish(low, acc, W) : cost_finish(low, acc[0], W);
         a.loss[P.p_off + pl] = L;
         if (FUSED) pso_pbest_particle(L, P, pl, a.pbest_f, a.pbest_x, a.mv.x);
     }
     if (!TRAJ) wave_sync();  // LDS slice reads done before it is restaged
 }
 
-template <typename R, bool TRAJ, bool FUSED>
+template <typename R, bool TRAJ, bool FUSED, int MODEL, bool IRD>
 __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
 {
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     double *ly = lds + (size_t)wave * a.lds_stride;
-    double *lw = ly + a.lds_stride / 2;
     if (a.n_waves > 0) {
         for (;;) {
             int t = 0;
             if (lane == 0) t = atomicAdd(&a.sched[0], 1);
             t = wave_uniform(t);
             if (t >= a.n_tiles) break;
-            fwd_tile<R, TRAJ, FUSED>(a, t, lane, ly, lw);
+            fwd_tile<R, TRAJ, FUSED, MODEL, IRD>(a, t, lane, ly);
         }
         // The last wavefront out resets the counters for the next launch.
         if (lane == 0) {
@@ -154,16 +236,30 @@ __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
         }
     } else {
         const int t = wave_tile_index();
-        if (t < a.n_tiles) fwd_tile<R, TRAJ, FUSED>(a, t, lane, ly, lw);
+        if (t < a.n_tiles) fwd_tile<R, TRAJ, FUSED, MODEL, IRD>(a, t, lane, ly);
     }
 }
 
-template <typename R, bool TRAJ, bool FUSED = false>
+template <typename R, bool TRAJ, bool FUSED, bool IRD>
+static int launch_model(const sird_batch *b, const FwdArgs &a, int model, int grid, int block,
+                        size_t lds, hipStream_t s)
+{
+    if (model == SIRD_MODEL_RK4_SEGMENTS)
+        hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED, SIRD_MODEL_RK4_SEGMENTS, IRD>),
+                           dim3(grid), dim3(block), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED, SIRD_MODEL_EULER_RAMP, IRD>),
+                           dim3(grid), dim3(block), lds, s, a);
+    return 0;
+}
+
+template <typename R, bool TRAJ, bool FUSED = false, bool IRD = false>
 static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const char *who)
 {
     const int block = integ_block(b);
     const int wpb = block / kWave;
-    a.lds_stride = 2 * (b->max_days + 1);
+    a.obs_series = b->obs_series;
+    a.lds_stride = (IRD ? 6 : 2) * (b->max_days + 1);
     const size_t lds = TRAJ ? 0 : (size_t)wpb * a.lds_stride * sizeof(double);
     if (lds > 65536)
         return fail(SIRD_EINVAL, std::string(who) +
@@ -177,8 +273,20 @@ static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const c
         a.n_waves = 0;
     }
     if (grid == 0) return SIRD_OK;
-    hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED>), dim3(grid), dim3(block), lds, s, a);
-    return hip_status(hipGetLastError(), who);
+    for (int m = 0; m < 2; ++m) {
+        if (!(b->models & (1 << m))) continue;
+        launch_model<R, TRAJ, FUSED, IRD>(b, a, m, grid, block, lds, s);
+        const int st = hip_status(hipGetLastError(), who);
+        if (st) return st;
+    }
+    return SIRD_OK;
+}
+
+template <typename R, bool FUSED>
+static int launch_cost(const sird_batch *b, const FwdArgs &a, hipStream_t s, const char *who)
+{
+    if (is_ird(a.loss_kind)) return launch_forward<R, false, FUSED, true>(b, a, s, who);
+    return launch_forward<R, false, FUSED, false>(b, a, s, who);
 }
 
 int forward_loss(const sird_batch *b, const double *theta, const double *obs, int kind,
@@ -193,8 +301,8 @@ int forward_loss(const sird_batch *b, const double *theta, const double *obs, in
     a.loss = loss;
     a.n_tiles = b->n_tiles;
     a.loss_kind = kind;
-    if (b->dtype == SIRD_F32) return launch_forward<float, false>(b, a, s, "sird_loss");
-    return launch_forward<double, false>(b, a, s, "sird_loss");
+    if (b->dtype == SIRD_F32) return launch_cost<float, false>(b, a, s, "sird_loss");
+    return launch_cost<double, false>(b, a, s, "sird_loss");
 }
 
 int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
@@ -214,8 +322,8 @@ int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
     a.pbest_x = st->pbest_x;
     a.iter = st->iter;
     a.do_move = move ? 1 : 0;
-    if (b->dtype == SIRD_F32) return launch_forward<float, false, true>(b, a, s, "sird_pso_iterate");
-    return launch_forward<double, false, true>(b, a, s, "sird_pso_iterate");
+    if (b->dtype == SIRD_F32) return launch_cost<float, true>(b, a, s, "sird_pso_iterate");
+    return launch_cost<double, true>(b, a, s, "sird_pso_iterate");
 }
 
 }  // namespace sird
@@ -228,8 +336,8 @@ extern "C" int sird_loss(const sird_batch *batch, const double *theta, const dou
     int st = check_batch(batch, "sird_loss");
     if (st) return st;
     if (!theta || !obs || !loss) return fail(SIRD_EINVAL, "sird_loss: NULL array");
-    if (loss_kind < SIRD_LOSS_SSRE || loss_kind > SIRD_LOSS_MAPE)
-        return fail(SIRD_EINVAL, "sird_loss: unknown loss_kind");
+    st = check_kind(batch, loss_kind, "sird_loss");
+    if (st) return st;
     if (batch->obs_len < 1) return fail(SIRD_EINVAL, "sird_loss: batch planned without obs");
     return forward_loss(batch, theta, obs, loss_kind, loss, (hipStream_t)stream);
 }

@@ -46,7 +46,20 @@ int check_batch(const sird_batch *b, const char *who)
     if (b->persistent < 0) return fail(SIRD_EINVAL, w + ": persistent < 0");
     if (b->persistent > 0 && !b->sched)
         return fail(SIRD_EINVAL, w + ": persistent launch needs sched counters");
-    if (b->reserved != 0) return fail(SIRD_EINVAL, w + ": reserved must be 0");
+    if (b->obs_series != 1 && b->obs_series != 3)
+        return fail(SIRD_EINVAL, w + ": obs_series must be 1 or 3");
+    if (b->models < 1 || b->models > 3)
+        return fail(SIRD_EINVAL, w + ": models must be a non-empty mask of SIRD_MODEL_*");
+    return SIRD_OK;
+}
+
+int check_kind(const sird_batch *b, int kind, const char *who)
+{
+    const std::string w(who);
+    if (kind < SIRD_LOSS_SSRE || kind > SIRD_LOSS_IRD_MAPE)
+        return fail(SIRD_EINVAL, w + ": unknown loss_kind");
+    if (is_ird(kind) && b->obs_series != 3)
+        return fail(SIRD_EINVAL, w + ": the F_IRD costs need a batch with obs_series = 3");
     return SIRD_OK;
 }
 
@@ -76,10 +89,13 @@ static bool range_ok(int64_t off, int64_t count, int64_t len)
 
 extern "C" int sird_problem_validate(const sird_problem *probs, int n_prob,
                                      int64_t total_particles, int64_t theta_len,
-                                     int64_t obs_len, int64_t traj_len, int64_t box_len)
+                                     int64_t obs_len, int64_t traj_len, int64_t box_len,
+                                     int obs_series)
 {
     if (!probs) return fail(SIRD_EINVAL, "sird_problem_validate: probs is NULL");
     if (n_prob < 1) return fail(SIRD_EINVAL, "sird_problem_validate: n_prob < 1");
+    if (obs_series != 1 && obs_series != 3)
+        return fail(SIRD_EINVAL, "sird_problem_validate: obs_series must be 1 or 3");
     for (int r = 0; r < n_prob; ++r) {
         const sird_problem &p = probs[r];
         char buf[160];
@@ -92,7 +108,10 @@ extern "C" int sird_problem_validate(const sird_problem *probs, int n_prob,
         if (p.seg_days < 1) return bad("seg_days < 1");
         if (p.n_seg < 1) return bad("n_seg < 1");
         if (p.n_part < 0) return bad("n_part < 0");
-        if (p.reserved != 0) return bad("reserved != 0");
+        if (p.model != SIRD_MODEL_RK4_SEGMENTS && p.model != SIRD_MODEL_EULER_RAMP)
+            return bad("unknown model");
+        if (p.model == SIRD_MODEL_EULER_RAMP && p.n_seg != 4)
+            return bad("the ramp model needs n_seg = 4");
         if ((int64_t)p.n_days * p.steps_per_day > (int64_t)1 << 30)
             return bad("n_days * steps_per_day too large");
         if (p.n_days > (1 << 20) || p.n_seg > (1 << 20)) return bad("n_days or n_seg too large");
@@ -102,7 +121,7 @@ extern "C" int sird_problem_validate(const sird_problem *probs, int n_prob,
         const int64_t d = (int64_t)p.n_seg + 3;
         if (!range_ok(p.p_off, p.n_part, total_particles)) return bad("particle range");
         if (!range_ok(p.theta_off, d * p.n_part, theta_len)) return bad("theta block");
-        if (obs_len > 0 && !range_ok(p.obs_off, (int64_t)p.n_days + 1, obs_len))
+        if (obs_len > 0 && !range_ok(p.obs_off, obs_series * ((int64_t)p.n_days + 1), obs_len))
             return bad("obs block");
         if (traj_len > 0 && !range_ok(p.traj_off, 4 * ((int64_t)p.n_days + 1) * p.n_part, traj_len))
             return bad("traj block");
@@ -133,19 +152,20 @@ extern "C" int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile 
 
 extern "C" int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,
                                int64_t total_particles, int64_t theta_len, int64_t obs_len,
-                               int64_t traj_len, int64_t box_len, int n_tiles,
+                               int64_t traj_len, int64_t box_len, int obs_series, int n_tiles,
                                const sird_problem *probs_dev, const sird_tile *tiles_dev,
                                int32_t *sched_dev)
 {
     if (!batch) return fail(SIRD_EINVAL, "sird_batch_plan: batch is NULL");
     int st = sird_problem_validate(probs_host, n_prob, total_particles, theta_len, obs_len,
-                                   traj_len, box_len);
+                                   traj_len, box_len, obs_series);
     if (st != SIRD_OK) return st;
     int64_t tiles = 0;
-    int max_days = 0, max_d = 0;
+    int max_days = 0, max_d = 0, models = 0;
     int64_t max_steps = 0;
     for (int r = 0; r < n_prob; ++r) {
         const sird_problem &p = probs_host[r];
+        models |= 1 << p.model;
         tiles += (p.n_part + kTileParticles - 1) / kTileParticles;
         max_days = std::max(max_days, p.n_days);
         max_d = std::max(max_d, p.n_seg + 3);
@@ -168,5 +188,7 @@ extern "C" int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host
     batch->probs = probs_dev;
     batch->tiles = tiles_dev;
     batch->sched = sched_dev;
+    batch->obs_series = obs_series;
+    batch->models = models;
     return SIRD_OK;
 }

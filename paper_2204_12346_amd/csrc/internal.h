@@ -20,6 +20,12 @@ int fail(int status, const std::string &msg);
 // itself is checked by sird_batch_plan).
 int check_batch(const sird_batch *b, const char *who);
 
+// A cost kind this batch can evaluate: SIRD_LOSS_* in [0, 8]; the F_IRD
+// kinds need three observed series.
+int check_kind(const sird_batch *b, int kind, const char *who);
+
+inline bool is_ird(int kind) { return kind >= SIRD_LOSS_IRD_MXSE; }
+
 // Map a HIP status after enqueueing to SIRD_OK / SIRD_EHIP.
 int hip_status(hipError_t e, const char *who);
 

@@ -95,6 +95,10 @@ __global__ void __launch_bounds__(256) k_pso_init(PsoArgs a)
             a.st.pbest_x[o] = x;
         }
     }
+    if (P.model == SIRD_MODEL_EULER_RAMP) {
+        ramp_order(a.st.x, P, pl);
+        ramp_order(a.st.pbest_x, P, pl);
+    }
     a.st.pbest_f[P.p_off + pl] = INFINITY;
 }
 
@@ -320,8 +324,8 @@ int check_iterate(const sird_batch *b, const pso_params *p, const pso_state *st,
     if (!st->f) return fail(SIRD_EINVAL, w + ": state->f is NULL");
     if (!obs) return fail(SIRD_EINVAL, w + ": obs is NULL");
     if (b->obs_len < 1) return fail(SIRD_EINVAL, w + ": batch planned without obs");
-    if (kind < SIRD_LOSS_SSRE || kind > SIRD_LOSS_MAPE)
-        return fail(SIRD_EINVAL, w + ": unknown loss_kind");
+    r = check_kind(b, kind, who);
+    if (r) return r;
     if (n_iters < 0) return fail(SIRD_EINVAL, w + ": n_iters < 0");
     return SIRD_OK;
 }

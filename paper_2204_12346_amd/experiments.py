@@ -1,6 +1,8 @@
 """Measured workloads beside the main throughput line: single-fit swarm
 throughput, gradients per second, time-to-fit of plain swarm vs swarm +
-adjoint refinement, and the rolling-window fit + 14-day forecast.
+adjoint refinement, the rolling-window fit + 14-day forecast, the paper's
+own timing case (one swarm iteration of its Euler + ramp model under
+F_IRD^MXSE) and its repetition study.
 
 Each function builds its batch from ``synth`` inputs, times device work with
 HIP events (or wall clock where the protocol is wall time) and returns a
@@ -8,6 +10,7 @@ plain dict for the benchmark's JSON line.
 """
 from __future__ import annotations
 
+import sys
 import time
 from typing import Dict, List
 
@@ -23,16 +26,32 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def swarm_throughput(wl, dtype="f64", iters=200, warmup=10, graph_chunk=10,
-                     launch=None) -> Dict:
-    """particle-RK4-steps/s of whole swarm iterations of one workload,
-    replayed as HIP graphs of graph_chunk iterations."""
+def _setup(wl, dtype="f64", launch=None, hist_len=0):
+    """Batch, swarm parameters, swarm and observations of a workload; the
+    F_IRD costs get the three observed series."""
+    three = wl.loss.startswith("ird")
     specs = [ProblemSpec.from_fit(f) for f in wl.fits]
-    b = Batch(specs, dtype=dtype, **(launch or {}))
+    b = Batch(specs, dtype=dtype, obs_series=3 if three else 1, **(launch or {}))
     params = PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
                        wl.c2, wl.seed)
-    sw = Swarm(b)
-    obs = b.pack_obs([f.y for f in wl.fits])
+    sw = Swarm(b, hist_len=hist_len)
+    obs = b.pack_obs([f.obs3 if three else f.y for f in wl.fits])
+    return b, params, sw, obs
+
+
+def r2(y, yhat):
+    """Coefficient of determination 1 - sum (y - yhat)^2 / sum (y - mean y)^2
+    (the goodness-of-fit measure the paper reports on D)."""
+    y = np.asarray(y, dtype=np.float64)
+    yhat = np.asarray(yhat, dtype=np.float64)
+    return float(1.0 - np.sum((y - yhat) ** 2) / np.sum((y - y.mean()) ** 2))
+
+
+def swarm_throughput(wl, dtype="f64", iters=200, warmup=10, graph_chunk=10,
+                     launch=None) -> Dict:
+    """particle-steps/s of whole swarm iterations of one workload, replayed
+    as HIP graphs of graph_chunk iterations."""
+    b, params, sw, obs = _setup(wl, dtype, launch)
     pso_init(b, params, sw)
     sird_pso_iterate(b, params, sw, obs, wl.loss, warmup)
     g = Graph(b, params, sw, obs, wl.loss, iters_per_launch=graph_chunk)
@@ -84,18 +103,19 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
 
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
-                k=32, refine_steps=600, lr=1e-2, rel=1e-6, chunk=50,
+                k=64, refine_steps=1000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6), chunk=50,
                 method="lbfgs") -> Dict:
     """Wall time from pso_init until the loss is within rel of the best
     loss any run of either arm found (L_best), per seed:
       plain arm: swarm iterations (graph chunks of `chunk`), capped;
       adjoint arm: I' swarm iterations, then refinement of the top-k
       personal bests with gradients from the discrete adjoint: projected
-      L-BFGS rounds (method "lbfgs") or projected Adam steps ("adam").
-    Every run's trajectory of (elapsed s, best loss) is recorded first, the
-    threshold applied afterwards, so both arms are judged against the same
-    L_best.  Reports the median over seeds for each arm (None if not
-    reached)."""
+      L-BFGS rounds (method "lbfgs", I0 in log coordinates) or projected
+      Adam steps ("adam").
+    Every run's trajectory of (elapsed s, best loss) is recorded first and
+    the thresholds applied afterwards, so both arms are judged against the
+    same L_best.  Reports per threshold the median over seeds (None when
+    the median run does not reach it) and the final losses."""
     f = wl.fits[0]
     spec = ProblemSpec.from_fit(f)
 
@@ -105,7 +125,7 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
         obs = b.pack_obs([f.y])
         return b, params, obs
 
-    plain: Dict[int, List] = {}
+    curves: Dict[str, Dict[int, List]] = {"plain": {}}
     for seed in seeds:
         b, params, obs = new(seed)
         sw = Swarm(b)
@@ -119,9 +139,11 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
             best = sw.gbest_f[0].item()  # synchronises
             curve.append((time.perf_counter() - t0, best, (i + 1) * chunk))
         g.close()
-        plain[seed] = curve
-    adj: Dict = {}
+        curves["plain"][seed] = curve
+        _progress(f"time_to_fit plain seed {seed}: {curve[-1][0]:.2f} s, loss {curve[-1][1]:.9g}")
     for I1 in pso_first:
+        arm = f"adjoint_I{I1}"
+        curves[arm] = {}
         for seed in seeds:
             b, params, obs = new(seed)
             sw = Swarm(b)
@@ -134,37 +156,34 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
                 _adam_curve(b, sw, params, obs, wl.loss, k, refine_steps, lr, t0, curve)
             else:
                 _lbfgs_curve(b, sw, params, obs, wl.loss, k, refine_steps, t0, curve)
-            adj[(I1, seed)] = curve
-    L_best = min(min(c[1] for c in cur) for cur in list(plain.values()) + list(adj.values()))
-    thr = L_best * (1 + rel)
+            curves[arm][seed] = curve
+            _progress(f"time_to_fit {arm} seed {seed}: {curve[-1][0]:.2f} s, "
+                      f"loss {curve[-1][1]:.9g}")
+    L_best = min(min(c[1] for c in cur) for arm in curves.values() for cur in arm.values())
 
-    def reach(curve):
+    def reach(curve, thr):
         for t, l, it in curve:
             if l <= thr:
-                return t, it
-        return None, None
+                return t
+        return None
 
-    res = {"L_best": L_best, "threshold": thr, "rel": rel, "seeds": list(seeds),
+    res = {"L_best": L_best, "rels": list(rels), "seeds": list(seeds),
            "plain_cap_iterations": plain_cap, "refine": method,
-           "refine_steps_cap": refine_steps, "k": k}
+           "refine_steps_cap": refine_steps, "k": k, "pso_first": list(pso_first)}
     if method == "adam":
         res["lr"] = lr
-    pt = [reach(plain[s]) for s in seeds]
-    res["plain"] = {"times_s": [t for t, _ in pt], "iterations": [i for _, i in pt],
-                    "final_loss": [plain[s][-1][1] for s in seeds]}
-    res["plain"]["median_s"] = _median([t for t, _ in pt])
-    best_arm = None
-    for I1 in pso_first:
-        at = [reach(adj[(I1, s)]) for s in seeds]
-        m = _median([t for t, _ in at])
-        res[f"adjoint_I{I1}"] = {"times_s": [t for t, _ in at],
-                                 "refine_steps": [i for _, i in at],
-                                 "final_loss": [adj[(I1, s)][-1][1] for s in seeds],
-                                 "median_s": m}
-        if m is not None and (best_arm is None or m < res[best_arm]["median_s"]):
-            best_arm = f"adjoint_I{I1}"
-    res["best_adjoint_arm"] = best_arm
+    for arm, runs in curves.items():
+        entry = {"final_loss": [runs[s][-1][1] for s in seeds],
+                 "wall_s": [runs[s][-1][0] for s in seeds], "median_s": {}}
+        for rel in rels:
+            thr = L_best * (1 + rel)
+            entry["median_s"][f"{rel:g}"] = _median([reach(runs[s], thr) for s in seeds])
+        res[arm] = entry
     return res
+
+
+def _progress(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def _median(ts):
@@ -179,9 +198,8 @@ def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=2
     (elapsed s, best loss so far, Adam step) every check_every steps."""
     from .core import pso_topk, sird_adam_step, sird_gather
     idx = pso_topk(b, sw.pbest_f, k)
-    specs = [ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, k, s.stream)
-             for s in b.specs]
-    rb = Batch(specs, device=b.device)
+    specs = [s.with_particles(k) for s in b.specs]
+    rb = Batch(specs, device=b.device, obs_series=b.obs_series)
     theta = sird_gather(b, sw.pbest_x, params.lo, rb, idx, k)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
@@ -207,9 +225,8 @@ def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10)
     (elapsed s, best loss so far, round) every check_every rounds."""
     from .core import LbfgsState, pso_topk, sird_gather
     idx = pso_topk(b, sw.pbest_f, k)
-    specs = [ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, k, s.stream)
-             for s in b.specs]
-    rb = Batch(specs, device=b.device)
+    specs = [s.with_particles(k) for s in b.specs]
+    rb = Batch(specs, device=b.device, obs_series=b.obs_series)
     theta = sird_gather(b, sw.pbest_x, params.lo, rb, idx, k)
     st = LbfgsState(rb, theta)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, 0), 8), dtype=torch.uint8,
@@ -263,9 +280,8 @@ def rolling_forecast(wl, truth, restarts, iters=300, k_per_restart=2, refine_rou
         win_theta.append(th[pi])
         win_spec.append(specs[pi])
         starts.append(7 * w)
-    traj = fit.forecast([ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, 1, s.stream)
-                         for s in win_spec], [t[None, :] for t in win_theta], horizon,
-                        device=b.device)
+    traj = fit.forecast([s.with_particles(1) for s in win_spec],
+                        [t[None, :] for t in win_theta], horizon, device=b.device)
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
     e7, e14, einc = [], [], []
@@ -289,3 +305,77 @@ def rolling_forecast(wl, truth, restarts, iters=300, k_per_restart=2, refine_rou
             "particle_steps_per_s_swarm": b.particle_steps * iters / t_pso,
             "rel_err_cum_deaths_h7": q(e7), "rel_err_cum_deaths_h14": q(e14),
             "rel_err_14day_increment": q(einc)}
+
+
+def paper_iteration(wl, dtype="f64", reps=20, launch=None) -> Dict:
+    """The paper's timing protocol (Sec. 3.3): the mean and standard
+    deviation over reps of one swarm iteration (every particle's model over
+    the window, its F_IRD^MXSE cost, bests and move), each launched and
+    timed on its own; then a whole run of wl.iters iterations from pso_init
+    (wall clock) and the fit it reaches (loss, R^2 on D, I and R)."""
+    b, params, sw, obs = _setup(wl, dtype, launch, hist_len=wl.iters)
+    pso_init(b, params, sw)
+    sird_pso_iterate(b, params, sw, obs, wl.loss, 3)  # warm-up
+    ms = []
+    for _ in range(reps):
+        e0, e1 = _events()
+        e0.record()
+        sird_pso_iterate(b, params, sw, obs, wl.loss, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    # a whole run, eager
+    b, params, sw, obs = _setup(wl, dtype, launch, hist_len=wl.iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pso_init(b, params, sw)
+    sird_pso_iterate(b, params, sw, obs, wl.loss, wl.iters)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    f = wl.fits[0]
+    gx = b.unpack_box(sw.gbest_x)[0]
+    tr = fit.forecast([b.specs[0]], [gx[None, :]], 0, device=b.device)[0][0]
+    o = np.asarray(f.obs3).reshape(3, -1)
+    return {"particles": b.total_particles, "days": f.W, "steps_per_day": f.spd,
+            "dtype": dtype, "ms_per_iteration_mean": float(np.mean(ms)),
+            "ms_per_iteration_std": float(np.std(ms)), "reps": reps,
+            "particle_steps_per_s": b.particle_steps / (np.mean(ms) / 1e3),
+            "iterations": wl.iters, "seconds_run": t_run,
+            "final_loss": sw.gbest_f[0].item(), "r2_D": r2(o[2], tr[3]),
+            "r2_I": r2(o[0], tr[1]), "r2_R": r2(o[1], tr[2])}
+
+
+def repetition(wl, horizon=21, launch=None) -> Dict:
+    """The repetition study (Sec. 4.2): every fit of the workload is the
+    same window with its own Philox stream, all in one batch; returns the
+    time, the spread of the fitted parameters (5/50/95 % quantiles), the
+    spread of the losses and the 50/90/95 % bands of the horizon-day
+    extension of D, I and R at the window end + horizon."""
+    b, params, sw, obs = _setup(wl, "f64", launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pso_init(b, params, sw)
+    sird_pso_iterate(b, params, sw, obs, wl.loss, wl.iters)
+    torch.cuda.synchronize()
+    t_pso = time.perf_counter() - t0
+    th = np.stack(b.unpack_box(sw.gbest_x))
+    L = sw.gbest_f.cpu().numpy()
+    trajs = fit.forecast(b.specs, [t[None, :] for t in th], horizon, device=b.device)
+    end = np.stack([t[0, :, -1] for t in trajs])  # (n_rep, 4) at W + horizon
+    t_all = time.perf_counter() - t0
+
+    def q(v, ps=(5, 50, 95)):
+        return {p: float(np.quantile(v, p / 100)) for p in ps}
+
+    names = ["beta1", "beta2", "t1", "t2", "gamma", "mu"]
+    bands = {}
+    for c, name in ((1, "I"), (2, "R"), (3, "D")):
+        bands[name] = {f"{lvl}%": [float(np.quantile(end[:, c], (1 - lvl / 100) / 2)),
+                                   float(np.quantile(end[:, c], 1 - (1 - lvl / 100) / 2))]
+                       for lvl in (50, 90, 95)}
+    return {"fits": b.n_prob, "particles_per_fit": b.specs[0].n_part,
+            "iterations": wl.iters, "particle_steps": b.particle_steps * wl.iters,
+            "seconds_swarm": t_pso, "seconds_total": t_all,
+            "particle_steps_per_s": b.particle_steps * wl.iters / t_pso,
+            "loss": q(L), "params": {n: q(th[:, j]) for j, n in enumerate(names)},
+            f"extension_day_{horizon}_bands": bands}

@@ -56,9 +56,8 @@ def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre",
     discrete adjoint.  Stops after max_steps, or when no refined particle's
     loss changed by more than rel_tol (relative) over check_every steps."""
     idx = pso_topk(batch, swarm.pbest_f, k)
-    specs = [ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, k, s.stream)
-             for s in batch.specs]
-    rb = Batch(specs, dtype="f64", device=batch.device)
+    specs = [s.with_particles(k) for s in batch.specs]
+    rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
@@ -113,9 +112,8 @@ def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre"
     Stops after max_rounds, or when no vector's loss changed by more than
     rel_tol (relative) over check_every rounds."""
     idx = pso_topk(batch, swarm.pbest_f, k)
-    specs = [ProblemSpec(s.W, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0, k, s.stream)
-             for s in batch.specs]
-    rb = Batch(specs, dtype="f64", device=batch.device)
+    specs = [s.with_particles(k) for s in batch.specs]
+    rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
     st = LbfgsState(rb, theta, m=m)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
@@ -153,11 +151,11 @@ def best_per_problem(batch: Batch, theta: torch.Tensor, loss: torch.Tensor):
 def forecast(specs: Sequence[ProblemSpec], thetas: Sequence[np.ndarray], horizon_days: int,
              device="cuda") -> List[np.ndarray]:
     """Integrate every parameter vector over its window plus horizon_days
-    (the last beta segment continues past the window, as the paper extends
-    a window with its last transmission rate); returns per problem an array
-    (n, 4, W + horizon + 1) of S, I, R, D."""
-    ext = [ProblemSpec(s.W + horizon_days, s.spd, s.seg_days, s.K, s.N, s.R0, s.D0,
-                       len(th), s.stream) for s, th in zip(specs, thetas)]
+    (the last beta segment continues past the window, and the ramp model
+    stays at beta2, as the paper extends a window with its last
+    transmission rate); returns per problem an array (n, 4, W + horizon + 1)
+    of S, I, R, D."""
+    ext = [s.with_particles(len(th), W=s.W + horizon_days) for s, th in zip(specs, thetas)]
     # segments are anchored at the window start; the last one extends
     b = Batch(ext, with_traj=True, device=device)
     traj = sird_integrate(b, b.pack_theta([np.asarray(t) for t in thetas]))

@@ -107,3 +107,28 @@ def make_batch(fits, n_parts=None, **kw):
     specs = [S.ProblemSpec.from_fit(f, None if n_parts is None else n_parts[i])
              for i, f in enumerate(fits)]
     return S.Batch(specs, **kw)
+
+
+def oracle_problem_model(f):
+    """Oracle problem of a fit of either model."""
+    return oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0,
+                          model=1 if getattr(f, "model", "rk4") == "euler_ramp" else 0)
+
+
+def kappa_ird(kind, traj, obs3):
+    """Sensitivity bound of an F_IRD cost: the largest over I, R, D of the
+    low-level cost's kappa on the normalised values (MAPE unnormalised)."""
+    low = kind[len("ird_"):]
+    W1 = traj.shape[1]
+    y = np.asarray(obs3, dtype=np.float64).reshape(3, W1)
+    worst = 0.0
+    for c in range(3):
+        yh, yo = traj[c + 1], y[c]
+        if low == "mape":
+            k = kappa("mape", yh, yo)
+        else:
+            r = yo.max() - yo.min()
+            r = r if r > 0 else 1.0
+            k = kappa(low, yh / r, yo / r)
+        worst = max(worst, k)
+    return worst

@@ -104,13 +104,14 @@ def test_status_strings_and_last_error(L):
     (dict(n_days=0), b"n_days"), (dict(steps_per_day=0), b"steps_per_day"),
     (dict(seg_days=0), b"seg_days"), (dict(n_seg=0), b"n_seg"), (dict(n_part=-1), b"n_part"),
     (dict(N=0.0), b"N must"), (dict(N=float("nan")), b"N must"), (dict(R0=-1.0), b"R0"),
-    (dict(reserved=3), b"reserved"), (dict(p_off=1), b"particle"),
+    (dict(model=3), b"unknown model"), (dict(model=1), b"ramp model needs n_seg = 4"),
+    (dict(p_off=1), b"particle"),
     (dict(theta_off=1), b"theta"), (dict(obs_off=1), b"obs"), (dict(box_off=1), b"box"),
 ])
 def test_validate_rejects(L, bad, msg):
     lib = L.lib()
     t = _table([_good(**bad)])
-    st = lib.sird_problem_validate(t.ctypes.data, 1, 70, 5 * 70, 11, 0, 5)
+    st = lib.sird_problem_validate(t.ctypes.data, 1, 70, 5 * 70, 11, 0, 5, 1)
     assert st == L.SIRD_EINVAL
     assert msg in lib.sird_last_error()
 
@@ -118,10 +119,21 @@ def test_validate_rejects(L, bad, msg):
 def test_validate_accepts_and_checks_lengths(L):
     lib = L.lib()
     t = _table([_good(), _good(p_off=70, theta_off=350, obs_off=11, box_off=5, n_part=0)])
-    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 350, 22, 0, 10) == 0
-    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 349, 22, 0, 10) == L.SIRD_EINVAL
-    assert lib.sird_problem_validate(None, 2, 70, 350, 22, 0, 10) == L.SIRD_EINVAL
-    assert lib.sird_problem_validate(t.ctypes.data, 0, 70, 350, 22, 0, 10) == L.SIRD_EINVAL
+    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 350, 22, 0, 10, 1) == 0
+    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 349, 22, 0, 10, 1) == L.SIRD_EINVAL
+    assert lib.sird_problem_validate(None, 2, 70, 350, 22, 0, 10, 1) == L.SIRD_EINVAL
+    assert lib.sird_problem_validate(t.ctypes.data, 0, 70, 350, 22, 0, 10, 1) == L.SIRD_EINVAL
+    for series in (0, 2, 4):
+        assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 350, 22, 0, 10,
+                                         series) == L.SIRD_EINVAL
+    # three observed series: blocks of 3 (W+1) values
+    assert lib.sird_problem_validate(t.ctypes.data, 2, 70, 350, 22, 0, 10, 3) == L.SIRD_EINVAL
+    t3 = _table([_good(), _good(p_off=70, theta_off=350, obs_off=33, box_off=5, n_part=0)])
+    assert lib.sird_problem_validate(t3.ctypes.data, 2, 70, 350, 66, 0, 10, 3) == 0
+    assert lib.sird_problem_validate(t3.ctypes.data, 2, 70, 350, 65, 0, 10, 3) == L.SIRD_EINVAL
+    # the ramp model with its four parameters of beta
+    tr = _table([_good(model=1, n_seg=4)])
+    assert lib.sird_problem_validate(tr.ctypes.data, 1, 70, 7 * 70, 11, 0, 7, 1) == 0
 
 
 def test_plan_tiles_longest_first(L):
@@ -165,11 +177,22 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     assert b.c.max_days == 45 and b.c.max_d == 7 and b.c.max_steps == 300
     assert b.total_particles == 165 and b.theta_len == 6 * 100 + 7 * 65
     assert b.obs_len == 31 + 13 + 46 and b.box_len == 6 + 5 + 7
+    assert b.c.obs_series == 1 and b.c.models == 1
     lib = L.lib()
     dummy = torch.zeros(8, dtype=torch.float64)
-    for kind in (-1, 5):
+    for kind in (-1, 9):
         assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), kind,
                              dummy.data_ptr(), None) == L.SIRD_EINVAL
+        assert b"unknown loss_kind" in lib.sird_last_error()
+    # the F_IRD kinds need the I and R series too
+    for kind in (5, 8):
+        assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), kind,
+                             dummy.data_ptr(), None) == L.SIRD_EINVAL
+        assert b"obs_series = 3" in lib.sird_last_error()
+    b.c.models = 0
+    assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
+                         dummy.data_ptr(), None) == L.SIRD_EINVAL
+    b.c.models = 1
     b.c.dtype = 7
     assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
                          dummy.data_ptr(), None) == L.SIRD_EINVAL
@@ -185,6 +208,29 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
                                 dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 16, None)
     assert st == L.SIRD_ENOSPACE
+
+
+def test_ramp_model_and_three_series_batches_on_host(L):
+    import torch
+    from paper_2204_12346_amd import core
+    specs = [core.ProblemSpec(92, 1, 1, 4, 3.8e7, n_part=100, model="euler_ramp"),
+             core.ProblemSpec(30, 4, 10, 3, 1e6, n_part=10)]
+    b = core.Batch(specs, device="cpu", obs_series=3)
+    assert b.c.models == 3 and b.c.obs_series == 3
+    assert b.obs_len == 3 * 93 + 3 * 31
+    y = [np.arange(3 * 93.0), np.arange(3 * 31.0)]
+    o = b.pack_obs(y).numpy()
+    assert o[3 * 93] == 0.0 and o[-1] == 3 * 31 - 1
+    lib = L.lib()
+    dummy = torch.zeros(8, dtype=torch.float64)
+    # gradients exist for the RK4 model with a deceased-count cost only
+    st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
+                                dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 1 << 40, None)
+    assert st == L.SIRD_EINVAL and b"RK4 segment model" in lib.sird_last_error()
+    b.c.models = 1
+    st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 5, None,
+                                dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 1 << 40, None)
+    assert st == L.SIRD_EINVAL and b"deceased-count" in lib.sird_last_error()
 
 
 def test_layout_round_trip_on_host():
