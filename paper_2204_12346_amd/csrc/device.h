@@ -208,8 +208,58 @@ __device__ __forceinline__ void euler_ramp_step(SirdState<R> &y, const RampConst
 }
 
 // ------------------------------------------------------------ costs (3.1)
-// One day's contribution of the deceased-count cost; y the observation,
-// w = 1/max(y, 1), i the day index (SSRE skips day 0).
+// Every cost of Sec. 3.1 is one of three accumulations of weighted daily
+// errors e_i = (y_i - yhat_i) w_i over days 0..W, then a scale:
+//   SSRE   sum e^2, w = 1/max(y,1) (0 on day 0)        scale 1
+//   MSE    sum e^2, w = 1                              scale 1/n
+//   MXSE   max e^2, w = 1                              scale 1
+//   MAE    sum |e|, w = 1                              scale 1/n
+//   MAPE   sum |e|, w = 1/max(y,1)                     scale 100/n
+// (n = W + 1).  The F_IRD costs apply the same per series c in {I, R, D}
+// with w = 1/(max y_c - min y_c) over the window (1 for a flat series), or
+// 1/max(y,1) for MAPE, and take the largest of the three (NaN if any is
+// NaN).  The forward kernels are specialised on the accumulation, so the
+// daily update carries no branch on the cost kind.
+enum CostAcc { kAccSq = 0, kAccAbs = 1, kAccMax = 2 };
+
+// Per-kind constants of a cost, chosen on the host.
+struct CostPlan {
+    int series;     // 1 (D) or 3 (I, R, D)
+    int acc;        // CostAcc
+    int w_rel;      // weights 1/max(y, 1) instead of 1 (or 1/range)
+    int skip0;      // weight 0 on day 0 (SSRE)
+    double scale;   // 1 or 100
+    int per_day;    // divide by n = W + 1
+};
+
+// Starting value of an accumulator: the max starts below any square so
+// that day 0 always replaces it.
+template <int ACC>
+__device__ __forceinline__ double acc_init()
+{
+    return ACC == kAccMax ? -INFINITY : 0.0;
+}
+
+template <int ACC>
+__device__ __forceinline__ void acc_day(double &acc, double e)
+{
+    if constexpr (ACC == kAccSq) {
+        acc = fma(e, e, acc);
+    } else if constexpr (ACC == kAccAbs) {
+        acc += fabs(e);
+    } else {
+        const double sq = e * e;
+        acc = (sq > acc || sq != sq) ? sq : acc;  // a NaN sticks
+    }
+}
+
+__device__ __forceinline__ double cost_value(const CostPlan &c, double acc, int W)
+{
+    return (c.scale * acc) / (c.per_day ? (double)(W + 1) : 1.0);
+}
+
+// One day's contribution of a deceased-count cost in the form the adjoint
+// differentiates; y the observation, w = 1/max(y, 1), i the day index.
 __device__ __forceinline__ void cost_accum(int kind, double &acc, double D, double y,
                                            double w, int i)
 {
@@ -243,55 +293,6 @@ __device__ __forceinline__ double cost_finish(int kind, double acc, int W)
     if (kind == SIRD_LOSS_MSE || kind == SIRD_LOSS_MAE) return acc / n;
     if (kind == SIRD_LOSS_MAPE) return 100.0 * acc / n;
     return acc;
-}
-
-// F_IRD (Sec. 3.1): per series c in {I, R, D} a low-level cost of the
-// errors (y - yhat) w, where w = 1/(max y - min y) over the window (1 for a
-// flat series) for MXSE, MSE, MAE and w = 1/max(y, 1) for MAPE; the loss is
-// the largest of the three (NaN if any is NaN).  row holds one day's
-// (y_I, y_R, y_D, w_I, w_R, w_D); low is SIRD_LOSS_MXSE/MSE/MAE/MAPE.
-__device__ __forceinline__ void ird_accum(int low, double acc[3], const double yhat[3],
-                                          const double *row, int i)
-{
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double e = (row[c] - yhat[c]) * row[3 + c];
-        if (low == SIRD_LOSS_MXSE) {
-            const double sq = e * e;
-            if (i == 0 || sq > acc[c] || sq != sq) acc[c] = sq;  // a NaN sticks
-        } else if (low == SIRD_LOSS_MSE) {
-            acc[c] = fma(e, e, acc[c]);
-        } else {
-            acc[c] += fabs(e);
-        }
-    }
-}
-
-__device__ __forceinline__ double ird_finish(int low, const double acc[3], int W)
-{
-    const double n = (double)(W + 1);
-    double F = -INFINITY;
-    bool nan = false;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double v = acc[c];
-        if (low == SIRD_LOSS_MSE || low == SIRD_LOSS_MAE) v = v / n;
-        if (low == SIRD_LOSS_MAPE) v = 100.0 * v / n;
-        nan |= v != v;
-        F = v > F ? v : F;
-    }
-    return nan ? NAN : F;
-}
-
-// Low-level cost of an F_IRD kind.
-__device__ __forceinline__ int ird_low(int kind)
-{
-    switch (kind) {
-    case SIRD_LOSS_IRD_MXSE: return SIRD_LOSS_MXSE;
-    case SIRD_LOSS_IRD_MSE: return SIRD_LOSS_MSE;
-    case SIRD_LOSS_IRD_MAE: return SIRD_LOSS_MAE;
-    default: return SIRD_LOSS_MAPE;
-    }
 }
 
 // --------------------------------------------------------- Philox4x64-10

@@ -35,9 +35,9 @@ struct FwdArgs {
     double *traj;
     int n_tiles;
     int n_waves;     // resident wavefronts of a persistent launch, else 0
-    int loss_kind;
     int obs_series;  // 1 (D) or 3 (I, R, D)
     int lds_stride;  // doubles per wavefront slice: 2 or 6 times (max_days + 1)
+    CostPlan cost;
     // swarm fused into the integration (sird_pso_iterate): theta is the
     // swarm's x, loss its f; before integrating, a particle is moved with
     // counter iter[0] - 1 when do_move; after, its personal best is updated
@@ -58,7 +58,8 @@ __device__ __forceinline__ void store_day(double *o, size_t comp_stride, const S
     o[3 * comp_stride] = state_value(y.D, y.eD);
 }
 
-// Deceased-count costs: (y_i, 1/max(y_i, 1)) of the D series.
+// Deceased-count costs: (y_i) and (w_i) of the D series, the last of the
+// obs_series blocks.
 __device__ __forceinline__ void stage_d(const FwdArgs &a, const sird_problem &P, int lane,
                                         double *ly)
 {
@@ -68,14 +69,15 @@ __device__ __forceinline__ void stage_d(const FwdArgs &a, const sird_problem &P,
     for (int i = lane; i <= W; i += kWave) {
         const double yi = y[i];
         ly[i] = yi;
-        lw[i] = 1.0 / fmax(yi, 1.0);
+        lw[i] = a.cost.w_rel ? 1.0 / fmax(yi, 1.0) : 1.0;
     }
 }
 
 // F_IRD: per day (y_I, y_R, y_D, w_I, w_R, w_D); w = 1/range of the series
-// (1 for a flat one) or 1/max(y, 1) for MAPE.
+// (1 for a flat one), or 1/max(y, 1) for MAPE.  The ranges are reduced
+// across the wavefront with shuffles.
 __device__ __forceinline__ void stage_ird(const FwdArgs &a, const sird_problem &P, int lane,
-                                          double *ly, int low)
+                                          double *ly)
 {
     const int W = P.n_days;
     const double *y = a.obs + P.obs_off;
@@ -110,15 +112,16 @@ __device__ __forceinline__ void stage_ird(const FwdArgs &a, const sird_problem &
     for (int i = lane; i <= W; i += kWave) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            ly[6 * i + 3 + c] =
-                low == SIRD_LOSS_MAPE ? 1.0 / fmax(ly[6 * i + c], 1.0) : inv_range[c];
+            ly[6 * i + 3 + c] = a.cost.w_rel ? 1.0 / fmax(ly[6 * i + c], 1.0) : inv_range[c];
     }
 }
 
-template <typename R, bool TRAJ, bool FUSED, int MODEL, bool IRD>
+// NS: observed series of the cost (1 or 3), 0 when writing trajectories;
+// ACC: the cost's accumulation (CostAcc).
+template <typename R, bool TRAJ, bool FUSED, int MODEL, int NS, int ACC>
 __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, double *ly)
 {
-    constexpr bool WITH_R = TRAJ || IRD;
+    constexpr bool WITH_R = TRAJ || NS == 3;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
     if (P.model != MODEL) return;  // wavefront-uniform; the other launch has it
@@ -129,11 +132,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     const int pc = active ? pl : n - 1;  // idle lanes integrate a valid column
     const size_t ld = (size_t)n;
     const double *th = a.theta + P.theta_off + pc;
-    const int low = IRD ? ird_low(a.loss_kind) : a.loss_kind;
 
     if (!TRAJ) {
-        if (IRD)
-            stage_ird(a, P, lane, ly, low);
+        if (NS == 3)
+            stage_ird(a, P, lane, ly);
         else
             stage_d(a, P, lane, ly);
         wave_sync();
@@ -153,24 +155,31 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     y.s = R(0);
     y.eS = y.eI = y.eR = y.eD = R(0);
 
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[3] = {acc_init<ACC>(), acc_init<ACC>(), acc_init<ACC>()};
     double *tr = nullptr;
     const size_t comp_stride = (size_t)(W + 1) * ld;
     const double *lw = ly + a.lds_stride / 2;
     if (TRAJ) tr = a.traj + P.traj_off + pc;
     // the state after day i: stored, or added to the cost
     auto emit = [&](int i) {
-        if (TRAJ) {
+        if constexpr (TRAJ) {
             if (active) store_day(tr + (size_t)i * ld, comp_stride, y);
-        } else if (IRD) {
-            const double yh[3] = {state_value(y.I, y.eI), state_value(y.Rr, y.eR),
-                                  state_value(y.D, y.eD)};
-            ird_accum(low, acc, yh, ly + 6 * i, i);
+        } else if constexpr (NS == 3) {
+            const double *row = ly + 6 * i;
+            acc_day<ACC>(acc[0], (row[0] - state_value(y.I, y.eI)) * row[3]);
+            acc_day<ACC>(acc[1], (row[1] - state_value(y.Rr, y.eR)) * row[4]);
+            acc_day<ACC>(acc[2], (row[2] - state_value(y.D, y.eD)) * row[5]);
         } else {
-            cost_accum(low, acc[0], state_value(y.D, y.eD), ly[i], lw[i], i);
+            acc_day<ACC>(acc[0], (ly[i] - state_value(y.D, y.eD)) * lw[i]);
         }
     };
-    emit(0);
+    if constexpr (NS == 1) {
+        // SSRE leaves out day 0
+        const double e0 = (ly[0] - state_value(y.D, y.eD)) * lw[0];
+        acc_day<ACC>(acc[0], a.cost.skip0 ? 0.0 : e0);
+    } else {
+        emit(0);
+    }
 
     if constexpr (MODEL == SIRD_MODEL_RK4_SEGMENTS) {
         StepConst<R> sc = step_const<R>(gamma, mu, spd);
@@ -203,14 +212,22 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         }
     }
     if (!TRAJ && active) {
-        const double L = IRD ? ird_finish(low, acc, W) : cost_finish(low, acc[0], W);
+        double L = cost_value(a.cost, acc[0], W);
+        if constexpr (NS == 3) {
+            // the largest of the three series, NaN if any is NaN
+            const double v1 = cost_value(a.cost, acc[1], W);
+            const double v2 = cost_value(a.cost, acc[2], W);
+            const bool nan = L != L || v1 != v1 || v2 != v2;
+            L = fmax(L, fmax(v1, v2));
+            if (nan) L = NAN;
+        }
         a.loss[P.p_off + pl] = L;
         if (FUSED) pso_pbest_particle(L, P, pl, a.pbest_f, a.pbest_x, a.mv.x);
     }
     if (!TRAJ) wave_sync();  // LDS slice reads done before it is restaged
 }
 
-template <typename R, bool TRAJ, bool FUSED, int MODEL, bool IRD>
+template <typename R, bool TRAJ, bool FUSED, int MODEL, int NS, int ACC>
 __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
 {
     extern __shared__ double lds[];
@@ -223,7 +240,7 @@ __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
             if (lane == 0) t = atomicAdd(&a.sched[0], 1);
             t = wave_uniform(t);
             if (t >= a.n_tiles) break;
-            fwd_tile<R, TRAJ, FUSED, MODEL, IRD>(a, t, lane, ly);
+            fwd_tile<R, TRAJ, FUSED, MODEL, NS, ACC>(a, t, lane, ly);
         }
         // The last wavefront out resets the counters for the next launch.
         if (lane == 0) {
@@ -236,30 +253,33 @@ __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
         }
     } else {
         const int t = wave_tile_index();
-        if (t < a.n_tiles) fwd_tile<R, TRAJ, FUSED, MODEL, IRD>(a, t, lane, ly);
+        if (t < a.n_tiles) fwd_tile<R, TRAJ, FUSED, MODEL, NS, ACC>(a, t, lane, ly);
     }
 }
 
-template <typename R, bool TRAJ, bool FUSED, bool IRD>
-static int launch_model(const sird_batch *b, const FwdArgs &a, int model, int grid, int block,
-                        size_t lds, hipStream_t s)
+// The constants of each cost kind (Sec. 3.1).
+static CostPlan cost_plan(int kind)
 {
-    if (model == SIRD_MODEL_RK4_SEGMENTS)
-        hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED, SIRD_MODEL_RK4_SEGMENTS, IRD>),
-                           dim3(grid), dim3(block), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED, SIRD_MODEL_EULER_RAMP, IRD>),
-                           dim3(grid), dim3(block), lds, s, a);
-    return 0;
+    switch (kind) {
+    case SIRD_LOSS_SSRE: return {1, kAccSq, 1, 1, 1.0, 0};
+    case SIRD_LOSS_MSE: return {1, kAccSq, 0, 0, 1.0, 1};
+    case SIRD_LOSS_MXSE: return {1, kAccMax, 0, 0, 1.0, 0};
+    case SIRD_LOSS_MAE: return {1, kAccAbs, 0, 0, 1.0, 1};
+    case SIRD_LOSS_MAPE: return {1, kAccAbs, 1, 0, 100.0, 1};
+    case SIRD_LOSS_IRD_MXSE: return {3, kAccMax, 0, 0, 1.0, 0};
+    case SIRD_LOSS_IRD_MSE: return {3, kAccSq, 0, 0, 1.0, 1};
+    case SIRD_LOSS_IRD_MAE: return {3, kAccAbs, 0, 0, 1.0, 1};
+    default: return {3, kAccAbs, 1, 0, 100.0, 1};  // SIRD_LOSS_IRD_MAPE
+    }
 }
 
-template <typename R, bool TRAJ, bool FUSED = false, bool IRD = false>
+template <typename R, bool TRAJ, bool FUSED, int NS, int ACC>
 static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const char *who)
 {
     const int block = integ_block(b);
     const int wpb = block / kWave;
     a.obs_series = b->obs_series;
-    a.lds_stride = (IRD ? 6 : 2) * (b->max_days + 1);
+    a.lds_stride = (NS == 3 ? 6 : 2) * (b->max_days + 1);
     const size_t lds = TRAJ ? 0 : (size_t)wpb * a.lds_stride * sizeof(double);
     if (lds > 65536)
         return fail(SIRD_EINVAL, std::string(who) +
@@ -273,20 +293,39 @@ static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const c
         a.n_waves = 0;
     }
     if (grid == 0) return SIRD_OK;
-    for (int m = 0; m < 2; ++m) {
-        if (!(b->models & (1 << m))) continue;
-        launch_model<R, TRAJ, FUSED, IRD>(b, a, m, grid, block, lds, s);
+    if (b->models & (1 << SIRD_MODEL_RK4_SEGMENTS)) {
+        hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED, SIRD_MODEL_RK4_SEGMENTS, NS, ACC>),
+                           dim3(grid), dim3(block), lds, s, a);
+        const int st = hip_status(hipGetLastError(), who);
+        if (st) return st;
+    }
+    if (b->models & (1 << SIRD_MODEL_EULER_RAMP)) {
+        hipLaunchKernelGGL((k_forward<R, TRAJ, FUSED, SIRD_MODEL_EULER_RAMP, NS, ACC>),
+                           dim3(grid), dim3(block), lds, s, a);
         const int st = hip_status(hipGetLastError(), who);
         if (st) return st;
     }
     return SIRD_OK;
 }
 
+// Instantiation for the cost of kind: series and accumulation.
 template <typename R, bool FUSED>
-static int launch_cost(const sird_batch *b, const FwdArgs &a, hipStream_t s, const char *who)
+static int launch_cost(const sird_batch *b, FwdArgs a, int kind, hipStream_t s,
+                       const char *who)
 {
-    if (is_ird(a.loss_kind)) return launch_forward<R, false, FUSED, true>(b, a, s, who);
-    return launch_forward<R, false, FUSED, false>(b, a, s, who);
+    a.cost = cost_plan(kind);
+    const bool three = a.cost.series == 3;
+    switch (a.cost.acc) {
+    case kAccSq:
+        return three ? launch_forward<R, false, FUSED, 3, kAccSq>(b, a, s, who)
+                     : launch_forward<R, false, FUSED, 1, kAccSq>(b, a, s, who);
+    case kAccAbs:
+        return three ? launch_forward<R, false, FUSED, 3, kAccAbs>(b, a, s, who)
+                     : launch_forward<R, false, FUSED, 1, kAccAbs>(b, a, s, who);
+    default:
+        return three ? launch_forward<R, false, FUSED, 3, kAccMax>(b, a, s, who)
+                     : launch_forward<R, false, FUSED, 1, kAccMax>(b, a, s, who);
+    }
 }
 
 int forward_loss(const sird_batch *b, const double *theta, const double *obs, int kind,
@@ -300,9 +339,8 @@ int forward_loss(const sird_batch *b, const double *theta, const double *obs, in
     a.obs = obs;
     a.loss = loss;
     a.n_tiles = b->n_tiles;
-    a.loss_kind = kind;
-    if (b->dtype == SIRD_F32) return launch_cost<float, false>(b, a, s, "sird_loss");
-    return launch_cost<double, false>(b, a, s, "sird_loss");
+    if (b->dtype == SIRD_F32) return launch_cost<float, false>(b, a, kind, s, "sird_loss");
+    return launch_cost<double, false>(b, a, kind, s, "sird_loss");
 }
 
 int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
@@ -316,14 +354,13 @@ int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
     a.obs = obs;
     a.loss = st->f;
     a.n_tiles = b->n_tiles;
-    a.loss_kind = kind;
     a.mv = mv;
     a.pbest_f = st->pbest_f;
     a.pbest_x = st->pbest_x;
     a.iter = st->iter;
     a.do_move = move ? 1 : 0;
-    if (b->dtype == SIRD_F32) return launch_cost<float, true>(b, a, s, "sird_pso_iterate");
-    return launch_cost<double, true>(b, a, s, "sird_pso_iterate");
+    if (b->dtype == SIRD_F32) return launch_cost<float, true>(b, a, kind, s, "sird_pso_iterate");
+    return launch_cost<double, true>(b, a, kind, s, "sird_pso_iterate");
 }
 
 }  // namespace sird
@@ -358,6 +395,7 @@ extern "C" int sird_integrate(const sird_batch *batch, const double *theta, doub
     a.traj = traj;
     a.n_tiles = batch->n_tiles;
     hipStream_t s = (hipStream_t)stream;
-    if (batch->dtype == SIRD_F32) return launch_forward<float, true>(batch, a, s, "sird_integrate");
-    return launch_forward<double, true>(batch, a, s, "sird_integrate");
+    if (batch->dtype == SIRD_F32)
+        return launch_forward<float, true, false, 0, 0>(batch, a, s, "sird_integrate");
+    return launch_forward<double, true, false, 0, 0>(batch, a, s, "sird_integrate");
 }

@@ -175,3 +175,40 @@ def test_swarm_run_matches_oracle(graph_chunk):
     assert upto >= 10, f"oracle near-tie too early ({upto})"
     np.testing.assert_array_equal(sw.hist_idx.cpu().numpy()[:upto, 0], hidx[:upto])
     np.testing.assert_allclose(sw.hist_f.cpu().numpy()[:upto, 0], hf[:upto], rtol=1e-11)
+
+
+def test_repetition_batch_equals_single_fits():
+    """The repetition study's batch (one window, fits with their own Philox
+    streams) runs every fit exactly as a batch of that fit alone."""
+    wl = synth.rep(n_rep=6, n_part=100, iters=12)
+    fits = wl.fits
+    b = _batch(fits, [f.n_part for f in fits])
+    params = S.PsoParams(b, [f.lo for f in fits], [f.hi for f in fits], wl.w, wl.c1, wl.c2,
+                         wl.seed)
+    sw = S.Swarm(b, hist_len=wl.iters)
+    obs = b.pack_obs([f.obs3 for f in fits])
+    S.pso_init(b, params, sw)
+    S.sird_pso_iterate(b, params, sw, obs, wl.loss, wl.iters)
+    hist = sw.hist_f.cpu().numpy()
+    for r, f in enumerate(fits):
+        one = _batch([f], [f.n_part])
+        p1 = S.PsoParams(one, [f.lo], [f.hi], wl.w, wl.c1, wl.c2, wl.seed)
+        s1 = S.Swarm(one, hist_len=wl.iters)
+        S.pso_init(one, p1, s1)
+        S.sird_pso_iterate(one, p1, s1, one.pack_obs([f.obs3]), wl.loss, wl.iters)
+        assert np.array_equal(s1.hist_f.cpu().numpy()[:, 0], hist[:, r]), r
+        assert np.array_equal(one.unpack_box(s1.gbest_x)[0], b.unpack_box(sw.gbest_x)[r])
+    # different streams explore differently
+    assert len({tuple(h) for h in hist.T}) > 1
+
+
+def test_ramp_extension_stays_at_beta2():
+    from paper_2204_12346_amd import fit
+    f = synth.rep(n_rep=1).fits[0]
+    th = _thetas(f, 5, seed=4)
+    th[:, 2:4] = np.sort(np.minimum(th[:, 2:4], f.W - 7.0), axis=1)
+    spec = S.ProblemSpec.from_fit(f, 5)
+    out = fit.forecast([spec], [th], 21)[0]
+    prob = oracle.Problem(f.W + 21, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0, model=1)
+    for p in range(5):
+        assert_traj_close(out[p], oracle.integrate_model(prob, th[p]), TOL64, f"particle {p}")
