@@ -106,9 +106,21 @@ def cpu_baseline(wl, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one thread: 64 particles of each problem in turn
+    w1 = 0
+    t1 = time.perf_counter()
+    for f, th, prob in zip(wl.fits, thetas, probs):
+        oracle.loss_batch(prob, th[:64], f.y, wl.loss, nthreads=1)
+        w1 += min(64, f.n_part) * f.T
+        if time.perf_counter() - t1 > budget_s / 5:
+            break
+    dt1 = time.perf_counter() - t1
     return {"value": work / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"whole-batch loss evaluations of the same workload, stopped after "
-                      f"{budget_s:.0f} s: {work:.3e} particle-steps in {dt:.1f} s"}
+                      f"{budget_s:.0f} s: {work:.3e} particle-steps in {dt:.1f} s",
+            "single_thread_value": w1 / dt1,
+            "single_thread_sample": f"64 particles of each problem in turn, one thread: "
+                                    f"{w1:.3e} particle-steps in {dt1:.1f} s"}
 
 
 def copy_probe(mib):
@@ -144,7 +156,7 @@ def extras():
     for dt in ("f64", "f32"):
         res[f"paper_euler_ramp_ird_mxse_10000x92d_{dt}"] = X.paper_iteration(synth.paper(), dt)
     print("# extras: repetition study ...", file=sys.stderr, flush=True)
-    res["rep_1000x2048x36d"] = X.repetition(synth.rep())
+    res["rep_1000x10000x36d"] = X.repetition(synth.rep())
     print("# extras: rolling windows ...", file=sys.stderr, flush=True)
     z = synth.c5_series()
     res["c5_rolling_52x16x4096"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,
@@ -215,7 +227,10 @@ def main():
 
     steps_per_iter = b.particle_steps
     value = steps_per_iter * args.steps / (total_ms / 1e3)
-    alg_bytes = 8 * (b.theta_len + b.total_particles + b.obs_len)
+    # the fused kernel reads x, v, pbest_x, pbest_f and the observations and
+    # writes x, v and f; personal-best copies depend on the data and are not
+    # counted
+    alg_bytes = 8 * (5 * b.theta_len + 2 * b.total_particles + b.obs_len)
     meas = MEASURED_TRAFFIC.get(args.workload)
     traffic = None
     if meas and meas["sources"] == kernel_source_hash() and args.dtype == "f64":

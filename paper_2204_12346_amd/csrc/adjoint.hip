@@ -25,8 +25,11 @@
 // and kbar_s.D = w_s h a_D with the RK4 weights w = (1/6, 1/3, 1/3, 1/6).
 // The initial state depends on I0 through S0 = N - I0 - R0 - D0 and I = I0.
 //
-// Recomputation is deterministic (same operations from the same stored
-// state), so the gradient is bitwise independent of the checkpoint interval.
+// The forward pass here carries S next to s = b S (the form whose stages the
+// reverse sweep recomputes); it agrees with the loss kernel, which carries
+// s alone, to rounding.  Recomputation is deterministic (same operations
+// from the same stored state), so the gradient is bitwise independent of
+// the checkpoint interval.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -207,7 +210,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     cost_accum(a.kind, acc, y.D, ly[0], lw[0], 0);
     if (active) wsp[(size_t)day_base * PS] = y.D;
     {
-        // the same sequence of operations as the forward kernel: set_beta at
+        // the S-carrying form of the forward kernel's step: set_beta at
         // a segment start, rescale at a day start, then the step
         int k = 0;
         long next_seg = (K > 1) ? (long)SS : T + 1;

@@ -26,10 +26,11 @@ constexpr int kWave = 64;
 // with S+ = S - h/6 P, I+ = I + h/6 (P - lam J), R+ = R + h/6 gamma J,
 // D+ = D + h/6 mu J.
 // The stages use the scaled susceptible s = b S, so p_s = s_s I_s costs one
-// multiply; s is carried next to S (s+ = s - b h/6 P) and reset to b S at
-// the start of every day, which bounds its drift from b S to one day of
-// rounding.  In double: 24 VALU operations per step without R (4 mul,
-// 4 add, 16 fma), 25 with R.
+// multiply, and s+ = s - b h/6 P.  With WITH_S the step also carries S
+// (reset s = b S at the start of every day); without it s is the state and
+// S = s/b is formed only where beta changes, which saves one FMA per step.
+// In double without S and R: 23 VALU operations per step (4 mul, 4 add,
+// 15 fma); S and R cost one FMA each.
 template <typename R>
 struct StepConst {
     R b;      // beta / N of the current segment
@@ -92,7 +93,15 @@ __device__ __forceinline__ void rescale(SirdState<R> &y, const StepConst<R> &k)
     y.s = k.b * y.S;
 }
 
-template <typename R, bool WITH_R>
+// End of a segment integrated without S: S = s/b (S stays as it was when
+// beta = 0, since then s = 0 and S does not change).
+template <typename R>
+__device__ __forceinline__ void unscale(SirdState<R> &y, const StepConst<R> &k)
+{
+    if (k.b != R(0)) y.S = y.s / k.b;
+}
+
+template <typename R, bool WITH_R, bool WITH_S = true>
 __device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
 {
     const R s = y.s, I = y.I;
@@ -117,7 +126,7 @@ __device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
     const R J = fma(R(2), I2 + I3, I + I4);
     y.s = fma(-k.h6b, P, s);
     if constexpr (sizeof(R) == 8) {
-        y.S = fma(-k.h6, P, y.S);
+        if (WITH_S) y.S = fma(-k.h6, P, y.S);
         y.I = fma(k.h6, P, fma(-k.h6lam, J, I));
         if (WITH_R) y.Rr = fma(k.h6g, J, y.Rr);
         y.D = fma(k.h6mu, J, y.D);

@@ -182,6 +182,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     }
 
     if constexpr (MODEL == SIRD_MODEL_RK4_SEGMENTS) {
+        // the cost needs only I and D: in double, s = b S is the state
+        // within a segment (S is formed at segment ends); trajectories and
+        // the compensated float state carry S
+        constexpr bool WITH_S = TRAJ || sizeof(R) != 8;
         StepConst<R> sc = step_const<R>(gamma, mu, spd);
         const int seg = P.seg_days;
         int day = 0;
@@ -191,11 +195,13 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             if (k + 1 < K) beta_next = th[(size_t)(k + 1) * ld];  // prefetch
             const int dend = (k == K - 1) ? W : min(W, (k + 1) * seg);
             if (day >= dend) continue;
+            if (!WITH_S && day > 0) unscale(y, sc);
             set_beta(sc, beta_k, N);
+            if (!WITH_S) rescale(y, sc);
             for (; day < dend; ++day) {
-                rescale(y, sc);
+                if (WITH_S) rescale(y, sc);
 #pragma unroll 2
-                for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R>(y, sc);
+                for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
                 emit(day + 1);
             }
         }

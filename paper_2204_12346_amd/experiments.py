@@ -103,15 +103,18 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
 
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
-                k=64, refine_steps=1000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6), chunk=50,
-                method="lbfgs") -> Dict:
+                ks=(64, 1024), refine_steps=1000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6),
+                chunk=50, method="lbfgs") -> Dict:
     """Wall time from pso_init until the loss is within rel of the best
     loss any run of either arm found (L_best), per seed:
       plain arm: swarm iterations (graph chunks of `chunk`), capped;
-      adjoint arm: I' swarm iterations, then refinement of the top-k
+      adjoint arm: I' swarm iterations, then refinement of the k best
       personal bests with gradients from the discrete adjoint: projected
       L-BFGS rounds (method "lbfgs", I0 in log coordinates) or projected
-      Adam steps ("adam").
+      Adam steps ("adam"); one arm per (I', k).  A round on k vectors of
+      one window costs about the same wall time for any k up to a few
+      thousand (one wavefront per 64 vectors), so a larger k refines more
+      starting points, and so more basins, at little extra cost.
     Every run's trajectory of (elapsed s, best loss) is recorded first and
     the thresholds applied afterwards, so both arms are judged against the
     same L_best.  Reports per threshold the median over seeds (None when
@@ -141,8 +144,8 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
         g.close()
         curves["plain"][seed] = curve
         _progress(f"time_to_fit plain seed {seed}: {curve[-1][0]:.2f} s, loss {curve[-1][1]:.9g}")
-    for I1 in pso_first:
-        arm = f"adjoint_I{I1}"
+    for I1, k in [(I1, k) for k in ks for I1 in pso_first]:
+        arm = f"adjoint_I{I1}_k{k}"
         curves[arm] = {}
         for seed in seeds:
             b, params, obs = new(seed)
@@ -151,7 +154,8 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
             t0 = time.perf_counter()
             pso_init(b, params, sw)
             sird_pso_iterate(b, params, sw, obs, wl.loss, I1)
-            curve = [(time.perf_counter() - t0, sw.gbest_f[0].item(), 0)]
+            best = sw.gbest_f[0].item()  # synchronises
+            curve = [(time.perf_counter() - t0, best, 0)]
             if method == "adam":
                 _adam_curve(b, sw, params, obs, wl.loss, k, refine_steps, lr, t0, curve)
             else:
@@ -169,7 +173,7 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
 
     res = {"L_best": L_best, "rels": list(rels), "seeds": list(seeds),
            "plain_cap_iterations": plain_cap, "refine": method,
-           "refine_steps_cap": refine_steps, "k": k, "pso_first": list(pso_first)}
+           "refine_steps_cap": refine_steps, "k": list(ks), "pso_first": list(pso_first)}
     if method == "adam":
         res["lr"] = lr
     for arm, runs in curves.items():

@@ -24,7 +24,8 @@ Workloads (names follow the calibration setups they model):
       ramp of eq. (beta), cost F_IRD^MXSE, 10000 particles, coefficients
       0.5/0.5/0.5, 100 iterations, box of the paper's second run
   rep  the repetition study (Sec. 4.2): one 36-day window of the same series
-      (tau = 35) fitted 1000 times with independent Philox streams
+      (tau = 35) fitted 1000 times with independent Philox streams, each fit
+      with the paper's swarm (10000 particles, 100 iterations)
 """
 from __future__ import annotations
 
@@ -286,7 +287,7 @@ def paper(n_part=10000, iters=100):
                     loss="ird_mxse", w=0.5, c1=0.5, c2=0.5)
 
 
-def rep(n_rep=1000, n_part=2048, iters=100, t0=20):
+def rep(n_rep=1000, n_part=10000, iters=100, t0=20):
     """n_rep independent fits of the 36-day window starting on day t0, each
     with its own Philox stream (the repetition study of Sec. 4.2)."""
     fits = [_paper_fit(35, t0, n_part, r) for r in range(n_rep)]
