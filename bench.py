@@ -33,20 +33,21 @@ sys.path.insert(0, ROOT)
 C3_LAUNCH = dict(block=256, persistent=2048)
 
 # Algorithmic work of one particle-step of the FP64 forward: the RK4 step
-# (stages on the scaled susceptible b S) issues 4 mul + 4 add + 16 fma = 24
-# VALU instructions = 40 flops (an FMA counts 2).  The per-day cost and
-# rescale and the swarm update fused into the same kernel are not counted.
-FLOPS_PER_STEP = 40
-VALU_PER_STEP = 24
+# on (s = b S, I, D) issues 4 mul + 4 add + 15 fma = 23 VALU instructions =
+# 38 flops (an FMA counts 2).  The per-day cost and the swarm update fused
+# into the same kernel are not counted.
+FLOPS_PER_STEP = 38
+VALU_PER_STEP = 23
 PEAK_FP64_VECTOR = 78.6e12  # MI355X, FLOP/s
 
-# HBM bytes per k_forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (scaled by the copy-probe factors 2.0 / 1.0), recorded with the hash of the
-# kernel sources they were taken on; reported only while the sources match.
+# HBM bytes per fused k_forward launch from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs (KiB per dispatch, scaled by the copy-probe factors 2.0 /
+# 1.0), recorded with the hash of the kernel sources they were taken on;
+# reported only while the sources match.
 MEASURED_TRAFFIC = {
-    "c3": {"bytes": 2.0 * 36978.9 * 1024 + 1.0 * 4096.0 * 1024,
-           "sources": "f84f6ab73ae039d1",
-           "summary": "profiles/k_forward_batched_512x1024.md"},
+    "c3": {"bytes": 2.0 * 135876.8 * 1024 + 1.0 * 173432.5 * 1024,
+           "sources": "42086dc496d6f51f",
+           "summary": "profiles/k_forward_fused_batched_512x1024.md"},
 }
 
 METRIC = "particle·RK4-steps/sec"

@@ -5,9 +5,10 @@
 //   1. forward pass: RK4 over the window, the cost, Dhat_i of every day and
 //      the state (S, I, and the stages' scaled susceptible) every s steps
 //      (checkpoints) -> workspace;
-//   2. reverse sweep over the checkpoint intervals, last to first: recompute
-//      the interval's step-start states from its checkpoint into the
-//      workspace, then walk the steps backwards.  For step n with stages
+//   2. reverse sweep over the checkpoint intervals, last to first: replay
+//      the interval from its checkpoint, keeping the state before every 8th
+//      step in the workspace; then, chunk by chunk from the end, replay 8
+//      steps into registers and walk them backwards.  For step n with stages
 //      Y1 = y, Y2 = y + h/2 k1, Y3 = y + h/2 k2, Y4 = y + h k3 and adjoint
 //      abar of y_{n+1}:
 //        kbar4 = h/6 abar,           Ybar4 = J(Y4)^T kbar4
@@ -146,6 +147,9 @@ __device__ __forceinline__ void rk4_adjoint_step(double S, double I, double &aS,
     (void)q3;
 }
 
+// Steps replayed into registers at a time in the reverse sweep.
+constexpr int kChunk = 8;
+
 __device__ __forceinline__ int seg_of(long n, int SS, int K)
 {
     const long k = n / SS;
@@ -175,8 +179,8 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     const size_t PS = (size_t)a.P;
     double *wsp = a.ws + (size_t)(P.p_off + pc);
     const int ck_base = 0;  // checkpoint m: slots 3m (S), 3m+1 (I), 3m+2 (s)
-    const int sc_base = 3 * a.n_ck_max;
-    const int day_base = sc_base + 2 * a.s;
+    const int in_base = 3 * a.n_ck_max;  // chunk c of an interval: 3c .. 3c+2
+    const int day_base = in_base + 3 * ((a.s + kChunk - 1) / kChunk);
 
     {
         // deceased counts: the last of the obs_series blocks of W+1 values
@@ -267,8 +271,9 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     for (int m = n_ck - 1; m >= 0; --m) {
         const long n0 = (long)m * a.s;
         const long n1 = (n0 + a.s < T) ? n0 + a.s : T;
-        // recompute the interval's step-start states with exactly the
-        // forward pass's operations, from the stored (S, I, s)
+        // pass 1: replay the interval from its checkpoint with exactly the
+        // forward pass's operations, storing the state before every
+        // kChunk-th step
         {
             SirdState<double> yr;
             yr.S = active ? wsp[(size_t)(ck_base + 3 * m) * PS] : 0.0;
@@ -282,44 +287,75 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             long next_seg = (kf < K - 1) ? (long)(kf + 1) * SS : T + 1;
             int sd = (int)(n0 % spd);
             for (long st = n0; st < n1; ++st) {
+                if ((st - n0) % kChunk == 0 && active) {
+                    const int c = (int)((st - n0) / kChunk);
+                    wsp[(size_t)(in_base + 3 * c) * PS] = yr.S;
+                    wsp[(size_t)(in_base + 3 * c + 1) * PS] = yr.I;
+                    wsp[(size_t)(in_base + 3 * c + 2) * PS] = yr.s;
+                }
                 if (st == next_seg) {
                     ++kf;
                     next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
                     set_beta(sf, th[(size_t)kf * ld], N);
                 }
                 if (sd == 0) rescale(yr, sf);
-                if (active) {
-                    wsp[(size_t)(sc_base + 2 * (st - n0)) * PS] = yr.S;
-                    wsp[(size_t)(sc_base + 2 * (st - n0) + 1) * PS] = yr.I;
-                }
                 rk4_step<double, false>(yr, sf);
                 if (++sd == spd) sd = 0;
             }
         }
-        // walk the interval backwards; the state of step st-1 is loaded
-        // while step st is processed
-        double Ss = active ? wsp[(size_t)(sc_base + 2 * (n1 - 1 - n0)) * PS] : 0.0;
-        double Is = active ? wsp[(size_t)(sc_base + 2 * (n1 - 1 - n0) + 1) * PS] : 0.0;
-        for (long st = n1 - 1; st >= n0; --st) {
-            if (st < seg_lo) {
-                if (active) gout[(size_t)kr * ld] = g.beta * gl;
-                g.beta = 0.0;
-                --kr;
-                seg_lo = (long)kr * SS;
-                set_beta(sc, th[(size_t)kr * ld], N);
+        // pass 2: chunks last to first: replay kChunk steps into registers,
+        // then walk them backwards (no memory access inside a chunk but the
+        // day's Dhat)
+        const int n_chunks = (int)((n1 - n0 + kChunk - 1) / kChunk);
+        for (int c = n_chunks - 1; c >= 0; --c) {
+            const long cs = n0 + (long)c * kChunk;
+            const int len = (int)((n1 - cs < kChunk) ? n1 - cs : kChunk);
+            SirdState<double> yr;
+            yr.S = active ? wsp[(size_t)(in_base + 3 * c) * PS] : 0.0;
+            yr.I = active ? wsp[(size_t)(in_base + 3 * c + 1) * PS] : 0.0;
+            yr.s = active ? wsp[(size_t)(in_base + 3 * c + 2) * PS] : 0.0;
+            yr.Rr = yr.D = 0.0;
+            yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
+            int kf = seg_of(cs, SS, K);
+            StepConst<double> sf = sc;
+            set_beta(sf, th[(size_t)kf * ld], N);
+            long next_seg = (kf < K - 1) ? (long)(kf + 1) * SS : T + 1;
+            int sd = (int)(cs % spd);
+            double Sa[kChunk], Ia[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                Sa[j] = Ia[j] = 0.0;
+                if (j < len) {
+                    if (cs + j == next_seg) {
+                        ++kf;
+                        next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
+                        set_beta(sf, th[(size_t)kf * ld], N);
+                    }
+                    if (sd == 0) rescale(yr, sf);
+                    Sa[j] = yr.S;
+                    Ia[j] = yr.I;
+                    rk4_step<double, false>(yr, sf);
+                    if (++sd == spd) sd = 0;
+                }
             }
-            double Sn = 0.0, In = 0.0;
-            if (active && st > n0) {
-                Sn = wsp[(size_t)(sc_base + 2 * (st - 1 - n0)) * PS];
-                In = wsp[(size_t)(sc_base + 2 * (st - 1 - n0) + 1) * PS];
-            }
-            rk4_adjoint_step(Ss, Is, aS, aI, aD, sc, mu, invN, h3, g);
-            Ss = Sn;
-            Is = In;
-            if (st % spd == 0) {
-                const int i = (int)(st / spd);
-                const double Di = active ? wsp[(size_t)(day_base + i) * PS] : 0.0;
-                aD += cost_grad(a.kind, i, W, Di, ly[i], lw[i], imax);
+#pragma unroll
+            for (int j = kChunk - 1; j >= 0; --j) {
+                if (j < len) {
+                    const long st = cs + j;
+                    if (st < seg_lo) {
+                        if (active) gout[(size_t)kr * ld] = g.beta * gl;
+                        g.beta = 0.0;
+                        --kr;
+                        seg_lo = (long)kr * SS;
+                        set_beta(sc, th[(size_t)kr * ld], N);
+                    }
+                    rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, invN, h3, g);
+                    if (st % spd == 0) {
+                        const int i = (int)(st / spd);
+                        const double Di = active ? wsp[(size_t)(day_base + i) * PS] : 0.0;
+                        aD += cost_grad(a.kind, i, W, Di, ly[i], lw[i], imax);
+                    }
+                }
             }
         }
     }
@@ -338,12 +374,13 @@ static int resolve_interval(const sird_batch *b, int ckpt_interval)
     return s < 1 ? 1 : s;
 }
 
-// Workspace slots per particle: 3 per checkpoint (S, I, s), 2 per step of
-// one recomputed interval (S, I), and Dhat of every day.
+// Workspace slots per particle: 3 per checkpoint (S, I, s), 3 per chunk of
+// one replayed interval, and Dhat of every day.
 static size_t ws_slots(const sird_batch *b, int s)
 {
     const int64_t n_ck = (b->max_steps + s - 1) / s;
-    return (size_t)(3 * n_ck + 2 * (int64_t)s + b->max_days + 1);
+    const int64_t n_chunk = ((int64_t)s + kChunk - 1) / kChunk;
+    return (size_t)(3 * n_ck + 3 * n_chunk + b->max_days + 1);
 }
 
 }  // namespace sird

@@ -203,7 +203,8 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     b.c.block = 0
     ws = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 0)
     s = int(np.ceil(np.sqrt(300)))
-    assert ws == (3 * int(np.ceil(300 / s)) + 2 * s + 46) * 165 * 8
+    # 3 per checkpoint, 3 per 8-step chunk of one interval, one per day
+    assert ws == (3 * int(np.ceil(300 / s)) + 3 * int(np.ceil(s / 8)) + 46) * 165 * 8
     # too small a workspace is reported before anything is enqueued
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
                                 dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 16, None)

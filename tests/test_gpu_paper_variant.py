@@ -212,3 +212,37 @@ def test_ramp_extension_stays_at_beta2():
     prob = oracle.Problem(f.W + 21, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0, model=1)
     for p in range(5):
         assert_traj_close(out[p], oracle.integrate_model(prob, th[p]), TOL64, f"particle {p}")
+
+
+def test_ramp_edge_cases_against_oracle():
+    """One-day and ragged windows, several steps per day, a problem with no
+    particles, a flat observed series (normalised by 1) and NaN parameters."""
+    N = 1e6
+    rng = np.random.default_rng(8)
+    specs, ths, obs, probs = [], [], [], []
+    for W, spd, n in ((1, 1, 3), (2, 3, 65), (5, 2, 0), (13, 1, 64)):
+        specs.append(S.ProblemSpec(W, spd, 1, 4, N, R0=100.0, D0=10.0, n_part=n,
+                                   model="euler_ramp"))
+        lo = np.array([0, 0, 0, 0, 0, 0, 500.0])
+        hi = np.array([1, 1, W, W, 0.5, 0.05, 500.0])
+        ths.append(lo + rng.uniform(0, 1, (n, 7)) * (hi - lo))
+        o = rng.uniform(0, 1000, (3, W + 1))
+        o[2] = 7.0  # flat deceased series
+        obs.append(o.reshape(-1))
+        probs.append(oracle.Problem(W, spd, 1, 4, N, R0=100.0, D0=10.0, model=1))
+    ths[3][5, 4] = np.nan
+    b = S.Batch(specs, obs_series=3)
+    theta, ob = b.pack_theta(ths), b.pack_obs(obs)
+    for kind in KINDS_IRD + ["mse"]:
+        print(f"case ramp edges {kind}", flush=True)
+        got = b.split_particles(S.sird_loss(b, theta, ob, kind))
+        for r, s in enumerate(specs):
+            if s.n_part == 0:
+                continue
+            o = obs[r] if kind.startswith("ird") else obs[r][-(s.W + 1):]
+            ref = oracle.loss_batch_model(probs[r], ths[r], o, kind)
+            trajs = [oracle.integrate_model(probs[r], t) for t in ths[r]]
+            kap = [kappa_ird(kind, t, obs[r]) if kind.startswith("ird") else kappa(kind, t[3], o)
+                   for t in trajs]
+            assert_loss_close(got[r], ref, np.nan_to_num(kap), TOL64, f"{kind}/problem {r}")
+    assert np.isnan(got[3][5])
