@@ -151,6 +151,7 @@ def extras():
     print("# extras: gradients ...", file=sys.stderr, flush=True)
     wl4, th4 = synth.c4()
     res["c4_gradients_65536x7300steps"] = X.gradients_per_s(wl4, th4)
+    res["c4_gradients_65536x7300steps_interval8"] = X.gradients_per_s(wl4, th4, ckpt_interval=8)
     print("# extras: time to fit ...", file=sys.stderr, flush=True)
     res["time_to_fit_c2"] = X.time_to_fit(synth.c2())
     print("# extras: the paper's own timing case ...", file=sys.stderr, flush=True)

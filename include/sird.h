@@ -329,8 +329,10 @@ size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval);
 
 /* Indices (local to each problem) of the k particles with the smallest
  * pbest_f, ordered by (pbest_f, index), NaN last.  idx_out: device [n_prob][k];
- * problems with fewer than k particles pad with -1.
- * Errors: SIRD_EINVAL (k < 1 or k > 1024, null pointer), SIRD_EHIP. */
+ * problems with fewer than k particles pad with -1.  Up to k = 32 the
+ * selection takes k rounds over each problem; above it every particle's
+ * rank is counted (O(n^2) comparisons per problem of n particles).
+ * Errors: SIRD_EINVAL (k < 1 or k > 65536, null pointer), SIRD_EHIP. */
 int pso_topk(const sird_batch *batch, const double *pbest_f, int k, int64_t *idx_out,
              void *stream);
 

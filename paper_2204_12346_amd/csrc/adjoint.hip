@@ -150,10 +150,10 @@ __device__ __forceinline__ void rk4_adjoint_step(double S, double I, double &aS,
 // Steps replayed into registers at a time in the reverse sweep.
 constexpr int kChunk = 8;
 
-__device__ __forceinline__ int seg_of(long n, int SS, int K)
+__device__ __forceinline__ int seg_of(int n, int SS, int K)
 {
-    const long k = n / SS;
-    return k > K - 1 ? K - 1 : (int)k;
+    const int k = n / SS;
+    return k > K - 1 ? K - 1 : k;
 }
 
 __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
@@ -169,8 +169,9 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
     const int W = P.n_days, spd = P.steps_per_day, K = P.n_seg, n = P.n_part;
-    const int SS = P.seg_days * spd;  // steps per segment
     const long T = (long)W * spd;
+    // steps per segment (a segment longer than the window is the window)
+    const int SS = (int)min((long)P.seg_days * spd, T + 1);
     const int pl = tl.p0 + lane;
     const bool active = pl < n;
     const int pc = active ? pl : n - 1;
@@ -265,16 +266,19 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     Grad g{0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
     set_beta(sc, th[(size_t)kr * ld], N);
-    long seg_lo = (long)kr * SS;  // first step of segment kr
+    int seg_lo = kr * SS;  // first step of segment kr
 
-    const int n_ck = (int)((T + a.s - 1) / a.s);
+    const int Ti = (int)T;  // at most 2^30 (checked on the host)
+    const int n_ck = (Ti + a.s - 1) / a.s;
     for (int m = n_ck - 1; m >= 0; --m) {
-        const long n0 = (long)m * a.s;
-        const long n1 = (n0 + a.s < T) ? n0 + a.s : T;
+        const int n0 = m * a.s;
+        const int n1 = (n0 + a.s < Ti) ? n0 + a.s : Ti;
         // pass 1: replay the interval from its checkpoint with exactly the
-        // forward pass's operations, storing the state before every
-        // kChunk-th step
-        {
+        // forward pass's operations up to the start of its last chunk,
+        // storing the state before the first step of every chunk but the
+        // first (which is the checkpoint)
+        const int n_chunks = (n1 - n0 + kChunk - 1) / kChunk;
+        if (n_chunks > 1) {
             SirdState<double> yr;
             yr.S = active ? wsp[(size_t)(ck_base + 3 * m) * PS] : 0.0;
             yr.I = active ? wsp[(size_t)(ck_base + 3 * m + 1) * PS] : 0.0;
@@ -284,43 +288,78 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             int kf = seg_of(n0, SS, K);
             StepConst<double> sf = sc;
             set_beta(sf, th[(size_t)kf * ld], N);
-            long next_seg = (kf < K - 1) ? (long)(kf + 1) * SS : T + 1;
-            int sd = (int)(n0 % spd);
-            for (long st = n0; st < n1; ++st) {
-                if ((st - n0) % kChunk == 0 && active) {
-                    const int c = (int)((st - n0) / kChunk);
+            int next_seg = (kf < K - 1) ? (kf + 1) * SS : Ti + 1;
+            int sd = n0 % spd;
+            for (int c = 1; c < n_chunks; ++c) {
+                for (int j = 0; j < kChunk; ++j) {
+                    const int st = n0 + (c - 1) * kChunk + j;
+                    if (st == next_seg) {
+                        ++kf;
+                        next_seg = (kf < K - 1) ? next_seg + SS : Ti + 1;
+                        set_beta(sf, th[(size_t)kf * ld], N);
+                    }
+                    if (sd == 0) rescale(yr, sf);
+                    rk4_step<double, false>(yr, sf);
+                    if (++sd == spd) sd = 0;
+                }
+                if (active) {
                     wsp[(size_t)(in_base + 3 * c) * PS] = yr.S;
                     wsp[(size_t)(in_base + 3 * c + 1) * PS] = yr.I;
                     wsp[(size_t)(in_base + 3 * c + 2) * PS] = yr.s;
                 }
-                if (st == next_seg) {
-                    ++kf;
-                    next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
-                    set_beta(sf, th[(size_t)kf * ld], N);
-                }
-                if (sd == 0) rescale(yr, sf);
-                rk4_step<double, false>(yr, sf);
-                if (++sd == spd) sd = 0;
             }
         }
         // pass 2: chunks last to first: replay kChunk steps into registers,
-        // then walk them backwards (no memory access inside a chunk but the
-        // day's Dhat)
-        const int n_chunks = (int)((n1 - n0 + kChunk - 1) / kChunk);
+        // then walk them backwards.  The next chunk's start state, its day
+        // boundaries and their Dhat are loaded before the current chunk is
+        // walked, so with one wavefront per SIMD their latency is hidden.
+        double nS, nI, ns, nD[kChunk];
+        int nday[kChunk], nph;
+        auto load_chunk = [&](int c) {
+            // chunk 0 starts at the interval's checkpoint
+            const int slot = c == 0 ? ck_base + 3 * m : in_base + 3 * c;
+            nS = active ? wsp[(size_t)slot * PS] : 0.0;
+            nI = active ? wsp[(size_t)(slot + 1) * PS] : 0.0;
+            ns = active ? wsp[(size_t)(slot + 2) * PS] : 0.0;
+            const int cs = n0 + c * kChunk;
+            const int q = cs / spd;
+            nph = cs - q * spd;  // step of the day at cs
+            int ph = nph, d = nph == 0 ? q : q + 1;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                nday[j] = -1;
+                nD[j] = 0.0;
+                if (cs + j < n1 && ph == 0) {
+                    nday[j] = d;
+                    if (active) nD[j] = wsp[(size_t)(day_base + d) * PS];
+                    ++d;
+                }
+                ph = (ph + 1 == spd) ? 0 : ph + 1;
+            }
+        };
+        load_chunk(n_chunks - 1);
         for (int c = n_chunks - 1; c >= 0; --c) {
-            const long cs = n0 + (long)c * kChunk;
-            const int len = (int)((n1 - cs < kChunk) ? n1 - cs : kChunk);
+            const int cs = n0 + c * kChunk;
+            const int len = (n1 - cs < kChunk) ? n1 - cs : kChunk;
             SirdState<double> yr;
-            yr.S = active ? wsp[(size_t)(in_base + 3 * c) * PS] : 0.0;
-            yr.I = active ? wsp[(size_t)(in_base + 3 * c + 1) * PS] : 0.0;
-            yr.s = active ? wsp[(size_t)(in_base + 3 * c + 2) * PS] : 0.0;
+            yr.S = nS;
+            yr.I = nI;
+            yr.s = ns;
             yr.Rr = yr.D = 0.0;
             yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
+            double Dd[kChunk];
+            int day[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                Dd[j] = nD[j];
+                day[j] = nday[j];
+            }
+            int sd = nph;
+            if (c > 0) load_chunk(c - 1);
             int kf = seg_of(cs, SS, K);
-            StepConst<double> sf = sc;
-            set_beta(sf, th[(size_t)kf * ld], N);
-            long next_seg = (kf < K - 1) ? (long)(kf + 1) * SS : T + 1;
-            int sd = (int)(cs % spd);
+            StepConst<double> sf = sc;  // the reverse's segment: no reload
+            if (kf != kr) set_beta(sf, th[(size_t)kf * ld], N);
+            int next_seg = (kf < K - 1) ? (kf + 1) * SS : Ti + 1;
             double Sa[kChunk], Ia[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
@@ -328,7 +367,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                 if (j < len) {
                     if (cs + j == next_seg) {
                         ++kf;
-                        next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
+                        next_seg = (kf < K - 1) ? next_seg + SS : Ti + 1;
                         set_beta(sf, th[(size_t)kf * ld], N);
                     }
                     if (sd == 0) rescale(yr, sf);
@@ -341,19 +380,17 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
 #pragma unroll
             for (int j = kChunk - 1; j >= 0; --j) {
                 if (j < len) {
-                    const long st = cs + j;
-                    if (st < seg_lo) {
+                    if (cs + j < seg_lo) {
                         if (active) gout[(size_t)kr * ld] = g.beta * gl;
                         g.beta = 0.0;
                         --kr;
-                        seg_lo = (long)kr * SS;
+                        seg_lo = kr * SS;
                         set_beta(sc, th[(size_t)kr * ld], N);
                     }
                     rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, invN, h3, g);
-                    if (st % spd == 0) {
-                        const int i = (int)(st / spd);
-                        const double Di = active ? wsp[(size_t)(day_base + i) * PS] : 0.0;
-                        aD += cost_grad(a.kind, i, W, Di, ly[i], lw[i], imax);
+                    if (day[j] >= 0) {
+                        const int i = day[j];
+                        aD += cost_grad(a.kind, i, W, Dd[j], ly[i], lw[i], imax);
                     }
                 }
             }
@@ -375,7 +412,8 @@ static int resolve_interval(const sird_batch *b, int ckpt_interval)
 }
 
 // Workspace slots per particle: 3 per checkpoint (S, I, s), 3 per chunk of
-// one replayed interval, and Dhat of every day.
+// one replayed interval (the first chunk's slots go unused: it starts at
+// the checkpoint), and Dhat of every day.
 static size_t ws_slots(const sird_batch *b, int s)
 {
     const int64_t n_ck = (b->max_steps + s - 1) / s;

@@ -193,7 +193,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         for (int k = 0; k < K; ++k) {
             const double beta_k = beta_next;
             if (k + 1 < K) beta_next = th[(size_t)(k + 1) * ld];  // prefetch
-            const int dend = (k == K - 1) ? W : min(W, (k + 1) * seg);
+            const int dend = (k == K - 1) ? W : (int)min((long)W, (long)(k + 1) * seg);
             if (day >= dend) continue;
             if (!WITH_S && day > 0) unscale(y, sc);
             set_beta(sc, beta_k, N);

@@ -12,6 +12,10 @@
 namespace sird {
 
 // ------------------------------------------------------------------ top-k
+// Up to kTopkRounds the selection runs in k rounds, above it by ranks.
+constexpr int kTopkRounds = 32;
+constexpr int kTopkMax = 65536;
+
 // One block per problem.  Round q selects the smallest (f, index) pair that
 // is strictly greater than the pair selected in round q-1, so the k rounds
 // emit the k smallest in (f, index) order.  NaN is ordered as +inf.
@@ -74,6 +78,54 @@ __global__ void __launch_bounds__(256) k_topk(const sird_problem *probs, const d
         }
         __syncthreads();
     }
+}
+
+// Larger k: the rank of every particle, the number of particles whose
+// (f, index) key is smaller, computed by one wavefront per 64-particle tile
+// scanning its problem's n keys (broadcast 64 at a time by shuffles);
+// a particle of rank < k is written to position rank.  Keys are distinct,
+// so ranks are a permutation and the output equals the k-round selection.
+// O(n^2) comparisons per problem, in parallel over its tiles.
+__global__ void __launch_bounds__(256) k_topk_rank(const sird_problem *probs,
+                                                   const sird_tile *tiles, int n_tiles,
+                                                   const double *pbest_f, int k,
+                                                   int64_t *idx_out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = wave_tile_index();
+    if (t >= n_tiles) return;
+    const sird_tile tl = tiles[t];
+    const sird_problem P = probs[tl.prob];
+    const int n = P.n_part;
+    const int p = tl.p0 + lane;
+    double fp = INFINITY;
+    if (p < n) {
+        fp = pbest_f[P.p_off + p];
+        if (fp != fp) fp = INFINITY;
+    }
+    int rank = 0;
+    for (int q0 = 0; q0 < n; q0 += kWave) {
+        double fq = INFINITY;
+        if (q0 + lane < n) {
+            fq = pbest_f[P.p_off + q0 + lane];
+            if (fq != fq) fq = INFINITY;
+        }
+        const int m = min(kWave, n - q0);
+        for (int j = 0; j < m; ++j) {
+            const double g = __shfl(fq, j);
+            rank += key_less(g, q0 + j, fp, p) ? 1 : 0;
+        }
+    }
+    if (p < n && rank < k) idx_out[(size_t)tl.prob * k + rank] = p;
+}
+
+// Positions n..k-1 of every problem with fewer than k particles.
+__global__ void __launch_bounds__(256) k_topk_pad(const sird_problem *probs, int k,
+                                                  int64_t *idx_out)
+{
+    const int r = blockIdx.x;
+    const int n = probs[r].n_part;
+    for (int q = n + (int)threadIdx.x; q < k; q += blockDim.x) idx_out[(size_t)r * k + q] = -1;
 }
 
 // ----------------------------------------------------------------- gather
@@ -446,9 +498,22 @@ extern "C" int pso_topk(const sird_batch *batch, const double *pbest_f, int k,
     int st = check_batch(batch, "pso_topk");
     if (st) return st;
     if (!pbest_f || !idx_out) return fail(SIRD_EINVAL, "pso_topk: NULL array");
-    if (k < 1 || k > 1024) return fail(SIRD_EINVAL, "pso_topk: k must be in [1, 1024]");
-    hipLaunchKernelGGL(k_topk, dim3(batch->n_prob), dim3(256), 0, (hipStream_t)stream,
-                       batch->probs, pbest_f, k, idx_out);
+    if (k < 1 || k > kTopkMax)
+        return fail(SIRD_EINVAL, "pso_topk: k must be in [1, 65536]");
+    hipStream_t s = (hipStream_t)stream;
+    if (k <= kTopkRounds) {
+        hipLaunchKernelGGL(k_topk, dim3(batch->n_prob), dim3(256), 0, s, batch->probs, pbest_f,
+                           k, idx_out);
+        return hip_status(hipGetLastError(), "pso_topk");
+    }
+    hipLaunchKernelGGL(k_topk_pad, dim3(batch->n_prob), dim3(256), 0, s, batch->probs, k,
+                       idx_out);
+    st = hip_status(hipGetLastError(), "pso_topk");
+    if (st) return st;
+    const int grid = tile_blocks(batch->n_tiles);
+    if (grid == 0) return SIRD_OK;
+    hipLaunchKernelGGL(k_topk_rank, dim3(grid), dim3(256), 0, s, batch->probs, batch->tiles,
+                       batch->n_tiles, pbest_f, k, idx_out);
     return hip_status(hipGetLastError(), "pso_topk");
 }
 

@@ -98,12 +98,13 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
     torch.cuda.synchronize()
     ms_f = e0.elapsed_time(e1) / reps
     return {"gradients_per_s": len(thetas) / (ms_b / 1e3), "ms_backward": ms_b,
+            "ckpt_interval": ckpt_interval or "ceil(sqrt(T))",
             "ms_forward": ms_f, "backward_over_forward": ms_b / ms_f,
             "particle_steps": b.particle_steps, "workspace_bytes": int(ws.numel())}
 
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
-                ks=(64, 1024), refine_steps=1000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6),
+                ks=(64, 1024, 4096), refine_steps=2000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6),
                 chunk=50, method="lbfgs") -> Dict:
     """Wall time from pso_init until the loss is within rel of the best
     loss any run of either arm found (L_best), per seed:
@@ -209,11 +210,13 @@ def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=2
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
     loss = rb.empty_particles()
-    ws = torch.empty(max(sird_loss_backward_workspace(rb, 0), 8), dtype=torch.uint8,
+    ci = fit.refine_interval(rb)
+    ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
                      device=b.device)
     best = curve[-1][1]
     for t in range(1, steps + 1):
-        sird_loss_backward(rb, theta, obs, kind, grad_theta=grad, loss_out=loss, workspace=ws)
+        sird_loss_backward(rb, theta, obs, kind, grad_theta=grad, loss_out=loss,
+                           ckpt_interval=ci, workspace=ws)
         sird_adam_step(rb, theta, grad, m, v, params.lo, params.hi, t, lr=lr)
         if t % check_every == 0:
             cur = float(torch.nan_to_num(loss, nan=float("inf")).min().item())
@@ -233,9 +236,11 @@ def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10)
     rb = Batch(specs, device=b.device, obs_series=b.obs_series)
     theta = sird_gather(b, sw.pbest_x, params.lo, rb, idx, k)
     st = LbfgsState(rb, theta)
-    ws = torch.empty(max(sird_loss_backward_workspace(rb, 0), 8), dtype=torch.uint8,
+    ci = fit.refine_interval(rb)
+    ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
                      device=b.device)
-    sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f, workspace=ws)
+    sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f,
+                       ckpt_interval=ci, workspace=ws)
     best = [curve[-1][1]]
 
     def record(r):
@@ -244,8 +249,8 @@ def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10)
         curve.append((time.perf_counter() - t0, best[0], r))
         return False
 
-    fit.lbfgs_rounds(rb, st, params, obs, kind, rounds, workspace=ws, callback=record,
-                     check_every=check_every)
+    fit.lbfgs_rounds(rb, st, params, obs, kind, rounds, ckpt_interval=ci, workspace=ws,
+                     callback=record, check_every=check_every)
     record(rounds)
     return rb
 

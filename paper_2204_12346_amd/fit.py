@@ -19,6 +19,20 @@ from .core import (Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm, pso_
                    sird_loss_backward_workspace, sird_pso_iterate)
 
 
+# Checkpoint interval of the adjoint that the refinement drivers use when
+# the workspace allows: the reverse sweep replays 8 steps at a time into
+# registers, so an interval of 8 leaves nothing else to replay.
+SHORT_INTERVAL = 8
+
+
+def refine_interval(batch: Batch, budget_bytes=1 << 28) -> int:
+    """ckpt_interval for sird_loss_backward on this batch: 8 when its
+    workspace fits budget_bytes, else 0 (ceil(sqrt(T)))."""
+    if sird_loss_backward_workspace(batch, SHORT_INTERVAL) <= budget_bytes:
+        return SHORT_INTERVAL
+    return 0
+
+
 def run_swarm(batch: Batch, params: PsoParams, obs, kind="ssre", iters=100, hist=True,
               graph_chunk=0, swarm: Optional[Swarm] = None, init=True) -> Swarm:
     """iters swarm iterations from pso_init.  graph_chunk > 0 replays a HIP
@@ -50,7 +64,7 @@ class Refined:
 
 def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre", k=32,
                 max_steps=2000, lr=1e-3, rel_tol=1e-12, check_every=25,
-                ckpt_interval=0) -> Refined:
+                ckpt_interval=None) -> Refined:
     """Projected Adam (Kingma & Ba 2015) from the k best personal bests of
     every problem, in box-normalised coordinates, with gradients from the
     discrete adjoint.  Stops after max_steps, or when no refined particle's
@@ -59,6 +73,8 @@ def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre",
     specs = [s.with_particles(k) for s in batch.specs]
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
+    if ckpt_interval is None:
+        ckpt_interval = refine_interval(rb)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
@@ -83,12 +99,14 @@ def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre",
 
 
 def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre", rounds=200,
-                 c1=1e-4, ckpt_interval=0, workspace=None, callback=None, check_every=0):
+                 c1=1e-4, ckpt_interval=None, workspace=None, callback=None, check_every=0):
     """Run projected L-BFGS rounds on every parameter vector of rb: each
     round is sird_lbfgs_propose, the adjoint at the trial points
     (sird_loss_backward), sird_lbfgs_accept.  st.f / st.grad must hold the
     loss and gradient at st.theta.  callback(round) every check_every rounds
     may return True to stop."""
+    if ckpt_interval is None:
+        ckpt_interval = refine_interval(rb)
     ws = workspace
     if ws is None:
         ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8),
@@ -106,7 +124,7 @@ def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre",
 
 def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre", k=32,
                  max_rounds=500, rel_tol=1e-12, check_every=25, m=8,
-                 ckpt_interval=0) -> Refined:
+                 ckpt_interval=None) -> Refined:
     """Projected L-BFGS from the k best personal bests of every problem, in
     box-normalised coordinates, with gradients from the discrete adjoint.
     Stops after max_rounds, or when no vector's loss changed by more than
@@ -115,6 +133,8 @@ def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre"
     specs = [s.with_particles(k) for s in batch.specs]
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
+    if ckpt_interval is None:
+        ckpt_interval = refine_interval(rb)
     st = LbfgsState(rb, theta, m=m)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
                      device=batch.device)

@@ -37,6 +37,24 @@ def test_topk_order_ties_and_nan():
         assert list(idx[r]) == exp, r
 
 
+def test_topk_by_rank_for_large_k():
+    """Above 32 the selection counts ranks; same order, ties and padding."""
+    specs = [S.ProblemSpec(10, 2, 5, 2, 1e5, n_part=n) for n in (3000, 70, 0, 500)]
+    b = S.Batch(specs)
+    rng = np.random.default_rng(4)
+    fs = [np.round(rng.uniform(0, 5, s.n_part), 2) for s in specs]
+    fs[0][[3, 7, 2999]] = np.nan
+    fs[3][[10, 20]] = np.inf
+    f_all = torch.from_numpy(np.concatenate(fs)).cuda()
+    for k in (33, 300, 3000, 4096):
+        idx = S.pso_topk(b, f_all, k).cpu().numpy()
+        for r, f in enumerate(fs):
+            key = np.where(np.isnan(f), np.inf, f)
+            order = np.lexsort((np.arange(len(f)), key))[:k]
+            exp = list(order) + [-1] * (k - len(order))
+            assert list(idx[r]) == exp, (k, r)
+
+
 def test_gather_and_adam_match_oracle():
     wl = synth.c3(regions=[0, 1, 2])
     n_parts = [100, 40, 64]
