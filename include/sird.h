@@ -375,7 +375,7 @@ typedef struct lbfgs_state {
     double *gp;
     int32_t *count;
     int32_t *head;
-    int32_t m;        /* pairs kept, 1..8 */
+    int32_t m;        /* pairs kept, 1..32 */
     int32_t log_last; /* 1: the last parameter (I0) is optimised as log I0
                          in [log lo, log hi] (requires lo > 0) */
 } lbfgs_state;
@@ -397,7 +397,7 @@ typedef struct lbfgs_state {
  *     (store the pair (u_t - u, g_u,t - g_u) when s.y > 0; alpha = 1), else
  *     halve alpha (below 1e-20: drop the memory, alpha = 1).
  * Parameter vectors are independent; d <= 64.
- * Errors: SIRD_EINVAL (null pointer, m outside 1..8, c1 outside (0,1),
+ * Errors: SIRD_EINVAL (null pointer, m outside 1..32, c1 outside (0,1),
  * log_last not 0/1), SIRD_EHIP. */
 int sird_lbfgs_propose(const sird_batch *batch, const lbfgs_state *state, const double *lo,
                        const double *hi, void *stream);

@@ -339,7 +339,7 @@ class LbfgsState:
     batch (lbfgs_state); theta is copied in, f/grad are evaluated by the
     caller before the first round."""
 
-    def __init__(self, batch: Batch, theta, m=8, log_last=True):
+    def __init__(self, batch: Batch, theta, m=32, log_last=True):
         dev = batch.device
         th = max(batch.theta_len, 1)
         P = max(batch.total_particles, 1)

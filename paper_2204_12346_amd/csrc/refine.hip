@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 }
 
 // ---------------------------------------------------------------- L-BFGS
-constexpr int kLbfgsMaxM = 8;
+constexpr int kLbfgsMaxM = 32;
 
 struct LbfgsArgs {
     const sird_problem *probs;
@@ -440,7 +440,7 @@ static int check_lbfgs(const sird_batch *b, const lbfgs_state *st, const double 
     if (!st->theta || !st->grad || !st->f || !st->theta_t || !st->grad_t || !st->f_t ||
         !st->S || !st->Y || !st->rho || !st->alpha || !st->gp || !st->count || !st->head)
         return fail(SIRD_EINVAL, w + ": NULL state array");
-    if (st->m < 1 || st->m > kLbfgsMaxM) return fail(SIRD_EINVAL, w + ": m must be in 1..8");
+    if (st->m < 1 || st->m > kLbfgsMaxM) return fail(SIRD_EINVAL, w + ": m must be in 1..32");
     if (st->log_last != 0 && st->log_last != 1)
         return fail(SIRD_EINVAL, w + ": log_last must be 0 or 1");
     if (b->max_d > 64) return fail(SIRD_EINVAL, w + ": d > 64");

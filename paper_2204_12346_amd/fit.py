@@ -123,7 +123,7 @@ def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre",
 
 
 def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre", k=32,
-                 max_rounds=500, rel_tol=1e-12, check_every=25, m=8,
+                 max_rounds=500, rel_tol=1e-12, check_every=25, m=32,
                  ckpt_interval=None) -> Refined:
     """Projected L-BFGS from the k best personal bests of every problem, in
     box-normalised coordinates, with gradients from the discrete adjoint.

@@ -154,16 +154,18 @@ def test_autotuner_candidates_agree_bitwise(tmp_path, monkeypatch):
     assert again == best
 
 
-def test_lbfgs_rounds_match_oracle_in_lockstep():
-    """Same (f, grad) inputs on both sides -> the same proposals and updates."""
+@pytest.mark.parametrize("m,rounds", [(5, 12), (32, 40)])
+def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds):
+    """Same (f, grad) inputs on both sides -> the same proposals and updates
+    (the second case wraps the 32-pair memory)."""
     f = synth.c2().fits[0]
     P = 40
     th = random_theta(f, P, seed=11)
     th[:, :f.K] *= 0.5
     b = make_batch([f], [P])
     lo, hi = b.pack_box([f.lo]), b.pack_box([f.hi])
-    st = S.LbfgsState(b, b.pack_theta([th]), m=5, log_last=True)
-    ost = oracle.Lbfgs(th, m=5, log_last=True)
+    st = S.LbfgsState(b, b.pack_theta([th]), m=m, log_last=True)
+    ost = oracle.Lbfgs(th, m=m, log_last=True)
     prob = oracle_problem(f)
 
     def fg(t):
@@ -173,7 +175,7 @@ def test_lbfgs_rounds_match_oracle_in_lockstep():
         ost.f[q], ost.grad[q] = fg(th[q])
     st.f.copy_(torch.from_numpy(np.concatenate([ost.f, np.zeros(0)])).cuda())
     st.grad.copy_(b.pack_theta([ost.grad]))
-    for rnd in range(12):
+    for rnd in range(rounds):
         S.sird_lbfgs_propose(b, st, lo, hi)
         ost.propose(f.lo, f.hi)
         tt = b.unpack_theta(st.theta_t)[0]
