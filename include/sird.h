@@ -263,7 +263,8 @@ int pso_init(const sird_batch *batch, const pso_params *params, const pso_state 
  *   2. global best per problem: argmin of pbest_f, lowest index on ties,
  *      replacing gbest only on strict improvement; recorded in hist_* row it;
  *   3. velocity and position with r1, r2 from Philox counter
- *      (it, local particle, j/2, 1), words 2*(j%2) and 2*(j%2)+1:
+ *      (it, local particle, j/4, 1), word j%4: r1 its high and r2 its low
+ *      32 bits, times 2^-32:
  *        t = w v; t = t + (c1 r1)(pbest - x); t = t + (c2 r2)(gbest - x);
  *        v = t;   x = min(max(x + v, lo), hi)
  *      each operation a single rounded IEEE multiply or add (no fusion);

@@ -265,10 +265,12 @@ void orc_loss_batch(int W, int spd, int seg_days, int K, double N, double R0,
 /* ------------------------------------------------------------------ */
 /* PSO, Sec. 3.3.                                                       */
 /* Random numbers: Philox4x64-10, key = (seed, stream).                 */
-/* A counter block (iteration, particle, m, purpose) yields four words;  */
-/* it serves the dimension pair j = 2m, 2m+1.                            */
-/*   init (purpose 0):     u_j  = u01(word 2*(j&1))                      */
-/*   velocity (purpose 1): r1_j = u01(word 2*(j&1)), r2_j = u01(word 2*(j&1)+1) */
+/* A counter block (iteration, particle, m, purpose) yields four words.  */
+/*   init (purpose 0): block m = j/2 serves dimensions 2m, 2m+1 with     */
+/*     u_j = u01(word 2*(j&1)) (53 bits);                                */
+/*   velocity (purpose 1): block m = j/4 serves dimensions 4m..4m+3;     */
+/*     word j&3 gives r1_j = (high 32 bits) 2^-32 and                    */
+/*     r2_j = (low 32 bits) 2^-32.                                       */
 /* Arrays are row-major [P][d].                                          */
 /* ------------------------------------------------------------------ */
 static void philox_block(uint64_t seed, uint64_t stream, uint64_t it, uint64_t p,
@@ -364,9 +366,10 @@ void orc_pso_move(int P, int d, uint64_t it, double w, double c1, double c2,
     for (int p = 0; p < P; ++p) {
         for (int j = 0; j < d; ++j) {
             uint64_t wd[4];
-            philox_block(seed, stream, it, (uint64_t)p, (uint64_t)(j / 2), 1, wd);
-            double r1 = orc_u01(wd[2 * (j % 2)]);
-            double r2 = orc_u01(wd[2 * (j % 2) + 1]);
+            philox_block(seed, stream, it, (uint64_t)p, (uint64_t)(j / 4), 1, wd);
+            uint64_t word = wd[j % 4];
+            double r1 = (double)(word >> 32) * (1.0 / 4294967296.0);
+            double r2 = (double)(word & 0xffffffffULL) * (1.0 / 4294967296.0);
             long o = (long)p * d + j;
             double xo = x[o];
             double t = w * v[o];

@@ -360,9 +360,10 @@ struct PsoMove {
 };
 
 // Velocity and position update of local particle pl of problem P at swarm
-// iteration it: r1, r2 from Philox counter (it, pl, j/2, 1), words 2(j%2)
-// and 2(j%2)+1; every operation a single rounded multiply or add (the
-// library is built without contraction):
+// iteration it: r1, r2 from Philox counter (it, pl, j/4, 1), word j%4, its
+// high and low 32 bits times 2^-32 (one block serves four dimensions); every
+// operation a single rounded multiply or add (the library is built without
+// contraction):
 //   t = w v; t = t + (c1 r1)(pb - x); t = t + (c2 r2)(g - x);
 //   v = t;   x = min(max(x + v, lo), hi).
 // For the ramp model the positions of t1 and t2 (dimensions 2, 3) are then
@@ -421,13 +422,13 @@ __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_p
     const double *hi = m.hi + P.box_off;
     const double *g = m.gbest_x + P.box_off;
     const size_t base = (size_t)P.theta_off + pl;
-    for (int q = 0; 2 * q < d; ++q) {
+    for (int q = 0; 4 * q < d; ++q) {
         const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
-        for (int jj = 0; jj < 2; ++jj) {
-            const int j = 2 * q + jj;
+        for (int jj = 0; jj < 4; ++jj) {
+            const int j = 4 * q + jj;
             if (j >= d) break;
-            const double r1 = u01(r.w[2 * jj]);
-            const double r2 = u01(r.w[2 * jj + 1]);
+            const double r1 = (double)(uint32_t)(r.w[jj] >> 32) * 0x1.0p-32;
+            const double r2 = (double)(uint32_t)r.w[jj] * 0x1.0p-32;
             const size_t o = base + (size_t)j * n;
             const double xo = m.x[o];
             double tv = m.w * m.v[o];

@@ -58,18 +58,17 @@ __device__ __forceinline__ void store_day(double *o, size_t comp_stride, const S
     o[3 * comp_stride] = state_value(y.D, y.eD);
 }
 
-// Deceased-count costs: (y_i) and (w_i) of the D series, the last of the
-// obs_series blocks.
+// Deceased-count costs: (y_i, w_i) pairs of the D series (the last of the
+// obs_series blocks), one 16-byte LDS read per day.
 __device__ __forceinline__ void stage_d(const FwdArgs &a, const sird_problem &P, int lane,
                                         double *ly)
 {
     const int W = P.n_days;
     const double *y = a.obs + P.obs_off + (size_t)(a.obs_series - 1) * (W + 1);
-    double *lw = ly + a.lds_stride / 2;
     for (int i = lane; i <= W; i += kWave) {
         const double yi = y[i];
-        ly[i] = yi;
-        lw[i] = a.cost.w_rel ? 1.0 / fmax(yi, 1.0) : 1.0;
+        ly[2 * i] = yi;
+        ly[2 * i + 1] = a.cost.w_rel ? 1.0 / fmax(yi, 1.0) : 1.0;
     }
 }
 
@@ -158,10 +157,11 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     double acc[3] = {acc_init<ACC>(), acc_init<ACC>(), acc_init<ACC>()};
     double *tr = nullptr;
     const size_t comp_stride = (size_t)(W + 1) * ld;
-    const double *lw = ly + a.lds_stride / 2;
     if (TRAJ) tr = a.traj + P.traj_off + pc;
-    // the state after day i: stored, or added to the cost
-    auto emit = [&](int i) {
+    // the state after day i: stored, or added to the cost; yw is the day's
+    // (y_i, w_i) of a deceased-count cost, read from LDS before the day's
+    // steps so that the read's latency overlaps them
+    auto emit = [&](int i, double2 yw) {
         if constexpr (TRAJ) {
             if (active) store_day(tr + (size_t)i * ld, comp_stride, y);
         } else if constexpr (NS == 3) {
@@ -170,15 +170,20 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             acc_day<ACC>(acc[1], (row[1] - state_value(y.Rr, y.eR)) * row[4]);
             acc_day<ACC>(acc[2], (row[2] - state_value(y.D, y.eD)) * row[5]);
         } else {
-            acc_day<ACC>(acc[0], (ly[i] - state_value(y.D, y.eD)) * lw[i]);
+            acc_day<ACC>(acc[0], (yw.x - state_value(y.D, y.eD)) * yw.y);
         }
     };
-    if constexpr (NS == 1) {
+    auto day_obs = [&](int i) {
+        double2 yw = make_double2(0.0, 0.0);
+        if constexpr (!TRAJ && NS == 1) yw = make_double2(ly[2 * i], ly[2 * i + 1]);
+        return yw;
+    };
+    if constexpr (!TRAJ && NS == 1) {
         // SSRE leaves out day 0
-        const double e0 = (ly[0] - state_value(y.D, y.eD)) * lw[0];
+        const double e0 = (ly[0] - state_value(y.D, y.eD)) * ly[1];
         acc_day<ACC>(acc[0], a.cost.skip0 ? 0.0 : e0);
     } else {
-        emit(0);
+        emit(0, day_obs(0));
     }
 
     if constexpr (MODEL == SIRD_MODEL_RK4_SEGMENTS) {
@@ -200,9 +205,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             if (!WITH_S) rescale(y, sc);
             for (; day < dend; ++day) {
                 if (WITH_S) rescale(y, sc);
+                const double2 yw = day_obs(day + 1);
 #pragma unroll 2
                 for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
-                emit(day + 1);
+                emit(day + 1, yw);
             }
         }
     } else {
@@ -211,10 +217,11 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         const double h = 1.0 / (double)spd;
         int64_t step = 0;
         for (int day = 0; day < W; ++day) {
+            const double2 yw = day_obs(day + 1);
             // the ramp is evaluated at the start of each step, t = step h
             for (int s = 0; s < spd; ++s, ++step)
                 euler_ramp_step<R, WITH_R>(y, rc, (double)step * h);
-            emit(day + 1);
+            emit(day + 1, yw);
         }
     }
     if (!TRAJ && active) {

@@ -49,8 +49,8 @@ def test_one_step_by_hand(orc):
     orc.pso_move(s, it, w, c1, c2, lo, hi, seed=5, stream=2)
     for p in range(2):
         for j in range(3):
-            b = np_block(it, p, j // 2, 1, 5, 2)
-            r1, r2 = u(b[2 * (j % 2)]), u(b[2 * (j % 2) + 1])
+            word = int(np_block(it, p, j // 4, 1, 5, 2)[j % 4])
+            r1, r2 = (word >> 32) * 2.0 ** -32, (word & 0xFFFFFFFF) * 2.0 ** -32
             t = w * v0[p, j]
             t = t + (c1 * r1) * (s.pbest_x[p, j] - x0[p, j])
             t = t + (c2 * r2) * (s.gbest_x[j] - x0[p, j])
