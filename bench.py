@@ -45,8 +45,8 @@ PEAK_FP64_VECTOR = 78.6e12  # MI355X, FLOP/s
 # 1.0), recorded with the hash of the kernel sources they were taken on;
 # reported only while the sources match.
 MEASURED_TRAFFIC = {
-    "c3": {"bytes": 2.0 * 139660.6 * 1024 + 1.0 * 173803.2 * 1024,
-           "sources": "30747e657397fe8c",
+    "c3": {"bytes": 2.0 * 135385.9 * 1024 + 1.0 * 173803.2 * 1024,
+           "sources": "c8c35d68b1d18d1a",
            "summary": "profiles/k_forward_fused_batched_512x1024.md"},
 }
 

@@ -44,6 +44,8 @@ struct StepConst {
     R hb;     // b h
     R h2b;    // b h / 2
     R h6b;    // b h / 6
+    R h2lam;  // h/2 * lam
+    R hlam;   // h * lam
 };
 
 // The state of one particle.  In float, S, I, R and D carry the running
@@ -104,21 +106,24 @@ __device__ __forceinline__ void unscale(SirdState<R> &y, const StepConst<R> &k)
 template <typename R, bool WITH_R, bool WITH_S = true>
 __device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
 {
+    // Stage I_{k+1} = I + c h (p_k - lam I_k) is formed as
+    // fma(c h, p_k, I - c h lam I_k): the second term does not wait for
+    // p_k, which takes three operations off the dependent chain of a step.
     const R s = y.s, I = y.I;
     const R p1 = s * I;
-    const R q1 = fma(-k.lam, I, p1);
+    const R c1 = fma(-k.h2lam, I, I);
     const R s2 = fma(-k.h2b, p1, s);
-    const R I2 = fma(k.h2, q1, I);
+    const R I2 = fma(k.h2, p1, c1);
 
     const R p2 = s2 * I2;
-    const R q2 = fma(-k.lam, I2, p2);
+    const R c2 = fma(-k.h2lam, I2, I);
     const R s3 = fma(-k.h2b, p2, s);
-    const R I3 = fma(k.h2, q2, I);
+    const R I3 = fma(k.h2, p2, c2);
 
     const R p3 = s3 * I3;
-    const R q3 = fma(-k.lam, I3, p3);
+    const R c3 = fma(-k.hlam, I3, I);
     const R s4 = fma(-k.hb, p3, s);
-    const R I4 = fma(k.h, q3, I);
+    const R I4 = fma(k.h, p3, c3);
 
     const R p4 = s4 * I4;
 
@@ -151,6 +156,8 @@ __device__ __forceinline__ StepConst<R> step_const(double gamma, double mu, int 
     k.h6lam = (R)(h6 * (gamma + mu));
     k.h6mu = (R)(h6 * mu);
     k.h6g = (R)(h6 * gamma);
+    k.h2lam = (R)(0.5 * h * (gamma + mu));
+    k.hlam = (R)(h * (gamma + mu));
     k.b = k.hb = k.h2b = k.h6b = R(0);
     return k;
 }
