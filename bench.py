@@ -13,7 +13,7 @@ of the dominant kernel (the forward integration, timed per launch with HIP
 events on the stream it runs on) and the oracle's throughput on the host
 cores on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--dtype f64|f32]
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|paper] [--dtype f64|f32]
 """
 from __future__ import annotations
 
@@ -38,6 +38,9 @@ C3_LAUNCH = dict(block=256, persistent=2048)
 # into the same kernel are not counted.
 FLOPS_PER_STEP = 38
 VALU_PER_STEP = 23
+# The paper's scheme (forward Euler with the beta ramp): the ramp costs a
+# subtract and an fma (3 flops), the step 2 mul + 5 fma (12 flops).
+FLOPS_PER_STEP_EULER_RAMP = 15
 PEAK_FP64_VECTOR = 78.6e12  # MI355X, FLOP/s
 
 # HBM bytes per fused k_forward launch from rocprofv3 FETCH_SIZE /
@@ -73,14 +76,18 @@ def build_workload(name, dtype):
     elif name == "c1":
         wl = synth.c1()
         launch = dict(block=64, persistent=0)
+    elif name == "paper":
+        wl = synth.paper()
+        launch = dict(block=64, persistent=0)
     else:
         raise SystemExit(f"unknown workload {name}")
+    three = wl.loss.startswith("ird")
     specs = [S.ProblemSpec.from_fit(f) for f in wl.fits]
-    b = S.Batch(specs, dtype=dtype, **launch)
+    b = S.Batch(specs, dtype=dtype, obs_series=3 if three else 1, **launch)
     params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
                          wl.c2, wl.seed)
     sw = S.Swarm(b)
-    obs = b.pack_obs([f.y for f in wl.fits])
+    obs = b.pack_obs([f.obs3 if three else f.y for f in wl.fits])
     return wl, b, params, sw, obs
 
 
@@ -93,13 +100,16 @@ def cpu_baseline(wl, budget_s):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rng = np.random.default_rng(0)
     thetas = [f.lo + rng.uniform(0, 1, (f.n_part, f.d)) * (f.hi - f.lo) for f in wl.fits]
-    probs = [oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0) for f in wl.fits]
+    probs = [oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0,
+                            model=1 if f.model == "euler_ramp" else 0) for f in wl.fits]
+    three = wl.loss.startswith("ird")
     work = 0
     reps = 0
     t0 = time.perf_counter()
     while True:
         for f, th, prob in zip(wl.fits, thetas, probs):
-            oracle.loss_batch(prob, th, f.y, wl.loss, nthreads=threads)
+            oracle.loss_batch_model(prob, th, f.obs3 if three else f.y, wl.loss,
+                                    nthreads=threads)
             work += f.n_part * f.T
             if time.perf_counter() - t0 > budget_s:
                 break
@@ -111,7 +121,7 @@ def cpu_baseline(wl, budget_s):
     w1 = 0
     t1 = time.perf_counter()
     for f, th, prob in zip(wl.fits, thetas, probs):
-        oracle.loss_batch(prob, th[:64], f.y, wl.loss, nthreads=1)
+        oracle.loss_batch_model(prob, th[:64], f.obs3 if three else f.y, wl.loss, nthreads=1)
         w1 += min(64, f.n_part) * f.T
         if time.perf_counter() - t1 > budget_s / 5:
             break
@@ -237,7 +247,8 @@ def main():
     traffic = None
     if meas and meas["sources"] == kernel_source_hash() and args.dtype == "f64":
         traffic = meas["bytes"]
-    achieved = FLOPS_PER_STEP * steps_per_iter / (fwd_ms / 1e3)
+    flops_step = FLOPS_PER_STEP_EULER_RAMP if args.workload == "paper" else FLOPS_PER_STEP
+    achieved = flops_step * steps_per_iter / (fwd_ms / 1e3)
     out = {
         "metric": METRIC,
         "value": value,
@@ -255,7 +266,10 @@ def main():
             "workload": {"c3": "batched uneven fits: 512 regions x 1024 particles, "
                                "W 28..365 days, 14-day beta segments, dt 0.1 day",
                          "c2": "one fit: 8192 particles, 180 days, 13 beta segments, dt 0.1",
-                         "c1": "one fit: 256 particles, 60 days, constant beta, dt 0.1"
+                         "c1": "one fit: 256 particles, 60 days, constant beta, dt 0.1",
+                         "paper": "the paper's timing case: one fit, 10000 particles, 92 days, "
+                                  "forward Euler at one step per day with the beta ramp, "
+                                  "F_IRD^MXSE"
                          }[args.workload],
             "problems": b.n_prob,
             "particles": b.total_particles,
@@ -264,7 +278,9 @@ def main():
             "launch": {"block": b.c.block, "persistent": b.c.persistent},
         },
         "roofline": {
-            "kernel": "k_forward fused (pso_evaluate: move + RK4 + cost + pbest)",
+            "kernel": ("k_forward fused (pso_evaluate: move + Euler with the beta ramp + "
+                       "F_IRD^MXSE + pbest)" if args.workload == "paper" else
+                       "k_forward fused (pso_evaluate: move + RK4 + cost + pbest)"),
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP64_VECTOR / 1e12,
@@ -274,8 +290,9 @@ def main():
             "traffic_unit": "bytes per launch",
             "algorithmic_bytes": alg_bytes,
             "kernel_ms": fwd_ms,
-            "flops_per_particle_step": FLOPS_PER_STEP,
-            "valu_issue_frac": (VALU_PER_STEP * steps_per_iter / (fwd_ms / 1e3)) /
+            "flops_per_particle_step": flops_step,
+            "valu_issue_frac": None if args.workload == "paper" else
+                               (VALU_PER_STEP * steps_per_iter / (fwd_ms / 1e3)) /
                                (256 * 4 * 16 * 2.4e9),
         },
         "wall_s": wall,

@@ -138,10 +138,14 @@ __device__ __forceinline__ bool better(double f, int i, double bf, int bi)
 
 // Global best of one problem per block: argmin of pbest_f, then replace the
 // previous global best only on strict improvement, and record the history.
-__global__ void __launch_bounds__(256) k_pso_gbest(PsoArgs a)
+// 1024 threads, each with up to 8 loads in flight, so that a problem of
+// ten thousand particles costs about two memory latencies.
+constexpr int kGbestBlock = 1024;
+
+__global__ void __launch_bounds__(kGbestBlock) k_pso_gbest(PsoArgs a)
 {
-    __shared__ double sf[256 / kWave];
-    __shared__ int si[256 / kWave];
+    __shared__ double sf[kGbestBlock / kWave];
+    __shared__ int si[kGbestBlock / kWave];
     __shared__ int s_take;
     const int r = blockIdx.x;
     const sird_problem P = a.probs[r];
@@ -149,6 +153,7 @@ __global__ void __launch_bounds__(256) k_pso_gbest(PsoArgs a)
     const int tid = threadIdx.x;
     double bf = INFINITY;
     int bi = n;  // sentinel above every index
+#pragma unroll 8
     for (int p = tid; p < n; p += blockDim.x) {
         const double f = a.st.pbest_f[P.p_off + p];
         if (better(f, p, bf, bi)) {
@@ -197,13 +202,19 @@ __global__ void __launch_bounds__(256) k_pso_gbest(PsoArgs a)
             a.st.gbest_x[P.box_off + j] = a.st.pbest_x[(size_t)P.theta_off + (size_t)j * n + b];
     }
     if (a.gbest_advance && tid == 0) {
-        // the last block out advances the iteration (all blocks read it)
-        __threadfence();
-        const unsigned long long done =
-            atomicAdd((unsigned long long *)&a.st.iter[1], 1ull);
-        if (done == (unsigned long long)gridDim.x - 1) {
-            atomicExch((unsigned long long *)&a.st.iter[1], 0ull);
-            atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it + 1));
+        if (gridDim.x == 1) {
+            // one problem: this block read the iteration before the
+            // barrier above and is the only reader
+            a.st.iter[0] = it + 1;
+        } else {
+            // the last block out advances the iteration (all blocks read it)
+            __threadfence();
+            const unsigned long long done =
+                atomicAdd((unsigned long long *)&a.st.iter[1], 1ull);
+            if (done == (unsigned long long)gridDim.x - 1) {
+                atomicExch((unsigned long long *)&a.st.iter[1], 0ull);
+                atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it + 1));
+            }
         }
     }
 }
@@ -259,7 +270,7 @@ int pso_step_enqueue(const sird_batch *b, const pso_params *p, const pso_state *
     PsoArgs a = make_args(b, p, st);
     const int tb = tile_blocks(b->n_tiles);
     if (tb > 0) hipLaunchKernelGGL(k_pso_pbest, dim3(tb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(kGbestBlock), 0, s, a);
     // The move kernel always runs (at least one block) so the iteration
     // counter advances even for a batch without particles.
     hipLaunchKernelGGL(k_pso_move, dim3(tb > 0 ? tb : 1), dim3(256), 0, s, a);
@@ -287,7 +298,7 @@ static int gbest_enqueue(const sird_batch *b, const pso_params *p, const pso_sta
 {
     PsoArgs a = make_args(b, p, st);
     a.gbest_advance = 1;
-    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(kGbestBlock), 0, s, a);
     return hip_status(hipGetLastError(), "pso_gbest");
 }
 
