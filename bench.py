@@ -169,6 +169,8 @@ def extras():
         res[f"paper_euler_ramp_ird_mxse_10000x92d_{dt}"] = X.paper_iteration(synth.paper(), dt)
     print("# extras: repetition study ...", file=sys.stderr, flush=True)
     res["rep_1000x10000x36d"] = X.repetition(synth.rep())
+    print("# extras: window-wise calibration ...", file=sys.stderr, flush=True)
+    res["windows_139x10000x36d"] = X.window_wise(synth.windows())
     print("# extras: rolling windows ...", file=sys.stderr, flush=True)
     z = synth.c5_series()
     res["c5_rolling_52x16x4096"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,

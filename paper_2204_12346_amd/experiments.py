@@ -2,7 +2,7 @@
 throughput, gradients per second, time-to-fit of plain swarm vs swarm +
 adjoint refinement, the rolling-window fit + 14-day forecast, the paper's
 own timing case (one swarm iteration of its Euler + ramp model under
-F_IRD^MXSE) and its repetition study.
+F_IRD^MXSE), its window-wise calibration and its repetition study.
 
 Each function builds its batch from ``synth`` inputs, times device work with
 HIP events (or wall clock where the protocol is wall time) and returns a
@@ -388,3 +388,48 @@ def repetition(wl, horizon=21, launch=None) -> Dict:
             "particle_steps_per_s": b.particle_steps * wl.iters / t_pso,
             "loss": q(L), "params": {n: q(th[:, j]) for j, n in enumerate(names)},
             f"extension_day_{horizon}_bands": bands}
+
+
+def window_wise(wl, launch=None) -> Dict:
+    """The window-wise calibration (Sec. 3.1, 4.1): every window of the
+    series in one batch through wl.iters swarm iterations, then the fitted
+    I, R, D of each window's global best.  Returns the time, R^2 of D (the
+    paper's goodness-of-fit statistic; also of I and R) over the windows,
+    and the fitting bands: per day, the spread (max - min) of the fitted D
+    over the windows that cover it, relative to the observed D."""
+    b, params, sw, obs = _setup(wl, "f64", launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pso_init(b, params, sw)
+    sird_pso_iterate(b, params, sw, obs, wl.loss, wl.iters)
+    torch.cuda.synchronize()
+    t_pso = time.perf_counter() - t0
+    th = b.unpack_box(sw.gbest_x)
+    trajs = fit.forecast(b.specs, [t[None, :] for t in th], 0, device=b.device)
+    r2s = {"D": [], "I": [], "R": []}
+    delta = 3
+    T = len(wl.fits) * delta + wl.fits[0].W
+    lo_band = np.full(T, np.inf)
+    hi_band = np.full(T, -np.inf)
+    obs_D = np.full(T, np.nan)
+    for i, (f, tr) in enumerate(zip(wl.fits, trajs)):
+        o = np.asarray(f.obs3).reshape(3, -1)
+        for c, name in ((1, "I"), (2, "R"), (3, "D")):
+            r2s[name].append(r2(o[c - 1], tr[0, c]))
+        days = slice(delta * i, delta * i + f.W + 1)
+        lo_band[days] = np.minimum(lo_band[days], tr[0, 3])
+        hi_band[days] = np.maximum(hi_band[days], tr[0, 3])
+        obs_D[days] = o[2]
+    ok = np.isfinite(lo_band) & (obs_D > 0)
+    width = (hi_band[ok] - lo_band[ok]) / obs_D[ok]
+
+    def q(v):
+        return {p: float(np.quantile(v, p / 100)) for p in (5, 50, 95)}
+
+    return {"windows": b.n_prob, "particles_per_window": wl.fits[0].n_part,
+            "iterations": wl.iters, "seconds_swarm": t_pso,
+            "particle_steps_per_s": b.particle_steps * wl.iters / t_pso,
+            "r2_D_mean": float(np.mean(r2s["D"])), "r2_D": q(r2s["D"]),
+            "r2_I_mean": float(np.mean(r2s["I"])), "r2_R_mean": float(np.mean(r2s["R"])),
+            "final_loss": q(sw.gbest_f.cpu().numpy()),
+            "band_width_rel_D": q(width)}

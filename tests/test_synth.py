@@ -20,7 +20,7 @@ def _maker():
 
 def test_stored_series_regenerate_bitwise(orc):
     m = _maker()
-    for name in ("c1", "c2", "c4", "c5", "c3"):
+    for name in ("c1", "c2", "c4", "c5", "c3", "paper", "windows"):
         fresh = m.MAKERS[name]()
         stored = synth._load(name)
         assert set(fresh) == set(stored)
@@ -42,3 +42,21 @@ def test_workload_shapes():
     assert len(c5.fits) == 32 and c5.fits[-1].stream == 16 * 51 + 15
     for f in synth.c1().fits + synth.c2().fits + c3.fits:
         assert f.y.shape == (f.W + 1,) and np.all(np.diff(f.y) >= 0) and f.y[0] == f.D0
+
+
+def test_paper_shaped_workloads():
+    wl = synth.paper()
+    f = wl.fits[0]
+    assert (f.W, f.spd, f.K, f.n_part, wl.iters, wl.loss) == (92, 1, 4, 10000, 100, "ird_mxse")
+    assert (wl.w, wl.c1, wl.c2) == (0.5, 0.5, 0.5)
+    o = f.obs3.reshape(3, -1)
+    assert o.shape == (3, 93) and tuple(o[:, 0]) == (f.lo[6], f.R0, f.D0)
+    assert np.all(np.diff(o[1]) >= 0) and np.all(np.diff(o[2]) >= 0)
+    ww = synth.windows()
+    assert len(ww.fits) == 139  # floor(1 + (449 - 35)/3)
+    for i, g in enumerate(ww.fits[::23]):
+        assert g.W == 35 and g.lo[6] == g.hi[6] and g.hi[2] == g.hi[3] == 28.0
+    assert [g.stream for g in ww.fits] == list(range(139))
+    r = synth.rep(n_rep=3)
+    assert all(np.array_equal(g.obs3, r.fits[0].obs3) for g in r.fits)
+    assert [g.stream for g in r.fits] == [0, 1, 2]
