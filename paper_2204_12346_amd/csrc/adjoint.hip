@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
         // a segment start, rescale at a day start, then the step
         int k = 0;
         long next_seg = (K > 1) ? (long)SS : T + 1;
-        set_beta(sc, th[0], N);
+        set_beta(sc, th[0], invN);
         long next_ck = 0;
         int m = 0;
         int sd = 0, day = 0;
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             if (st == next_seg) {
                 ++k;
                 next_seg = (k < K - 1) ? next_seg + SS : T + 1;
-                set_beta(sc, th[(size_t)k * ld], N);
+                set_beta(sc, th[(size_t)k * ld], invN);
             }
             if (sd == 0) rescale(y, sc);
             if (st == next_ck) {
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     double aD = cost_grad(a.kind, W, W, DW, ly[W], lw[W], imax);
     Grad g{0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
-    set_beta(sc, th[(size_t)kr * ld], N);
+    set_beta(sc, th[(size_t)kr * ld], invN);
     int seg_lo = kr * SS;  // first step of segment kr
 
     const int Ti = (int)T;  // at most 2^30 (checked on the host)
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
             int kf = seg_of(n0, SS, K);
             StepConst<double> sf = sc;
-            set_beta(sf, th[(size_t)kf * ld], N);
+            set_beta(sf, th[(size_t)kf * ld], invN);
             int next_seg = (kf < K - 1) ? (kf + 1) * SS : Ti + 1;
             int sd = n0 % spd;
             for (int c = 1; c < n_chunks; ++c) {
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                     if (st == next_seg) {
                         ++kf;
                         next_seg = (kf < K - 1) ? next_seg + SS : Ti + 1;
-                        set_beta(sf, th[(size_t)kf * ld], N);
+                        set_beta(sf, th[(size_t)kf * ld], invN);
                     }
                     if (sd == 0) rescale(yr, sf);
                     rk4_step<double, false>(yr, sf);
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             if (c > 0) load_chunk(c - 1);
             int kf = seg_of(cs, SS, K);
             StepConst<double> sf = sc;  // the reverse's segment: no reload
-            if (kf != kr) set_beta(sf, th[(size_t)kf * ld], N);
+            if (kf != kr) set_beta(sf, th[(size_t)kf * ld], invN);
             int next_seg = (kf < K - 1) ? (kf + 1) * SS : Ti + 1;
             double Sa[kChunk], Ia[kChunk];
 #pragma unroll
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                     if (cs + j == next_seg) {
                         ++kf;
                         next_seg = (kf < K - 1) ? next_seg + SS : Ti + 1;
-                        set_beta(sf, th[(size_t)kf * ld], N);
+                        set_beta(sf, th[(size_t)kf * ld], invN);
                     }
                     if (sd == 0) rescale(yr, sf);
                     Sa[j] = yr.S;
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                         g.beta = 0.0;
                         --kr;
                         seg_lo = kr * SS;
-                        set_beta(sc, th[(size_t)kr * ld], N);
+                        set_beta(sc, th[(size_t)kr * ld], invN);
                     }
                     rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, invN, h3, g);
                     if (day[j] >= 0) {

@@ -192,6 +192,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         // the compensated float state carry S
         constexpr bool WITH_S = TRAJ || sizeof(R) != 8;
         StepConst<R> sc = step_const<R>(gamma, mu, spd);
+        const double invN = 1.0 / N;
         const int seg = P.seg_days;
         int day = 0;
         double beta_next = th[0];
@@ -201,7 +202,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             const int dend = (k == K - 1) ? W : (int)min((long)W, (long)(k + 1) * seg);
             if (day >= dend) continue;
             if (!WITH_S && day > 0) unscale(y, sc);
-            set_beta(sc, beta_k, N);
+            set_beta(sc, beta_k, invN);
             if (!WITH_S) rescale(y, sc);
             for (; day < dend; ++day) {
                 if (WITH_S) rescale(y, sc);
