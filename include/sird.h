@@ -151,6 +151,9 @@ typedef struct sird_batch {
                                 (I, R, D); set by sird_batch_plan          */
     int32_t models;          /* bit m set when some problem has model m;
                                 set by sird_batch_plan                     */
+    int32_t max_part;        /* max n_part over problems; set by
+                                sird_batch_plan (picks the global-best
+                                kernel's shape)                            */
 } sird_batch;
 
 /* Coefficients of the swarm, Sec. 3.3 (inertia, cognitive, social), the

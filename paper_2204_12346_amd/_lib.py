@@ -54,7 +54,7 @@ class sird_batch(ctypes.Structure):
         ("probs", ctypes.c_void_p), ("tiles", ctypes.c_void_p), ("sched", ctypes.c_void_p),
         ("dtype", ctypes.c_int32), ("block", ctypes.c_int32),
         ("persistent", ctypes.c_int32), ("obs_series", ctypes.c_int32),
-        ("models", ctypes.c_int32),
+        ("models", ctypes.c_int32), ("max_part", ctypes.c_int32),
     ]
 
 

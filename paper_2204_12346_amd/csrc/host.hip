@@ -161,13 +161,14 @@ extern "C" int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host
                                    traj_len, box_len, obs_series);
     if (st != SIRD_OK) return st;
     int64_t tiles = 0;
-    int max_days = 0, max_d = 0, models = 0;
+    int max_days = 0, max_d = 0, models = 0, max_part = 0;
     int64_t max_steps = 0;
     for (int r = 0; r < n_prob; ++r) {
         const sird_problem &p = probs_host[r];
         models |= 1 << p.model;
         tiles += (p.n_part + kTileParticles - 1) / kTileParticles;
         max_days = std::max(max_days, p.n_days);
+        max_part = std::max(max_part, p.n_part);
         max_d = std::max(max_d, p.n_seg + 3);
         max_steps = std::max(max_steps, (int64_t)p.n_days * p.steps_per_day);
     }
@@ -190,5 +191,6 @@ extern "C" int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host
     batch->sched = sched_dev;
     batch->obs_series = obs_series;
     batch->models = models;
+    batch->max_part = max_part;
     return SIRD_OK;
 }

@@ -136,11 +136,84 @@ __device__ __forceinline__ bool better(double f, int i, double bf, int bi)
     return f < bf || (f == bf && i < bi);
 }
 
-// Global best of one problem per block: argmin of pbest_f, then replace the
-// previous global best only on strict improvement, and record the history.
-// 1024 threads, each with up to 8 loads in flight, so that a problem of
-// ten thousand particles costs about two memory latencies.
+// Global best of a problem: argmin of pbest_f (lowest index among equal
+// values), then replace the previous global best only on strict
+// improvement, and record the history.
+
+// Strided argmin over pbest_f of one problem, with up to 8 loads in flight.
+__device__ __forceinline__ void gbest_scan(const double *f, int n, int first, int stride,
+                                           double &bf, int &bi)
+{
+    bf = INFINITY;
+    bi = n;  // sentinel above every index
+#pragma unroll 8
+    for (int p = first; p < n; p += stride) {
+        const double v = f[p];
+        if (better(v, p, bf, bi)) {
+            bf = v;
+            bi = p;
+        }
+    }
+}
+
+// Butterfly over the wavefront: every lane ends with the wavefront's argmin.
+__device__ __forceinline__ void wave_argmin(double &bf, int &bi)
+{
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double of = __shfl_xor(bf, off);
+        const int oi = __shfl_xor(bi, off);
+        if (better(of, oi, bf, bi)) {
+            bf = of;
+            bi = oi;
+        }
+    }
+}
+
+// Compare the problem's argmin (bf, bi) with its global best and record the
+// history row of iteration it; one thread.  Returns whether bi was taken.
+__device__ __forceinline__ bool gbest_commit(const PsoArgs &a, int r, int n, double bf, int bi,
+                                             uint64_t it)
+{
+    bool take = false;
+    if (n > 0 && bi < n && bf < a.st.gbest_f[r]) {
+        a.st.gbest_f[r] = bf;
+        a.st.gbest_idx[r] = bi;
+        take = true;
+    }
+    if (a.st.hist_f && (int64_t)it < a.st.hist_len) {
+        a.st.hist_f[(size_t)it * a.n_prob + r] = a.st.gbest_f[r];
+        if (a.st.hist_idx) a.st.hist_idx[(size_t)it * a.n_prob + r] = a.st.gbest_idx[r];
+    }
+    return take;
+}
+
+// After every block has read iter[0] (= it): advance it once.  One thread
+// per block; the block must have passed a barrier after its read.
+__device__ __forceinline__ void gbest_advance_iteration(const PsoArgs &a, uint64_t it)
+{
+    if (gridDim.x == 1) {
+        // this block is the only reader
+        a.st.iter[0] = it + 1;
+        return;
+    }
+    // the last block out advances the iteration
+    __threadfence();
+    const unsigned long long done = atomicAdd((unsigned long long *)&a.st.iter[1], 1ull);
+    if (done == (unsigned long long)gridDim.x - 1) {
+        atomicExch((unsigned long long *)&a.st.iter[1], 0ull);
+        atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it + 1));
+    }
+}
+
+// Problems of more than kGbestWaveMax particles: one block per problem,
+// 1024 threads, so that ten thousand particles cost about two memory
+// latencies.
 constexpr int kGbestBlock = 1024;
+// Smaller problems: one wavefront per problem and four problems per block,
+// so that a batch of many problems needs few blocks (every block takes one
+// same-address atomic to advance the iteration, and those serialise).
+constexpr int kGbestWaveMax = 4096;
+constexpr int kGbestWaveBlock = 256;
 
 __global__ void __launch_bounds__(kGbestBlock) k_pso_gbest(PsoArgs a)
 {
@@ -151,24 +224,10 @@ __global__ void __launch_bounds__(kGbestBlock) k_pso_gbest(PsoArgs a)
     const sird_problem P = a.probs[r];
     const int n = P.n_part;
     const int tid = threadIdx.x;
-    double bf = INFINITY;
-    int bi = n;  // sentinel above every index
-#pragma unroll 8
-    for (int p = tid; p < n; p += blockDim.x) {
-        const double f = a.st.pbest_f[P.p_off + p];
-        if (better(f, p, bf, bi)) {
-            bf = f;
-            bi = p;
-        }
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        const double of = __shfl_xor(bf, off);
-        const int oi = __shfl_xor(bi, off);
-        if (better(of, oi, bf, bi)) {
-            bf = of;
-            bi = oi;
-        }
-    }
+    double bf;
+    int bi;
+    gbest_scan(a.st.pbest_f + P.p_off, n, tid, blockDim.x, bf, bi);
+    wave_argmin(bf, bi);
     if ((tid & (kWave - 1)) == 0) {
         sf[tid / kWave] = bf;
         si[tid / kWave] = bi;
@@ -181,18 +240,8 @@ __global__ void __launch_bounds__(kGbestBlock) k_pso_gbest(PsoArgs a)
                 bf = sf[k];
                 bi = si[k];
             }
-        int take = 0;
-        if (n > 0 && bi < n && bf < a.st.gbest_f[r]) {
-            a.st.gbest_f[r] = bf;
-            a.st.gbest_idx[r] = bi;
-            take = 1;
-        }
-        s_take = take;
+        s_take = gbest_commit(a, r, n, bf, bi, it) ? 1 : 0;
         si[0] = bi;
-        if (a.st.hist_f && (int64_t)it < a.st.hist_len) {
-            a.st.hist_f[(size_t)it * a.n_prob + r] = a.st.gbest_f[r];
-            if (a.st.hist_idx) a.st.hist_idx[(size_t)it * a.n_prob + r] = a.st.gbest_idx[r];
-        }
     }
     __syncthreads();
     if (s_take) {
@@ -201,22 +250,45 @@ __global__ void __launch_bounds__(kGbestBlock) k_pso_gbest(PsoArgs a)
         for (int j = tid; j < d; j += blockDim.x)
             a.st.gbest_x[P.box_off + j] = a.st.pbest_x[(size_t)P.theta_off + (size_t)j * n + b];
     }
-    if (a.gbest_advance && tid == 0) {
-        if (gridDim.x == 1) {
-            // one problem: this block read the iteration before the
-            // barrier above and is the only reader
-            a.st.iter[0] = it + 1;
-        } else {
-            // the last block out advances the iteration (all blocks read it)
-            __threadfence();
-            const unsigned long long done =
-                atomicAdd((unsigned long long *)&a.st.iter[1], 1ull);
-            if (done == (unsigned long long)gridDim.x - 1) {
-                atomicExch((unsigned long long *)&a.st.iter[1], 0ull);
-                atomicExch((unsigned long long *)&a.st.iter[0], (unsigned long long)(it + 1));
-            }
+    if (a.gbest_advance && tid == 0) gbest_advance_iteration(a, it);
+}
+
+__global__ void __launch_bounds__(kGbestWaveBlock) k_pso_gbest_waves(PsoArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    const uint64_t it = a.st.iter[0];
+    if (r < a.n_prob) {
+        const sird_problem P = a.probs[r];
+        const int n = P.n_part;
+        double bf;
+        int bi;
+        gbest_scan(a.st.pbest_f + P.p_off, n, lane, kWave, bf, bi);
+        wave_argmin(bf, bi);
+        int take = 0;
+        if (lane == 0) take = gbest_commit(a, r, n, bf, bi, it) ? 1 : 0;
+        if (wave_uniform(take)) {
+            const int d = P.n_seg + 3;
+            for (int j = lane; j < d; j += kWave)
+                a.st.gbest_x[P.box_off + j] =
+                    a.st.pbest_x[(size_t)P.theta_off + (size_t)j * n + bi];
         }
     }
+    if (!a.gbest_advance) return;
+    __syncthreads();
+    if (threadIdx.x == 0) gbest_advance_iteration(a, it);
+}
+
+static int launch_gbest(const sird_batch *b, const PsoArgs &a, hipStream_t s)
+{
+    if (b->max_part <= kGbestWaveMax) {
+        const int ppb = kGbestWaveBlock / kWave;
+        hipLaunchKernelGGL(k_pso_gbest_waves, dim3((b->n_prob + ppb - 1) / ppb),
+                           dim3(kGbestWaveBlock), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(kGbestBlock), 0, s, a);
+    }
+    return SIRD_OK;
 }
 
 // Velocity and position update with counter iter[0] - it_back; then, if
@@ -270,7 +342,7 @@ int pso_step_enqueue(const sird_batch *b, const pso_params *p, const pso_state *
     PsoArgs a = make_args(b, p, st);
     const int tb = tile_blocks(b->n_tiles);
     if (tb > 0) hipLaunchKernelGGL(k_pso_pbest, dim3(tb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(kGbestBlock), 0, s, a);
+    launch_gbest(b, a, s);
     // The move kernel always runs (at least one block) so the iteration
     // counter advances even for a batch without particles.
     hipLaunchKernelGGL(k_pso_move, dim3(tb > 0 ? tb : 1), dim3(256), 0, s, a);
@@ -298,7 +370,7 @@ static int gbest_enqueue(const sird_batch *b, const pso_params *p, const pso_sta
 {
     PsoArgs a = make_args(b, p, st);
     a.gbest_advance = 1;
-    hipLaunchKernelGGL(k_pso_gbest, dim3(b->n_prob), dim3(kGbestBlock), 0, s, a);
+    launch_gbest(b, a, s);
     return hip_status(hipGetLastError(), "pso_gbest");
 }
 

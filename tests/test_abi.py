@@ -177,7 +177,7 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     assert b.c.max_days == 45 and b.c.max_d == 7 and b.c.max_steps == 300
     assert b.total_particles == 165 and b.theta_len == 6 * 100 + 7 * 65
     assert b.obs_len == 31 + 13 + 46 and b.box_len == 6 + 5 + 7
-    assert b.c.obs_series == 1 and b.c.models == 1
+    assert b.c.obs_series == 1 and b.c.models == 1 and b.c.max_part == 100
     lib = L.lib()
     dummy = torch.zeros(8, dtype=torch.float64)
     for kind in (-1, 9):

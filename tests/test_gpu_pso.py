@@ -51,10 +51,14 @@ def test_init_bitwise():
     assert sw.iter.cpu().tolist() == [0, 0]
 
 
-def test_step_lockstep_bitwise():
+@pytest.mark.parametrize("regions,n_parts", [
+    ([3, 4], [200, 77]),                     # global best: one wavefront per problem, one block
+    ([3, 4], [5000, 77]),                    # one block per problem (a problem above 4096)
+    (list(range(9)), [64, 1, 130, 200, 77, 5, 300, 64, 90]),  # wavefronts, three blocks
+])
+def test_step_lockstep_bitwise(regions, n_parts):
     """Same f and state on both sides -> bitwise equal bests and moves."""
-    wl = synth.c3(regions=[3, 4])
-    n_parts = [200, 77]
+    wl = synth.c3(regions=regions)
     b = make_batch(wl.fits, n_parts)
     params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], w=0.7, c1=1.5,
                          c2=1.5, seed=wl.seed)
@@ -64,9 +68,10 @@ def test_step_lockstep_bitwise():
     refs = [oracle.pso_init(n, f.lo, f.hi, wl.seed, f.stream) for f, n in zip(wl.fits, n_parts)]
     for it in range(6):
         fs = [rng.uniform(0, 10, n) for n in n_parts]
-        for r in range(2):
-            fs[r][rng.integers(0, n_parts[r], 5)] = np.nan
-            fs[r][:3] = fs[r][3]  # exact ties
+        for r in range(len(n_parts)):
+            if n_parts[r] > 5:
+                fs[r][rng.integers(0, n_parts[r], 5)] = np.nan
+                fs[r][:3] = fs[r][3]  # exact ties
         f_all = np.concatenate(fs)
         sw.f.copy_(torch.from_numpy(f_all).to(sw.f.device))
         S.pso_step(b, params, sw)
