@@ -52,7 +52,6 @@ struct BwdArgs {
     double *ws;
     int64_t P;  // slot stride of the workspace (total particles)
     int n_tiles;
-    int kind;
     int obs_series;  // 1 or 3; the deceased counts are the last series
     int s;          // checkpoint interval in steps
     int n_ck_max;   // checkpoints per particle
@@ -77,29 +76,30 @@ __device__ __forceinline__ double cost_grad(int kind, int i, int W, double D, do
 }
 
 struct Grad {
-    double beta;   // of the current segment
+    double beta;   // of the current segment, times N: sum of S_s I_s u over its stages
     double gamma;
     double mu;
 };
 
 // One stage of the reverse step: Ybar = J(Y_s)^T kbar and the parameter
-// contributions; mkD = mu * kbar_s.D.
+// contributions; mkD = mu * kbar_s.D.  Ybar.S = b v with v = I_s u is
+// returned as v: the next stage's kbar.S and the final sum take b in their
+// constants.
 __device__ __forceinline__ void stage_adjoint(double Ss, double Is, double bs, double kS,
-                                              double kI, double mkD, double lam, double b,
-                                              double invN, double &YS, double &YI, Grad &g,
-                                              double &tI)
+                                              double kI, double mkD, double lam, double &v,
+                                              double &YI, Grad &g, double &tI)
 {
     const double u = kI - kS;
-    YS = (b * Is) * u;
+    v = Is * u;
     YI = fma(bs, u, fma(-lam, kI, mkD));
-    g.beta = fma((Ss * invN) * Is, u, g.beta);
+    g.beta = fma(Ss, v, g.beta);
     tI = fma(Is, kI, tI);
 }
 
 // One reverse step: (aS, aI) <- a_n from a_{n+1}; aD unchanged.
 __device__ __forceinline__ void rk4_adjoint_step(double S, double I, double &aS, double &aI,
                                                  double aD, const StepConst<double> &k,
-                                                 double mu, double invN, double h3, Grad &g)
+                                                 double mu, double h3, Grad &g)
 {
     // recompute the stages
     const double bs1 = k.b * S;
@@ -123,28 +123,27 @@ __device__ __forceinline__ void rk4_adjoint_step(double S, double I, double &aS,
     const double m6 = k.h6 * muaD;  // mu kbar_s.D for s = 1, 4
     const double m3 = h3 * muaD;    // mu kbar_s.D for s = 2, 3
     double tI = 0.0;                 // sum_s I_s kbar_s.I
-    double Y4S, Y4I, Y3S, Y3I, Y2S, Y2I, Y1S, Y1I;
+    double v4, v3, v2, v1, Y4I, Y3I, Y2I, Y1I;
     // stage 4: kbar4 = h/6 abar
     const double k4S = k.h6 * aS, k4I = k.h6 * aI;
-    stage_adjoint(S4, I4, bs4, k4S, k4I, m6, k.lam, k.b, invN, Y4S, Y4I, g, tI);
+    stage_adjoint(S4, I4, bs4, k4S, k4I, m6, k.lam, v4, Y4I, g, tI);
     // stage 3: kbar3 = h/3 abar + h Ybar4
     const double h3S = h3 * aS, h3I = h3 * aI;
-    stage_adjoint(S3, I3, bs3, fma(k.h, Y4S, h3S), fma(k.h, Y4I, h3I), m3, k.lam, k.b, invN,
-                  Y3S, Y3I, g, tI);
+    stage_adjoint(S3, I3, bs3, fma(k.hb, v4, h3S), fma(k.h, Y4I, h3I), m3, k.lam, v3, Y3I, g,
+                  tI);
     // stage 2: kbar2 = h/3 abar + h/2 Ybar3
-    stage_adjoint(S2, I2, bs2, fma(k.h2, Y3S, h3S), fma(k.h2, Y3I, h3I), m3, k.lam, k.b,
-                  invN, Y2S, Y2I, g, tI);
+    stage_adjoint(S2, I2, bs2, fma(k.h2b, v3, h3S), fma(k.h2, Y3I, h3I), m3, k.lam, v2, Y2I, g,
+                  tI);
     // stage 1: kbar1 = h/6 abar + h/2 Ybar2
-    stage_adjoint(S, I, bs1, fma(k.h2, Y2S, k4S), fma(k.h2, Y2I, k4I), m6, k.lam, k.b, invN,
-                  Y1S, Y1I, g, tI);
+    stage_adjoint(S, I, bs1, fma(k.h2b, v2, k4S), fma(k.h2, Y2I, k4I), m6, k.lam, v1, Y1I, g,
+                  tI);
 
     // gamma: -sum I_s kbar_s.I;  mu: sum I_s (kbar_s.D - kbar_s.I)
     const double J = fma(2.0, I2 + I3, I + I4);
     g.gamma -= tI;
     g.mu = fma(k.h6 * aD, J, g.mu - tI);
-    aS = aS + ((Y1S + Y2S) + (Y3S + Y4S));
+    aS = fma(k.b, (v1 + v2) + (v3 + v4), aS);
     aI = aI + ((Y1I + Y2I) + (Y3I + Y4I));
-    (void)q3;
 }
 
 // Steps replayed into registers at a time in the reverse sweep.
@@ -156,6 +155,7 @@ __device__ __forceinline__ int seg_of(int n, int SS, int K)
     return k > K - 1 ? K - 1 : k;
 }
 
+template <int KIND>
 __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
 {
     extern __shared__ double lds[];
@@ -169,19 +169,20 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
     const int W = P.n_days, spd = P.steps_per_day, K = P.n_seg, n = P.n_part;
-    const long T = (long)W * spd;
-    // steps per segment (a segment longer than the window is the window)
-    const int SS = (int)min((long)P.seg_days * spd, T + 1);
+    const int T = W * spd;  // at most 2^30 (checked on the host)
+    // steps per segment (a segment longer than the window is the window);
+    // segments start at day starts
+    const int SS = (int)min((long)P.seg_days * spd, (long)T + 1);
     const int pl = tl.p0 + lane;
     const bool active = pl < n;
     const int pc = active ? pl : n - 1;
     const size_t ld = (size_t)n;
     const double *th = a.theta + P.theta_off + pc;
     const size_t PS = (size_t)a.P;
-    double *wsp = a.ws + (size_t)(P.p_off + pc);
-    const int ck_base = 0;  // checkpoint m: slots 3m (S), 3m+1 (I), 3m+2 (s)
-    const int in_base = 3 * a.n_ck_max;  // chunk c of an interval: 3c .. 3c+2
-    const int day_base = in_base + 3 * ((a.s + kChunk - 1) / kChunk);
+    // workspace of this particle: slot k at base[k * PS]
+    double *const ck_ws = a.ws + (size_t)(P.p_off + pc);    // checkpoint m: 3m .. 3m+2 (S, I, s)
+    double *const in_ws = ck_ws + (size_t)(3 * a.n_ck_max) * PS;  // chunk c: 3c .. 3c+2
+    double *const day_ws = in_ws + (size_t)(3 * ((a.s + kChunk - 1) / kChunk)) * PS;  // Dhat_i
 
     {
         // deceased counts: the last of the obs_series blocks of W+1 values
@@ -203,6 +204,10 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     StepConst<double> sc = step_const<double>(gamma, mu, spd);
 
     // ---------------------------------------------------- forward pass
+    // The S-carrying form of the forward kernel's step, day by day: a
+    // segment change and the rescale s = b S at the start of a day, the
+    // checkpoint (S, I, s) before every s-th step, the cost and Dhat at the
+    // end of a day.
     SirdState<double> y;
     y.S = N - I0 - P.R0 - P.D0;
     y.I = I0;
@@ -212,45 +217,44 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     y.eS = y.eI = y.eR = y.eD = 0.0;
     double acc = 0.0;
     int imax = 0;
-    cost_accum(a.kind, acc, y.D, ly[0], lw[0], 0);
-    if (active) wsp[(size_t)day_base * PS] = y.D;
+    cost_accum(KIND, acc, y.D, ly[0], lw[0], 0);
+    if (active) day_ws[0] = y.D;
     {
-        // the S-carrying form of the forward kernel's step: set_beta at
-        // a segment start, rescale at a day start, then the step
-        int k = 0;
-        long next_seg = (K > 1) ? (long)SS : T + 1;
+        int kseg = 0;
         set_beta(sc, th[0], invN);
-        long next_ck = 0;
-        int m = 0;
-        int sd = 0, day = 0;
-        for (long st = 0; st < T; ++st) {
-            if (st == next_seg) {
-                ++k;
-                next_seg = (k < K - 1) ? next_seg + SS : T + 1;
-                set_beta(sc, th[(size_t)k * ld], invN);
+        int st = 0, next_ck = 0;
+        double *cp = ck_ws;
+        double *dp = day_ws;
+        for (int day = 0; day < W; ++day) {
+            if (kseg < K - 1 && st == (kseg + 1) * SS) {
+                ++kseg;
+                set_beta(sc, th[(size_t)kseg * ld], invN);
             }
-            if (sd == 0) rescale(y, sc);
-            if (st == next_ck) {
-                if (active) {
-                    wsp[(size_t)(ck_base + 3 * m) * PS] = y.S;
-                    wsp[(size_t)(ck_base + 3 * m + 1) * PS] = y.I;
-                    wsp[(size_t)(ck_base + 3 * m + 2) * PS] = y.s;
+            rescale(y, sc);
+            for (int sd = 0; sd < spd;) {
+                if (st == next_ck) {
+                    if (active) {
+                        cp[0] = y.S;
+                        cp[PS] = y.I;
+                        cp[2 * PS] = y.s;
+                    }
+                    cp += 3 * PS;
+                    next_ck += a.s;
                 }
-                ++m;
-                next_ck += a.s;
+                const int run = min(spd - sd, next_ck - st);
+#pragma unroll 2
+                for (int i = 0; i < run; ++i) rk4_step<double, false>(y, sc);
+                sd += run;
+                st += run;
             }
-            rk4_step<double, false>(y, sc);
-            if (++sd == spd) {
-                sd = 0;
-                ++day;
-                const double prev = acc;
-                cost_accum(a.kind, acc, y.D, ly[day], lw[day], day);
-                if (a.kind == SIRD_LOSS_MXSE && !(acc == prev)) imax = day;
-                if (active) wsp[(size_t)(day_base + day) * PS] = y.D;
-            }
+            const double prev = acc;
+            cost_accum(KIND, acc, y.D, ly[day + 1], lw[day + 1], day + 1);
+            if (KIND == SIRD_LOSS_MXSE && !(acc == prev)) imax = day + 1;
+            dp += PS;
+            if (active) *dp = y.D;
         }
     }
-    const double L = cost_finish(a.kind, acc, W);
+    const double L = cost_finish(KIND, acc, W);
     if (active && a.loss_out) a.loss_out[P.p_off + pl] = L;
 
     // ---------------------------------------------------- reverse sweep
@@ -261,85 +265,109 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
         if (active) gout[(size_t)k * ld] = 0.0;  // segments past the window end
 
     double aS = 0.0, aI = 0.0;
-    const double DW = active ? wsp[(size_t)(day_base + W) * PS] : 0.0;
-    double aD = cost_grad(a.kind, W, W, DW, ly[W], lw[W], imax);
+    const double DW = active ? day_ws[(size_t)W * PS] : 0.0;
+    double aD = cost_grad(KIND, W, W, DW, ly[W], lw[W], imax);
     Grad g{0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
     set_beta(sc, th[(size_t)kr * ld], invN);
     int seg_lo = kr * SS;  // first step of segment kr
 
-    const int Ti = (int)T;  // at most 2^30 (checked on the host)
-    const int n_ck = (Ti + a.s - 1) / a.s;
+    const int n_ck = (T + a.s - 1) / a.s;
     for (int m = n_ck - 1; m >= 0; --m) {
         const int n0 = m * a.s;
-        const int n1 = (n0 + a.s < Ti) ? n0 + a.s : Ti;
+        const int n1 = (n0 + a.s < T) ? n0 + a.s : T;
+        const double *cpm = ck_ws + (size_t)(3 * m) * PS;
+        const int n_chunks = (n1 - n0 + kChunk - 1) / kChunk;
         // pass 1: replay the interval from its checkpoint with exactly the
         // forward pass's operations up to the start of its last chunk,
         // storing the state before the first step of every chunk but the
         // first (which is the checkpoint)
-        const int n_chunks = (n1 - n0 + kChunk - 1) / kChunk;
         if (n_chunks > 1) {
             SirdState<double> yr;
-            yr.S = active ? wsp[(size_t)(ck_base + 3 * m) * PS] : 0.0;
-            yr.I = active ? wsp[(size_t)(ck_base + 3 * m + 1) * PS] : 0.0;
-            yr.s = active ? wsp[(size_t)(ck_base + 3 * m + 2) * PS] : 0.0;
+            yr.S = active ? cpm[0] : 0.0;
+            yr.I = active ? cpm[PS] : 0.0;
+            yr.s = active ? cpm[2 * PS] : 0.0;
             yr.Rr = yr.D = 0.0;
             yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
             int kf = seg_of(n0, SS, K);
             StepConst<double> sf = sc;
             set_beta(sf, th[(size_t)kf * ld], invN);
-            int next_seg = (kf < K - 1) ? (kf + 1) * SS : Ti + 1;
-            int sd = n0 % spd;
-            for (int c = 1; c < n_chunks; ++c) {
-                for (int j = 0; j < kChunk; ++j) {
-                    const int st = n0 + (c - 1) * kChunk + j;
-                    if (st == next_seg) {
+            const int stop = n0 + (n_chunks - 1) * kChunk;
+            int st = n0, sd = n0 % spd, next_store = n0 + kChunk;
+            double *ip = in_ws + 3 * PS;
+            while (st < stop) {
+                if (sd == 0) {
+                    if (kf < K - 1 && st == (kf + 1) * SS) {
                         ++kf;
-                        next_seg = (kf < K - 1) ? next_seg + SS : Ti + 1;
                         set_beta(sf, th[(size_t)kf * ld], invN);
                     }
-                    if (sd == 0) rescale(yr, sf);
-                    rk4_step<double, false>(yr, sf);
-                    if (++sd == spd) sd = 0;
+                    rescale(yr, sf);
                 }
-                if (active) {
-                    wsp[(size_t)(in_base + 3 * c) * PS] = yr.S;
-                    wsp[(size_t)(in_base + 3 * c + 1) * PS] = yr.I;
-                    wsp[(size_t)(in_base + 3 * c + 2) * PS] = yr.s;
+                const int run = min(spd - sd, next_store - st);
+#pragma unroll 2
+                for (int i = 0; i < run; ++i) rk4_step<double, false>(yr, sf);
+                st += run;
+                sd += run;
+                if (sd == spd) sd = 0;
+                if (st == next_store) {
+                    if (active) {
+                        ip[0] = yr.S;
+                        ip[PS] = yr.I;
+                        ip[2 * PS] = yr.s;
+                    }
+                    ip += 3 * PS;
+                    next_store += kChunk;
                 }
             }
         }
         // pass 2: chunks last to first: replay kChunk steps into registers,
         // then walk them backwards.  The next chunk's start state, its day
-        // boundaries and their Dhat are loaded before the current chunk is
-        // walked, so with one wavefront per SIMD their latency is hidden.
-        double nS, nI, ns, nD[kChunk];
-        int nday[kChunk], nph;
-        auto load_chunk = [&](int c) {
-            // chunk 0 starts at the interval's checkpoint
-            const int slot = c == 0 ? ck_base + 3 * m : in_base + 3 * c;
-            nS = active ? wsp[(size_t)slot * PS] : 0.0;
-            nI = active ? wsp[(size_t)(slot + 1) * PS] : 0.0;
-            ns = active ? wsp[(size_t)(slot + 2) * PS] : 0.0;
-            const int cs = n0 + c * kChunk;
-            const int q = cs / spd;
-            nph = cs - q * spd;  // step of the day at cs
-            int ph = nph, d = nph == 0 ? q : q + 1;
+        // starts (a mask) and their Dhat are loaded before the current
+        // chunk is walked, so with one wavefront per SIMD their latency is
+        // hidden.
+        // With at least kChunk steps per day a chunk holds at most one day
+        // start, kept in (nD1, nday1); else every day start j of the chunk
+        // has its own (nD[j], nday[j]).
+        const bool sparse = spd >= kChunk;
+        double nS, nI, ns, nD[kChunk], nD1;
+        int nday[kChunk], nday1;
+        unsigned nmask;
+        // chunk c starts at step cs = n0 + c kChunk = q spd + ph
+        auto load_chunk = [&](int c, int cs, int q, int ph) {
+            const double *sp = c == 0 ? cpm : in_ws + (size_t)(3 * c) * PS;
+            nS = active ? sp[0] : 0.0;
+            nI = active ? sp[PS] : 0.0;
+            ns = active ? sp[2 * PS] : 0.0;
+            const int len = (n1 - cs < kChunk) ? n1 - cs : kChunk;
+            int jd = ph == 0 ? 0 : spd - ph;  // first day start in the chunk
+            int d = ph == 0 ? q : q + 1;      // its day
+            nmask = 0u;
+            nD1 = 0.0;
+            nday1 = d;
+            if (sparse) {
+                if (jd < len) {
+                    nmask = 1u << jd;
+                    if (active) nD1 = day_ws[(size_t)d * PS];
+                }
+                return;
+            }
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
-                nday[j] = -1;
                 nD[j] = 0.0;
-                if (cs + j < n1 && ph == 0) {
+                nday[j] = 0;
+                if (j == jd && j < len) {
+                    nmask |= 1u << j;
                     nday[j] = d;
-                    if (active) nD[j] = wsp[(size_t)(day_base + d) * PS];
+                    if (active) nD[j] = day_ws[(size_t)d * PS];
                     ++d;
+                    jd += spd;
                 }
-                ph = (ph + 1 == spd) ? 0 : ph + 1;
             }
         };
-        load_chunk(n_chunks - 1);
+        int cs = n0 + (n_chunks - 1) * kChunk;
+        int q = cs / spd, ph = cs - q * spd;
+        load_chunk(n_chunks - 1, cs, q, ph);
         for (int c = n_chunks - 1; c >= 0; --c) {
-            const int cs = n0 + c * kChunk;
             const int len = (n1 - cs < kChunk) ? n1 - cs : kChunk;
             SirdState<double> yr;
             yr.S = nS;
@@ -349,55 +377,78 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
             double Dd[kChunk];
             int day[kChunk];
+            if (!sparse) {
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                Dd[j] = nD[j];
-                day[j] = nday[j];
+                for (int j = 0; j < kChunk; ++j) {
+                    Dd[j] = nD[j];
+                    day[j] = nday[j];
+                }
             }
-            int sd = nph;
-            if (c > 0) load_chunk(c - 1);
-            int kf = seg_of(cs, SS, K);
+            const double Dd1 = nD1;
+            const int day1 = nday1;
+            const unsigned dmask = nmask;
+            // the previous chunk's position
+            const int pcs = cs - kChunk;
+            int pq = q, pph = ph - kChunk;
+            while (pph < 0) {
+                pph += spd;
+                --pq;
+            }
+            if (c > 0) load_chunk(c - 1, pcs, pq, pph);
+            // segment of the chunk's first step: kr, or an earlier one when
+            // a segment starts inside the chunk
+            int kf = kr, lo = seg_lo;
+            while (cs < lo) {
+                --kf;
+                lo -= SS;
+            }
             StepConst<double> sf = sc;  // the reverse's segment: no reload
             if (kf != kr) set_beta(sf, th[(size_t)kf * ld], invN);
-            int next_seg = (kf < K - 1) ? (kf + 1) * SS : Ti + 1;
+            int next_seg = (kf < K - 1) ? (kf + 1) * SS : T + 1;
             double Sa[kChunk], Ia[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
                 Sa[j] = Ia[j] = 0.0;
                 if (j < len) {
-                    if (cs + j == next_seg) {
-                        ++kf;
-                        next_seg = (kf < K - 1) ? next_seg + SS : Ti + 1;
-                        set_beta(sf, th[(size_t)kf * ld], invN);
+                    if (dmask & (1u << j)) {
+                        if (cs + j == next_seg) {
+                            ++kf;
+                            next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
+                            set_beta(sf, th[(size_t)kf * ld], invN);
+                        }
+                        rescale(yr, sf);
                     }
-                    if (sd == 0) rescale(yr, sf);
                     Sa[j] = yr.S;
                     Ia[j] = yr.I;
                     rk4_step<double, false>(yr, sf);
-                    if (++sd == spd) sd = 0;
                 }
             }
 #pragma unroll
             for (int j = kChunk - 1; j >= 0; --j) {
                 if (j < len) {
-                    if (cs + j < seg_lo) {
-                        if (active) gout[(size_t)kr * ld] = g.beta * gl;
-                        g.beta = 0.0;
-                        --kr;
-                        seg_lo = kr * SS;
-                        set_beta(sc, th[(size_t)kr * ld], invN);
-                    }
-                    rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, invN, h3, g);
-                    if (day[j] >= 0) {
-                        const int i = day[j];
-                        aD += cost_grad(a.kind, i, W, Dd[j], ly[i], lw[i], imax);
+                    rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, h3, g);
+                    if (dmask & (1u << j)) {
+                        const int i = sparse ? day1 : day[j];
+                        const double Dj = sparse ? Dd1 : Dd[j];
+                        aD += cost_grad(KIND, i, W, Dj, ly[i], lw[i], imax);
+                        if (cs + j == seg_lo && kr > 0) {
+                            // the step just reversed opened segment kr
+                            if (active) gout[(size_t)kr * ld] = (g.beta * invN) * gl;
+                            g.beta = 0.0;
+                            --kr;
+                            seg_lo -= SS;
+                            set_beta(sc, th[(size_t)kr * ld], invN);
+                        }
                     }
                 }
             }
+            cs = pcs;
+            q = pq;
+            ph = pph;
         }
     }
     if (active) {
-        gout[(size_t)kr * ld] = g.beta * gl;
+        gout[(size_t)kr * ld] = (g.beta * invN) * gl;
         gout[(size_t)K * ld] = g.gamma * gl;
         gout[(size_t)(K + 1) * ld] = g.mu * gl;
         gout[(size_t)(K + 2) * ld] = (aI - aS) * gl;
@@ -467,7 +518,6 @@ extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
     a.ws = (double *)workspace;
     a.P = batch->total_particles;
     a.n_tiles = batch->n_tiles;
-    a.kind = loss_kind;
     a.obs_series = batch->obs_series;
     a.s = s;
     a.n_ck_max = (int)((batch->max_steps + s - 1) / s);
@@ -477,6 +527,23 @@ extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
     if (lds > 65536) return fail(SIRD_EINVAL, "sird_loss_backward: window too long for LDS");
     const int grid = tile_blocks(batch->n_tiles);
     if (grid == 0) return SIRD_OK;
-    hipLaunchKernelGGL(k_backward, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    hipStream_t s_ = (hipStream_t)stream;
+    switch (loss_kind) {
+    case SIRD_LOSS_SSRE:
+        hipLaunchKernelGGL(k_backward<SIRD_LOSS_SSRE>, dim3(grid), dim3(block), lds, s_, a);
+        break;
+    case SIRD_LOSS_MSE:
+        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MSE>, dim3(grid), dim3(block), lds, s_, a);
+        break;
+    case SIRD_LOSS_MXSE:
+        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MXSE>, dim3(grid), dim3(block), lds, s_, a);
+        break;
+    case SIRD_LOSS_MAE:
+        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MAE>, dim3(grid), dim3(block), lds, s_, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MAPE>, dim3(grid), dim3(block), lds, s_, a);
+        break;
+    }
     return hip_status(hipGetLastError(), "sird_loss_backward");
 }
