@@ -35,6 +35,7 @@
 
 #include <cmath>
 #include <string>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -273,20 +274,36 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     int seg_lo = kr * SS;  // first step of segment kr
 
     const int n_ck = (T + a.s - 1) / a.s;
+    // the checkpoint of the interval to reverse next, loaded one interval
+    // ahead
+    double cS, cI, cs_;
+    {
+        const double *cp = ck_ws + (size_t)(3 * (n_ck - 1)) * PS;
+        cS = active ? cp[0] : 0.0;
+        cI = active ? cp[PS] : 0.0;
+        cs_ = active ? cp[2 * PS] : 0.0;
+    }
     for (int m = n_ck - 1; m >= 0; --m) {
         const int n0 = m * a.s;
         const int n1 = (n0 + a.s < T) ? n0 + a.s : T;
-        const double *cpm = ck_ws + (size_t)(3 * m) * PS;
+        const double ckS = cS, ckI = cI, cks = cs_;
+        if (m > 0) {
+            const double *cp = ck_ws + (size_t)(3 * (m - 1)) * PS;
+            cS = active ? cp[0] : 0.0;
+            cI = active ? cp[PS] : 0.0;
+            cs_ = active ? cp[2 * PS] : 0.0;
+        }
         const int n_chunks = (n1 - n0 + kChunk - 1) / kChunk;
         // pass 1: replay the interval from its checkpoint with exactly the
         // forward pass's operations up to the start of its last chunk,
         // storing the state before the first step of every chunk but the
-        // first (which is the checkpoint)
+        // first (the checkpoint) and the last (kept in registers)
+        double lastS = ckS, lastI = ckI, lasts = cks;
         if (n_chunks > 1) {
             SirdState<double> yr;
-            yr.S = active ? cpm[0] : 0.0;
-            yr.I = active ? cpm[PS] : 0.0;
-            yr.s = active ? cpm[2 * PS] : 0.0;
+            yr.S = ckS;
+            yr.I = ckI;
+            yr.s = cks;
             yr.Rr = yr.D = 0.0;
             yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
             int kf = seg_of(n0, SS, K);
@@ -309,7 +326,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                 st += run;
                 sd += run;
                 if (sd == spd) sd = 0;
-                if (st == next_store) {
+                if (st == next_store && st < stop) {
                     if (active) {
                         ip[0] = yr.S;
                         ip[PS] = yr.I;
@@ -319,6 +336,9 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
                     next_store += kChunk;
                 }
             }
+            lastS = yr.S;
+            lastI = yr.I;
+            lasts = yr.s;
         }
         // pass 2: chunks last to first: replay kChunk steps into registers,
         // then walk them backwards.  The next chunk's start state, its day
@@ -334,10 +354,20 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
         unsigned nmask;
         // chunk c starts at step cs = n0 + c kChunk = q spd + ph
         auto load_chunk = [&](int c, int cs, int q, int ph) {
-            const double *sp = c == 0 ? cpm : in_ws + (size_t)(3 * c) * PS;
-            nS = active ? sp[0] : 0.0;
-            nI = active ? sp[PS] : 0.0;
-            ns = active ? sp[2 * PS] : 0.0;
+            if (c == 0) {
+                nS = ckS;
+                nI = ckI;
+                ns = cks;
+            } else if (c == n_chunks - 1) {
+                nS = lastS;
+                nI = lastI;
+                ns = lasts;
+            } else {
+                const double *sp = in_ws + (size_t)(3 * c) * PS;
+                nS = active ? sp[0] : 0.0;
+                nI = active ? sp[PS] : 0.0;
+                ns = active ? sp[2 * PS] : 0.0;
+            }
             const int len = (n1 - cs < kChunk) ? n1 - cs : kChunk;
             int jd = ph == 0 ? 0 : spd - ph;  // first day start in the chunk
             int d = ph == 0 ? q : q + 1;      // its day
@@ -405,43 +435,53 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             StepConst<double> sf = sc;  // the reverse's segment: no reload
             if (kf != kr) set_beta(sf, th[(size_t)kf * ld], invN);
             int next_seg = (kf < K - 1) ? (kf + 1) * SS : T + 1;
-            double Sa[kChunk], Ia[kChunk];
+            // replay, then walk back; a full chunk (every chunk but an
+            // interval's last one, when the interval is not a multiple of
+            // kChunk) has no per-step length test
+            auto walk = [&](auto full) {
+                constexpr bool FULL = decltype(full)::value;
+                double Sa[kChunk], Ia[kChunk];
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                Sa[j] = Ia[j] = 0.0;
-                if (j < len) {
-                    if (dmask & (1u << j)) {
-                        if (cs + j == next_seg) {
-                            ++kf;
-                            next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
-                            set_beta(sf, th[(size_t)kf * ld], invN);
+                for (int j = 0; j < kChunk; ++j) {
+                    Sa[j] = Ia[j] = 0.0;
+                    if (FULL || j < len) {
+                        if (dmask & (1u << j)) {
+                            if (cs + j == next_seg) {
+                                ++kf;
+                                next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
+                                set_beta(sf, th[(size_t)kf * ld], invN);
+                            }
+                            rescale(yr, sf);
                         }
-                        rescale(yr, sf);
-                    }
-                    Sa[j] = yr.S;
-                    Ia[j] = yr.I;
-                    rk4_step<double, false>(yr, sf);
-                }
-            }
-#pragma unroll
-            for (int j = kChunk - 1; j >= 0; --j) {
-                if (j < len) {
-                    rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, h3, g);
-                    if (dmask & (1u << j)) {
-                        const int i = sparse ? day1 : day[j];
-                        const double Dj = sparse ? Dd1 : Dd[j];
-                        aD += cost_grad(KIND, i, W, Dj, ly[i], lw[i], imax);
-                        if (cs + j == seg_lo && kr > 0) {
-                            // the step just reversed opened segment kr
-                            if (active) gout[(size_t)kr * ld] = (g.beta * invN) * gl;
-                            g.beta = 0.0;
-                            --kr;
-                            seg_lo -= SS;
-                            set_beta(sc, th[(size_t)kr * ld], invN);
-                        }
+                        Sa[j] = yr.S;
+                        Ia[j] = yr.I;
+                        rk4_step<double, false>(yr, sf);
                     }
                 }
-            }
+#pragma unroll
+                for (int j = kChunk - 1; j >= 0; --j) {
+                    if (FULL || j < len) {
+                        rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, h3, g);
+                        if (dmask & (1u << j)) {
+                            const int i = sparse ? day1 : day[j];
+                            const double Dj = sparse ? Dd1 : Dd[j];
+                            aD += cost_grad(KIND, i, W, Dj, ly[i], lw[i], imax);
+                            if (cs + j == seg_lo && kr > 0) {
+                                // the step just reversed opened segment kr
+                                if (active) gout[(size_t)kr * ld] = (g.beta * invN) * gl;
+                                g.beta = 0.0;
+                                --kr;
+                                seg_lo -= SS;
+                                set_beta(sc, th[(size_t)kr * ld], invN);
+                            }
+                        }
+                    }
+                }
+            };
+            if (len == kChunk)
+                walk(std::true_type{});
+            else
+                walk(std::false_type{});
             cs = pcs;
             q = pq;
             ph = pph;
@@ -463,8 +503,9 @@ static int resolve_interval(const sird_batch *b, int ckpt_interval)
 }
 
 // Workspace slots per particle: 3 per checkpoint (S, I, s), 3 per chunk of
-// one replayed interval (the first chunk's slots go unused: it starts at
-// the checkpoint), and Dhat of every day.
+// one replayed interval (the first and last chunks' slots go unused: the
+// first starts at the checkpoint, the last one's start stays in registers),
+// and Dhat of every day.
 static size_t ws_slots(const sird_batch *b, int s)
 {
     const int64_t n_ck = (b->max_steps + s - 1) / s;
