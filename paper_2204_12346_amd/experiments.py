@@ -91,6 +91,8 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
     e1.record()
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1) / reps
+    sird_loss(b, theta, obs, wl.loss, loss)
+    torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
         sird_loss(b, theta, obs, wl.loss, loss)
