@@ -175,6 +175,10 @@ def extras():
     z = synth.c5_series()
     res["c5_rolling_52x16x4096"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,
                                                       launch=dict(C3_LAUNCH))
+    # the configuration names Adam for the refinement
+    res["c5_rolling_52x16x4096_adam"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,
+                                                           launch=dict(C3_LAUNCH),
+                                                           method="adam")
     return res
 
 

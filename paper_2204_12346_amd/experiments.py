@@ -258,12 +258,13 @@ def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10)
 
 
 def rolling_forecast(wl, truth, restarts, iters=300, k_per_restart=2, refine_rounds=300,
-                     horizon=14, launch=None) -> Dict:
+                     horizon=14, launch=None, method="lbfgs", lr=1e-2) -> Dict:
     """All windows x restarts in one batch: swarm, refinement of the best
-    k_per_restart particles of every restart, best refined parameters per
-    window, and a horizon-day forecast of cumulative deaths compared with the
-    noise-free truth (relative error at 7 and 14 days, and of the 14-day
-    increment); quantiles over windows."""
+    k_per_restart particles of every restart (projected L-BFGS, or projected
+    Adam with step lr), best refined parameters per window, and a horizon-day
+    forecast of cumulative deaths compared with the noise-free truth
+    (relative error at 7 and 14 days, and of the 14-day increment);
+    quantiles over windows."""
     fits = wl.fits
     specs = [ProblemSpec.from_fit(f) for f in fits]
     b = Batch(specs, **(launch or {}))
@@ -277,8 +278,13 @@ def rolling_forecast(wl, truth, restarts, iters=300, k_per_restart=2, refine_rou
     sird_pso_iterate(b, params, sw, obs, wl.loss, iters)
     torch.cuda.synchronize()
     t_pso = time.perf_counter() - t0
-    ref = fit.refine_lbfgs(b, sw, params, obs, wl.loss, k=k_per_restart,
-                           max_rounds=refine_rounds, check_every=max(refine_rounds, 1))
+    if method == "adam":
+        ref = fit.refine_topk(b, sw, params, obs, wl.loss, k=k_per_restart,
+                              max_steps=refine_rounds, lr=lr,
+                              check_every=max(refine_rounds, 1))
+    else:
+        ref = fit.refine_lbfgs(b, sw, params, obs, wl.loss, k=k_per_restart,
+                               max_rounds=refine_rounds, check_every=max(refine_rounds, 1))
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0 - t_pso
     th, L = fit.best_per_problem(ref.batch, ref.theta, ref.loss)
@@ -311,7 +317,8 @@ def rolling_forecast(wl, truth, restarts, iters=300, k_per_restart=2, refine_rou
         return {p: float(np.quantile(v, p / 100)) for p in (5, 50, 95)}
 
     return {"windows": n_win, "restarts": restarts, "particles": b.total_particles,
-            "iterations": iters, "particle_steps": b.particle_steps * iters,
+            "iterations": iters, "refine": method, "refine_rounds": refine_rounds,
+            "particle_steps": b.particle_steps * iters,
             "seconds_swarm": t_pso, "seconds_refine": t_ref, "seconds_total": t_all,
             "particle_steps_per_s_swarm": b.particle_steps * iters / t_pso,
             "rel_err_cum_deaths_h7": q(e7), "rel_err_cum_deaths_h14": q(e14),
