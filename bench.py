@@ -158,6 +158,9 @@ def extras():
     for dt in ("f64", "f32"):
         res[f"c2_segmented_8192x180d_{dt}"] = X.swarm_throughput(
             synth.c2(), dt, iters=200, graph_chunk=20, launch=dict(block=64))
+    # the batched workload with its iterations captured in HIP graphs
+    res["c3_batched_512x1024_graph"] = X.swarm_throughput(
+        synth.c3(), "f64", iters=50, warmup=5, graph_chunk=10, launch=dict(C3_LAUNCH))
     print("# extras: gradients ...", file=sys.stderr, flush=True)
     wl4, th4 = synth.c4()
     res["c4_gradients_65536x7300steps"] = X.gradients_per_s(wl4, th4)
