@@ -204,7 +204,7 @@ def main():
         copy_probe(args.copy_probe_mib)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(independent fits would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)

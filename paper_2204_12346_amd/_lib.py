@@ -5,7 +5,7 @@ of ``libsird.so``.  Functions carry the C names; each raises ``SirdError``
 on a negative status.  Device arrays are passed as torch tensors (their
 ``data_ptr()``) and the stream defaults to torch's current stream.
 
-The library must have been built (``__graft_entry__.build()``); there is no
+The library must have been built (``python -m paper_2204_12346_amd.build``); there is no
 fallback path: a missing library raises ``ImportError`` when first used.
 """
 from __future__ import annotations
@@ -127,7 +127,8 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(
-                f"{LIB_PATH} not built: run __graft_entry__.build() (hipcc, gfx950)")
+                f"{LIB_PATH} not built: run python -m paper_2204_12346_amd.build "
+                "(hipcc, gfx950)")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
