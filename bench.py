@@ -147,41 +147,56 @@ def copy_probe(mib):
                       "launches": 3}))
 
 
-def extras():
-    """The other configurations, each measured once (see experiments.py)."""
+def extra_tasks():
+    """The other configurations, each measured once (see experiments.py):
+    (group, name, thunk) in run order."""
     import synth
     from paper_2204_12346_amd import experiments as X
-    res = {}
-    print("# extras: single-fit swarms ...", file=sys.stderr, flush=True)
-    res["c1_constant_beta_256x60d"] = X.swarm_throughput(synth.c1(), "f64", iters=200,
-                                                         graph_chunk=20, launch=dict(block=64))
+    t = [("single-fit swarms", "c1_constant_beta_256x60d",
+          lambda: X.swarm_throughput(synth.c1(), "f64", iters=200, graph_chunk=20,
+                                     launch=dict(block=64)))]
     for dt in ("f64", "f32"):
-        res[f"c2_segmented_8192x180d_{dt}"] = X.swarm_throughput(
-            synth.c2(), dt, iters=200, graph_chunk=20, launch=dict(block=64))
+        t.append(("single-fit swarms", f"c2_segmented_8192x180d_{dt}",
+                  lambda dt=dt: X.swarm_throughput(synth.c2(), dt, iters=200, graph_chunk=20,
+                                                   launch=dict(block=64))))
     # the batched workload with its iterations captured in HIP graphs
-    res["c3_batched_512x1024_graph"] = X.swarm_throughput(
-        synth.c3(), "f64", iters=50, warmup=5, graph_chunk=10, launch=dict(C3_LAUNCH))
-    print("# extras: gradients ...", file=sys.stderr, flush=True)
-    wl4, th4 = synth.c4()
-    res["c4_gradients_65536x7300steps"] = X.gradients_per_s(wl4, th4)
-    res["c4_gradients_65536x7300steps_interval8"] = X.gradients_per_s(wl4, th4, ckpt_interval=8)
-    print("# extras: time to fit ...", file=sys.stderr, flush=True)
-    res["time_to_fit_c2"] = X.time_to_fit(synth.c2())
-    print("# extras: the paper's own timing case ...", file=sys.stderr, flush=True)
+    t.append(("single-fit swarms", "c3_batched_512x1024_graph",
+              lambda: X.swarm_throughput(synth.c3(), "f64", iters=50, warmup=5, graph_chunk=10,
+                                         launch=dict(C3_LAUNCH))))
+    t.append(("gradients", "c4_gradients_65536x7300steps",
+              lambda: X.gradients_per_s(*synth.c4())))
+    t.append(("gradients", "c4_gradients_65536x7300steps_interval8",
+              lambda: X.gradients_per_s(*synth.c4(), ckpt_interval=8)))
+    t.append(("time to fit", "time_to_fit_c2", lambda: X.time_to_fit(synth.c2())))
     for dt in ("f64", "f32"):
-        res[f"paper_euler_ramp_ird_mxse_10000x92d_{dt}"] = X.paper_iteration(synth.paper(), dt)
-    print("# extras: repetition study ...", file=sys.stderr, flush=True)
-    res["rep_1000x10000x36d"] = X.repetition(synth.rep())
-    print("# extras: window-wise calibration ...", file=sys.stderr, flush=True)
-    res["windows_139x10000x36d"] = X.window_wise(synth.windows())
-    print("# extras: rolling windows ...", file=sys.stderr, flush=True)
-    z = synth.c5_series()
-    res["c5_rolling_52x16x4096"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,
-                                                      launch=dict(C3_LAUNCH))
+        t.append(("the paper's own timing case", f"paper_euler_ramp_ird_mxse_10000x92d_{dt}",
+                  lambda dt=dt: X.paper_iteration(synth.paper(), dt)))
+    t.append(("repetition study", "rep_1000x10000x36d", lambda: X.repetition(synth.rep())))
+    t.append(("window-wise calibration", "windows_139x10000x36d",
+              lambda: X.window_wise(synth.windows())))
+    t.append(("rolling windows", "c5_rolling_52x16x4096",
+              lambda: X.rolling_forecast(synth.c5(), synth.c5_series()["truth"], restarts=16,
+                                         launch=dict(C3_LAUNCH))))
     # the configuration names Adam for the refinement
-    res["c5_rolling_52x16x4096_adam"] = X.rolling_forecast(synth.c5(), z["truth"], restarts=16,
-                                                           launch=dict(C3_LAUNCH),
-                                                           method="adam")
+    t.append(("rolling windows", "c5_rolling_52x16x4096_adam",
+              lambda: X.rolling_forecast(synth.c5(), synth.c5_series()["truth"], restarts=16,
+                                         launch=dict(C3_LAUNCH), method="adam")))
+    return t
+
+
+def extras(only=None):
+    res = {}
+    group = None
+    for g, name, fn in extra_tasks():
+        if only is not None and name != only:
+            continue
+        if g != group:
+            print(f"# extras: {g} ...", file=sys.stderr, flush=True)
+            group = g
+        res[name] = fn()
+    if only is not None and not res:
+        raise SystemExit(f"unknown extra {only!r}: one of "
+                         + ", ".join(n for _, n, _ in extra_tasks()))
     return res
 
 
@@ -199,9 +214,17 @@ def main():
                     help="search the launch shape before timing instead of the recorded one")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (single fits, gradients, rolling windows)")
+    ap.add_argument("--extra", default=None,
+                    help="run only this one of the other workloads and print its JSON")
     args = ap.parse_args()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
+        return
+    if args.extra:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        print(json.dumps(extras(args.extra)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
