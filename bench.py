@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Launch configuration of the integration kernel for the batched workload
-# (block size and persistent wavefronts); chosen by the autotuner.
+# (block size and persistent wavefronts); what the autotuner of the fused
+# iteration (autotune.autotune_iterate, bench.py --autotune) picks.
 C3_LAUNCH = dict(block=256, persistent=0)
 
 # Algorithmic work of one particle-step of the FP64 forward: the RK4 step
@@ -244,7 +245,8 @@ def main():
     tuned = None
     if args.autotune:
         from paper_2204_12346_amd import autotune
-        tuned = autotune.autotune(b, sw.x, obs, kind, use_cache=False, verbose=True)
+        tuned = autotune.autotune_iterate(b, params, sw, obs, kind, use_cache=False,
+                                          verbose=True)
         print(f"# autotuned launch: {tuned}", file=sys.stderr, flush=True)
     S.sird_pso_iterate(b, params, sw, obs, kind, args.warmup)
     torch.cuda.synchronize()

@@ -3,10 +3,11 @@
 Searches threads per block (1, 2, 4 or 8 wavefronts, each on its own
 64-particle tile) and the persistent-queue size (0 = one wavefront per tile
 dispatched longest-first; otherwise that many resident wavefronts pulling
-tiles from a device counter), times sird_loss with HIP events, and checks
-that every candidate returns bitwise the same losses as the first -- the
-launch shape must never change results.  Choices are cached in a JSON file
-keyed by device, precision and workload shape.
+tiles from a device counter), times sird_loss (autotune) or the fused swarm
+iteration (autotune_iterate) with HIP events, and checks that every
+candidate returns bitwise the same losses as the first -- the launch shape
+must never change results.  Choices are cached in a JSON file keyed by
+device, precision, workload shape and objective.
 """
 from __future__ import annotations
 
@@ -14,9 +15,10 @@ import json
 import os
 from typing import Dict, List, Optional
 
+import numpy as np
 import torch
 
-from .core import Batch, sird_loss
+from .core import Batch, PsoParams, Swarm, pso_evaluate, sird_loss
 
 CACHE_ENV = "SIRD_AUTOTUNE_CACHE"
 
@@ -57,49 +59,108 @@ def time_config(batch: Batch, theta, obs, kind, reps=5, stream=None):
     return e0.elapsed_time(e1) / reps, out
 
 
-def autotune(batch: Batch, theta, obs, kind="ssre", reps=5, use_cache=True,
-             verbose=False) -> Dict[str, int]:
-    """Pick and apply the fastest launch shape for this batch; returns it."""
-    key = shape_key(batch)
-    path = _cache_path()
-    cache = {}
-    if use_cache and os.path.exists(path):
+def _load_cache(path):
+    if os.path.exists(path):
         try:
             with open(path) as fh:
-                cache = json.load(fh)
+                return json.load(fh)
         except (OSError, ValueError):
-            cache = {}
+            pass
+    return {}
+
+
+def _store_cache(path, cache):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    except OSError:
+        pass
+
+
+def _search(batch: Batch, key: str, run, use_cache: bool, verbose: bool,
+            rounds: int = 3, warm: int = 20) -> Dict[str, int]:
+    """run() -> (ms, result tensor) times one candidate launch shape.  Every
+    candidate's result must agree bitwise with the first's; the clock is
+    warmed first and the candidates are timed in interleaved rounds (median
+    per candidate), so that no candidate is judged at a colder clock than
+    another.  Applies and caches the fastest."""
+    path = _cache_path()
+    cache = _load_cache(path) if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]["launch"]
         batch.configure(**best)
         return best
     n_cu = torch.cuda.get_device_properties(batch.device).multi_processor_count
+    cands = [c for c in candidates(n_cu)
+             if (c["block"] // 64) * 2 * (batch.c.max_days + 1) * 8 <= 65536]
     ref = None
-    results = []
-    for cand in candidates(n_cu):
-        lds = (cand["block"] // 64) * 2 * (batch.c.max_days + 1) * 8
-        if lds > 65536:
-            continue
-        batch.configure(**cand)
-        ms, out = time_config(batch, theta, obs, kind, reps)
-        h = out.cpu()
-        if ref is None:
-            ref = h
-        elif not torch.equal(h.view(torch.int64), ref.view(torch.int64)):
-            raise RuntimeError(f"launch shape {cand} changed the losses: kernel bug")
-        results.append((ms, cand))
-        if verbose:
+    times = {i: [] for i in range(len(cands))}
+    for r in range(rounds):
+        for i, cand in enumerate(cands):
+            batch.configure(**cand)
+            if r == 0 and i == 0:
+                for _ in range(max(1, warm // 5)):
+                    run()
+            ms, out = run()
+            if r == 0:
+                h = out.cpu()
+                if ref is None:
+                    ref = h
+                elif not torch.equal(h.view(torch.int64), ref.view(torch.int64)):
+                    raise RuntimeError(f"launch shape {cand} changed the losses: kernel bug")
+            times[i].append(ms)
+    results = sorted(((float(np.median(times[i])), cand) for i, cand in enumerate(cands)),
+                     key=lambda r: r[0])
+    if verbose:
+        for ms, cand in results:
             print(f"autotune {cand}: {ms:.4f} ms", flush=True)
-    results.sort(key=lambda r: r[0])
     best = results[0][1]
     batch.configure(**best)
     if use_cache:
         cache[key] = {"launch": best, "ms": results[0][0],
                       "all": [[c, m] for m, c in results]}
-        try:
-            os.makedirs(os.path.dirname(path), exist_ok=True)
-            with open(path, "w") as fh:
-                json.dump(cache, fh, indent=1)
-        except OSError:
-            pass
+        _store_cache(path, cache)
     return best
+
+
+def autotune(batch: Batch, theta, obs, kind="ssre", reps=5, use_cache=True,
+             verbose=False) -> Dict[str, int]:
+    """Pick and apply the fastest launch shape of the loss kernel (sird_loss)
+    for this batch; returns it."""
+    return _search(batch, shape_key(batch),
+                   lambda: time_config(batch, theta, obs, kind, reps), use_cache, verbose)
+
+
+def autotune_iterate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre", reps=5,
+                     use_cache=True, verbose=False) -> Dict[str, int]:
+    """Pick and apply the fastest launch shape of the fused swarm iteration
+    (pso_evaluate with the move): every candidate starts from the same swarm
+    state, its first iteration's losses must agree bitwise, and the swarm is
+    restored afterwards."""
+    names = ("x", "v", "pbest_x", "pbest_f", "gbest_x", "gbest_f", "gbest_idx", "iter", "f")
+    saved = {n: getattr(swarm, n).clone() for n in names}
+
+    def restore():
+        for n in names:
+            getattr(swarm, n).copy_(saved[n])
+
+    def run():
+        s = torch.cuda.current_stream()
+        restore()
+        pso_evaluate(batch, params, swarm, obs, kind, move_first=True)
+        first = swarm.f.clone()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            pso_evaluate(batch, params, swarm, obs, kind, move_first=True)
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, first
+
+    try:
+        return _search(batch, shape_key(batch) + "|iterate", run, use_cache, verbose)
+    finally:
+        restore()
+        torch.cuda.synchronize()

@@ -154,6 +154,39 @@ def test_autotuner_candidates_agree_bitwise(tmp_path, monkeypatch):
     assert again == best
 
 
+def test_autotuner_of_the_fused_iteration_restores_the_swarm(tmp_path, monkeypatch):
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "cache.json"))
+    wl = synth.c3(regions=list(range(16)))
+    b = make_batch(wl.fits, [128] * 16)
+    params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
+                         wl.c2, wl.seed)
+    obs = b.pack_obs([f.y for f in wl.fits])
+    names = ("x", "v", "pbest_x", "pbest_f", "gbest_x", "gbest_f", "gbest_idx", "iter")
+
+    def fresh():
+        sw = S.Swarm(b)
+        S.pso_init(b, params, sw)
+        S.sird_pso_iterate(b, params, sw, obs, "ssre", 2)
+        return sw
+
+    def bits(t):
+        return t.view(torch.int64).cpu()
+
+    b.configure(block=256, persistent=0)
+    ref = fresh()
+    S.sird_pso_iterate(b, params, ref, obs, "ssre", 3)
+    sw = fresh()
+    before = {n: bits(getattr(sw, n)) for n in names}
+    best = autotune.autotune_iterate(b, params, sw, obs, "ssre", reps=2, verbose=True)
+    assert best in autotune.candidates(torch.cuda.get_device_properties(0).multi_processor_count)
+    for n in names:
+        assert torch.equal(bits(getattr(sw, n)), before[n]), n
+    # the tuned launch continues the run bitwise like the default one
+    S.sird_pso_iterate(b, params, sw, obs, "ssre", 3)
+    for n in names:
+        assert torch.equal(bits(getattr(sw, n)), bits(getattr(ref, n))), n
+
+
 @pytest.mark.parametrize("m,rounds", [(5, 12), (32, 40)])
 def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds):
     """Same (f, grad) inputs on both sides -> the same proposals and updates
