@@ -421,6 +421,33 @@ __device__ __forceinline__ T wave_uniform(T v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// One dimension of the move: offset o of the theta-shaped arrays, r the
+// Philox word whose high and low halves give r1 and r2, g, lo and hi the
+// dimension's global best and bounds.  Returns the new x.
+__device__ __forceinline__ double pso_move_dim(const PsoMove &m, size_t o, uint64_t r,
+                                               const double *g, const double *lo,
+                                               const double *hi)
+{
+    const double r1 = (double)(uint32_t)(r >> 32) * 0x1.0p-32;
+    const double r2 = (double)(uint32_t)r * 0x1.0p-32;
+    const double xo = m.x[o];
+    double tv = m.w * m.v[o];
+    const double a1 = m.c1 * r1;
+    const double d1 = m.pbest_x[o] - xo;
+    const double a2 = m.c2 * r2;
+    const double d2 = *g - xo;
+    const double m1 = a1 * d1;
+    tv = tv + m1;
+    const double m2 = a2 * d2;
+    tv = tv + m2;
+    m.v[o] = tv;
+    double xn = xo + tv;
+    if (xn < *lo) xn = *lo;
+    if (xn > *hi) xn = *hi;
+    m.x[o] = xn;
+    return xn;
+}
+
 __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_problem &P,
                                                   int pl, uint64_t it)
 {
@@ -435,27 +462,39 @@ __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_p
         for (int jj = 0; jj < 4; ++jj) {
             const int j = 4 * q + jj;
             if (j >= d) break;
-            const double r1 = (double)(uint32_t)(r.w[jj] >> 32) * 0x1.0p-32;
-            const double r2 = (double)(uint32_t)r.w[jj] * 0x1.0p-32;
-            const size_t o = base + (size_t)j * n;
-            const double xo = m.x[o];
-            double tv = m.w * m.v[o];
-            const double a1 = m.c1 * r1;
-            const double d1 = m.pbest_x[o] - xo;
-            const double a2 = m.c2 * r2;
-            const double d2 = g[j] - xo;
-            const double m1 = a1 * d1;
-            tv = tv + m1;
-            const double m2 = a2 * d2;
-            tv = tv + m2;
-            m.v[o] = tv;
-            double xn = xo + tv;
-            if (xn < lo[j]) xn = lo[j];
-            if (xn > hi[j]) xn = hi[j];
-            m.x[o] = xn;
+            pso_move_dim(m, base + (size_t)j * n, r.w[jj], g + j, lo + j, hi + j);
         }
     }
     if (P.model == SIRD_MODEL_EULER_RAMP) ramp_order(m.x, P, pl);
+}
+
+// The same move for the ramp model (d = 7, so fully unrolled), with the new
+// position also returned in xr (t1 <= t2 as stored): the caller integrates
+// from registers instead of reading x back.
+__device__ __forceinline__ void pso_move_ramp(const PsoMove &m, const sird_problem &P, int pl,
+                                              uint64_t it, double (&xr)[7])
+{
+    const size_t n = (size_t)P.n_part;
+    const double *lo = m.lo + P.box_off;
+    const double *hi = m.hi + P.box_off;
+    const double *g = m.gbest_x + P.box_off;
+    const size_t base = (size_t)P.theta_off + pl;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int j = 4 * q + jj;
+            if (j < 7) xr[j] = pso_move_dim(m, base + (size_t)j * n, r.w[jj], g + j, lo + j, hi + j);
+        }
+    }
+    if (xr[2] > xr[3]) {
+        const double t = xr[2];
+        xr[2] = xr[3];
+        xr[3] = t;
+        m.x[base + 2 * n] = xr[2];
+        m.x[base + 3 * n] = xr[3];
+    }
 }
 
 // Index of this wavefront's tile in a launch of one wavefront per tile,

@@ -139,11 +139,30 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             stage_d(a, P, lane, ly);
         wave_sync();
     }
-    if (FUSED && a.do_move && active) pso_move_particle(a.mv, P, pl, a.iter[0] - 1);
+    // the ramp model's parameters (d = 7): from the move's registers when
+    // the kernel moves the swarm (idle lanes take the box's lower corner),
+    // else from x
+    double xr[7];
+    if constexpr (MODEL == SIRD_MODEL_EULER_RAMP) {
+        if (FUSED && a.do_move) {
+            if (active) {
+                pso_move_ramp(a.mv, P, pl, a.iter[0] - 1, xr);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 7; ++j) xr[j] = a.mv.lo[P.box_off + j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 7; ++j) xr[j] = th[(size_t)j * ld];
+        }
+    } else if (FUSED && a.do_move && active) {
+        pso_move_particle(a.mv, P, pl, a.iter[0] - 1);
+    }
 
-    const double gamma = th[(size_t)K * ld];
-    const double mu = th[(size_t)(K + 1) * ld];
-    const double I0 = th[(size_t)(K + 2) * ld];
+    const bool ramp = MODEL == SIRD_MODEL_EULER_RAMP;
+    const double gamma = ramp ? xr[4] : th[(size_t)K * ld];
+    const double mu = ramp ? xr[5] : th[(size_t)(K + 1) * ld];
+    const double I0 = ramp ? xr[6] : th[(size_t)(K + 2) * ld];
     const double N = P.N;
 
     SirdState<R> y;
@@ -158,25 +177,34 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
     double *tr = nullptr;
     const size_t comp_stride = (size_t)(W + 1) * ld;
     if (TRAJ) tr = a.traj + P.traj_off + pc;
-    // the state after day i: stored, or added to the cost; yw is the day's
-    // (y_i, w_i) of a deceased-count cost, read from LDS before the day's
-    // steps so that the read's latency overlaps them
-    auto emit = [&](int i, double2 yw) {
+    // the state after day i: stored, or added to the cost; o holds the
+    // day's observations and weights ((y, w) of a deceased-count cost, or
+    // (y_I, y_R, y_D, w_I, w_R, w_D)), read from LDS before the day's steps
+    // so that the read's latency overlaps them
+    struct DayObs {
+        double v[NS == 3 ? 6 : 2];
+    };
+    auto emit = [&](int i, const DayObs &o) {
         if constexpr (TRAJ) {
             if (active) store_day(tr + (size_t)i * ld, comp_stride, y);
         } else if constexpr (NS == 3) {
-            const double *row = ly + 6 * i;
-            acc_day<ACC>(acc[0], (row[0] - state_value(y.I, y.eI)) * row[3]);
-            acc_day<ACC>(acc[1], (row[1] - state_value(y.Rr, y.eR)) * row[4]);
-            acc_day<ACC>(acc[2], (row[2] - state_value(y.D, y.eD)) * row[5]);
+            acc_day<ACC>(acc[0], (o.v[0] - state_value(y.I, y.eI)) * o.v[3]);
+            acc_day<ACC>(acc[1], (o.v[1] - state_value(y.Rr, y.eR)) * o.v[4]);
+            acc_day<ACC>(acc[2], (o.v[2] - state_value(y.D, y.eD)) * o.v[5]);
         } else {
-            acc_day<ACC>(acc[0], (yw.x - state_value(y.D, y.eD)) * yw.y);
+            acc_day<ACC>(acc[0], (o.v[0] - state_value(y.D, y.eD)) * o.v[1]);
         }
     };
     auto day_obs = [&](int i) {
-        double2 yw = make_double2(0.0, 0.0);
-        if constexpr (!TRAJ && NS == 1) yw = make_double2(ly[2 * i], ly[2 * i + 1]);
-        return yw;
+        DayObs o{};
+        if constexpr (!TRAJ && NS == 1) {
+            o.v[0] = ly[2 * i];
+            o.v[1] = ly[2 * i + 1];
+        } else if constexpr (!TRAJ && NS == 3) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) o.v[c] = ly[6 * i + c];
+        }
+        return o;
     };
     if constexpr (!TRAJ && NS == 1) {
         // SSRE leaves out day 0
@@ -206,23 +234,22 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             if (!WITH_S) rescale(y, sc);
             for (; day < dend; ++day) {
                 if (WITH_S) rescale(y, sc);
-                const double2 yw = day_obs(day + 1);
+                const DayObs o = day_obs(day + 1);
 #pragma unroll 2
                 for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
-                emit(day + 1, yw);
+                emit(day + 1, o);
             }
         }
     } else {
-        const RampConst<R> rc =
-            ramp_const<R>(th[0], th[ld], th[2 * ld], th[3 * ld], gamma, mu, N, spd);
+        const RampConst<R> rc = ramp_const<R>(xr[0], xr[1], xr[2], xr[3], gamma, mu, N, spd);
         const double h = 1.0 / (double)spd;
         int64_t step = 0;
         for (int day = 0; day < W; ++day) {
-            const double2 yw = day_obs(day + 1);
+            const DayObs o = day_obs(day + 1);
             // the ramp is evaluated at the start of each step, t = step h
             for (int s = 0; s < spd; ++s, ++step)
                 euler_ramp_step<R, WITH_R>(y, rc, (double)step * h);
-            emit(day + 1, yw);
+            emit(day + 1, o);
         }
     }
     if (!TRAJ && active) {
