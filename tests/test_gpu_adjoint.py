@@ -125,3 +125,33 @@ def test_full_size_gradient_workload_sampled():
     for p in (0, 12345, 65535):
         Lr, gr = oracle.loss_grad_fwd(prob, thetas[p], f.y, "ssre")
         assert_grad_close(gg[p], gr, f"particle {p}")
+
+
+@pytest.mark.parametrize("spd", [1, 3, 8])
+def test_adjoint_few_steps_per_day_and_zero_beta(spd):
+    """Steps per day below and at the 8-step replay chunk (several day starts
+    in a chunk, or exactly one at its start), a segment with beta = 0, and
+    segments shorter than a chunk: against the oracle's forward-mode
+    gradient, and bitwise the same for every checkpoint interval."""
+    f = synth.c2().fits[0]
+    f.spd = spd
+    f.seg_days = 2 if spd == 1 else f.seg_days  # segments of 2 steps when spd = 1
+    f.K = min(f.K, (f.W + f.seg_days - 1) // f.seg_days)
+    f.lo, f.hi = np.concatenate([f.lo[:f.K], f.lo[-3:]]), np.concatenate([f.hi[:f.K], f.hi[-3:]])
+    th = random_theta(f, 40, seed=11)
+    th[:, :f.K] *= 0.5
+    th[:, 1] = 0.0  # no transmission in the second segment
+    b = make_batch([f], [40])
+    theta, obs = b.pack_theta([th]), b.pack_obs([f.y])
+    prob = oracle_problem(f)
+    ref = None
+    for s in (0, 1, 5, 13):
+        print(f"case spd={spd} interval={s}", flush=True)
+        g, _ = S.sird_loss_backward(b, theta, obs, "ssre", ckpt_interval=s)
+        h = b.unpack_theta(g)[0]
+        if ref is None:
+            ref = h
+            for p in range(0, 40, 7):
+                assert_grad_close(h[p], oracle.loss_grad_fwd(prob, th[p], f.y, "ssre")[1],
+                                  f"spd {spd} particle {p}")
+        assert np.array_equal(h, ref), s
