@@ -168,7 +168,9 @@ def extra_tasks():
               lambda: X.gradients_per_s(*synth.c4())))
     t.append(("gradients", "c4_gradients_65536x7300steps_interval8",
               lambda: X.gradients_per_s(*synth.c4(), ckpt_interval=8)))
-    t.append(("time to fit", "time_to_fit_c2", lambda: X.time_to_fit(synth.c2())))
+    # L-BFGS arms, and two arms with the Adam refinement the protocol names
+    t.append(("time to fit", "time_to_fit_c2",
+              lambda: X.time_to_fit(synth.c2(), adam_arms=((100, 64), (100, 1024)))))
     for dt in ("f64", "f32"):
         t.append(("the paper's own timing case", f"paper_euler_ramp_ird_mxse_10000x92d_{dt}",
                   lambda dt=dt: X.paper_iteration(synth.paper(), dt)))

@@ -107,14 +107,15 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
                 ks=(64, 1024, 4096), refine_steps=2000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6),
-                chunk=50, method="lbfgs") -> Dict:
+                chunk=50, method="lbfgs", adam_arms=()) -> Dict:
     """Wall time from pso_init until the loss is within rel of the best
     loss any run of either arm found (L_best), per seed:
       plain arm: swarm iterations (graph chunks of `chunk`), capped;
       adjoint arm: I' swarm iterations, then refinement of the k best
       personal bests with gradients from the discrete adjoint: projected
       L-BFGS rounds (method "lbfgs", I0 in log coordinates) or projected
-      Adam steps ("adam"); one arm per (I', k).  A round on k vectors of
+      Adam steps ("adam"); one arm per (I', k), plus projected Adam arms
+      for the (I', k) in adam_arms (judged against the same L_best).  A round on k vectors of
       one window costs about the same wall time for any k up to a few
       thousand (one wavefront per 64 vectors), so a larger k refines more
       starting points, and so more basins, at little extra cost.
@@ -147,8 +148,10 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
         g.close()
         curves["plain"][seed] = curve
         _progress(f"time_to_fit plain seed {seed}: {curve[-1][0]:.2f} s, loss {curve[-1][1]:.9g}")
-    for I1, k in [(I1, k) for k in ks for I1 in pso_first]:
-        arm = f"adjoint_I{I1}_k{k}"
+    arms = [(I1, k, method) for k in ks for I1 in pso_first]
+    arms += [(I1, k, "adam") for I1, k in adam_arms]
+    for I1, k, meth in arms:
+        arm = f"adjoint_I{I1}_k{k}" if meth == method else f"{meth}_I{I1}_k{k}"
         curves[arm] = {}
         for seed in seeds:
             b, params, obs = new(seed)
@@ -159,7 +162,7 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
             sird_pso_iterate(b, params, sw, obs, wl.loss, I1)
             best = sw.gbest_f[0].item()  # synchronises
             curve = [(time.perf_counter() - t0, best, 0)]
-            if method == "adam":
+            if meth == "adam":
                 _adam_curve(b, sw, params, obs, wl.loss, k, refine_steps, lr, t0, curve)
             else:
                 _lbfgs_curve(b, sw, params, obs, wl.loss, k, refine_steps, t0, curve)
@@ -177,7 +180,7 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
     res = {"L_best": L_best, "rels": list(rels), "seeds": list(seeds),
            "plain_cap_iterations": plain_cap, "refine": method,
            "refine_steps_cap": refine_steps, "k": list(ks), "pso_first": list(pso_first)}
-    if method == "adam":
+    if method == "adam" or adam_arms:
         res["lr"] = lr
     for arm, runs in curves.items():
         entry = {"final_loss": [runs[s][-1][1] for s in seeds],
