@@ -29,9 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Launch configuration of the integration kernel for the batched workload
-# (block size and persistent wavefronts); what the autotuner of the fused
-# iteration (autotune.autotune_iterate, bench.py --autotune) picks.
-C3_LAUNCH = dict(block=256, persistent=0)
+# (block size, cap on resident wavefronts per SIMD, persistent wavefronts);
+# what the autotuner of the fused iteration (autotune.autotune_iterate,
+# bench.py --autotune) picks.
+C3_LAUNCH = dict(block=256, persistent=0, waves_per_simd=4)
 
 # Algorithmic work of one particle-step of the FP64 forward: the RK4 step
 # on (s = b S, I, D) issues 3 mul + 3 add + 16 fma = 22 VALU instructions =
@@ -311,7 +312,8 @@ def main():
             "particles": b.total_particles,
             "particle_steps_per_step": steps_per_iter,
             "loss": kind,
-            "launch": {"block": b.c.block, "persistent": b.c.persistent},
+            "launch": {"block": b.c.block, "persistent": b.c.persistent,
+                       "waves_per_simd": b.c.waves_per_simd},
         },
         "roofline": {
             "kernel": ("k_forward fused (pso_evaluate: move + Euler with the beta ramp + "

@@ -154,6 +154,12 @@ typedef struct sird_batch {
     int32_t max_part;        /* max n_part over problems; set by
                                 sird_batch_plan (picks the global-best
                                 kernel's shape)                            */
+    int32_t waves_per_simd;  /* 0: as many wavefronts of the integration
+                                kernels per SIMD as registers and LDS allow;
+                                1..8: at most this many (the launch reserves
+                                LDS so that no more blocks fit on a compute
+                                unit; SIRD_EINVAL when the reservation would
+                                exceed 64 KiB per block)                     */
 } sird_batch;
 
 /* Coefficients of the swarm, Sec. 3.3 (inertia, cognitive, social), the
@@ -222,8 +228,8 @@ int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile *tiles_out,
 
 /* Fill the scalar fields of *batch from a host problem table (validated as
  * in sird_problem_validate) and the given device pointers.  traj_len may be
- * 0 if sird_integrate is not used.  block/persistent/dtype are left as the
- * caller set them.  Pure host code. */
+ * 0 if sird_integrate is not used.  block/persistent/waves_per_simd/dtype
+ * are left as the caller set them.  Pure host code. */
 int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,
                     int64_t total_particles, int64_t theta_len, int64_t obs_len,
                     int64_t traj_len, int64_t box_len, int obs_series, int n_tiles,
@@ -265,9 +271,10 @@ int pso_init(const sird_batch *batch, const pso_params *params, const pso_state 
  *   1. personal bests: NaN f counts as +inf; f < pbest_f replaces (f, x);
  *   2. global best per problem: argmin of pbest_f, lowest index on ties,
  *      replacing gbest only on strict improvement; recorded in hist_* row it;
- *   3. velocity and position with r1, r2 from Philox counter
- *      (it, local particle, j/4, 1), word j%4: r1 its high and r2 its low
- *      32 bits, times 2^-32:
+ *   3. velocity and position; dimension j of the d takes slot
+ *      s = (j + 3) mod d (gamma, mu, I0 first), and r1, r2 come from word
+ *      s%4 of the Philox block with counter (it, local particle, s/4, 1):
+ *      r1 its high and r2 its low 32 bits, times 2^-32:
  *        t = w v; t = t + (c1 r1)(pbest - x); t = t + (c2 r2)(gbest - x);
  *        v = t;   x = min(max(x + v, lo), hi)
  *      each operation a single rounded IEEE multiply or add (no fusion);

@@ -268,9 +268,9 @@ void orc_loss_batch(int W, int spd, int seg_days, int K, double N, double R0,
 /* A counter block (iteration, particle, m, purpose) yields four words.  */
 /*   init (purpose 0): block m = j/2 serves dimensions 2m, 2m+1 with     */
 /*     u_j = u01(word 2*(j&1)) (53 bits);                                */
-/*   velocity (purpose 1): block m = j/4 serves dimensions 4m..4m+3;     */
-/*     word j&3 gives r1_j = (high 32 bits) 2^-32 and                    */
-/*     r2_j = (low 32 bits) 2^-32.                                       */
+/*   velocity (purpose 1): dimension j takes slot s = (j+3) mod d;       */
+/*     block m = s/4 serves slots 4m..4m+3 and word s&3 gives            */
+/*     r1_j = (high 32 bits) 2^-32 and r2_j = (low 32 bits) 2^-32.       */
 /* Arrays are row-major [P][d].                                          */
 /* ------------------------------------------------------------------ */
 static void philox_block(uint64_t seed, uint64_t stream, uint64_t it, uint64_t p,
@@ -357,7 +357,12 @@ void orc_pso_bests(int P, int d, const double *f, const double *x,
 /* Velocity and position update of iteration it, every operation a single
  * rounded IEEE multiply or add:
  *   t = w*v;  t = t + (c1*r1)*(pb - x);  t = t + (c2*r2)*(g - x);
- *   v = t;    x = min(max(x + v, lo), hi). */
+ *   v = t;    x = min(max(x + v, lo), hi).
+ * The paper does not say how the random numbers are drawn (Sec. 3.3).
+ * Reading used here: dimension j of a d-dimensional particle takes slot
+ * s = (j + 3) mod d; slot s is word s % 4 of the Philox block with counter
+ * (it, p, s / 4, 1); r1 is that word's high and r2 its low 32 bits, each
+ * times 2^-32.  (The slot order lists the last three parameters first.) */
 void orc_pso_move(int P, int d, uint64_t it, double w, double c1, double c2,
                   const double *lo, const double *hi, uint64_t seed,
                   uint64_t stream, const double *pbest_x, const double *gbest_x,
@@ -366,8 +371,9 @@ void orc_pso_move(int P, int d, uint64_t it, double w, double c1, double c2,
     for (int p = 0; p < P; ++p) {
         for (int j = 0; j < d; ++j) {
             uint64_t wd[4];
-            philox_block(seed, stream, it, (uint64_t)p, (uint64_t)(j / 4), 1, wd);
-            uint64_t word = wd[j % 4];
+            int slot = (j + 3) % d;
+            philox_block(seed, stream, it, (uint64_t)p, (uint64_t)(slot / 4), 1, wd);
+            uint64_t word = wd[slot % 4];
             double r1 = (double)(word >> 32) * (1.0 / 4294967296.0);
             double r2 = (double)(word & 0xffffffffULL) * (1.0 / 4294967296.0);
             long o = (long)p * d + j;

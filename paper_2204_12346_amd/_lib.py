@@ -55,6 +55,7 @@ class sird_batch(ctypes.Structure):
         ("dtype", ctypes.c_int32), ("block", ctypes.c_int32),
         ("persistent", ctypes.c_int32), ("obs_series", ctypes.c_int32),
         ("models", ctypes.c_int32), ("max_part", ctypes.c_int32),
+        ("waves_per_simd", ctypes.c_int32),
     ]
 
 

@@ -1,9 +1,11 @@
 """Autotuner of the integration kernel's launch shape.
 
 Searches threads per block (1, 2, 4 or 8 wavefronts, each on its own
-64-particle tile) and the persistent-queue size (0 = one wavefront per tile
-dispatched longest-first; otherwise that many resident wavefronts pulling
-tiles from a device counter), times sird_loss (autotune) or the fused swarm
+64-particle tile), the cap on resident wavefronts per SIMD of a launch with
+one wavefront per tile, and the persistent-queue size (0 = one wavefront per
+tile dispatched longest-first; otherwise that many resident wavefronts
+pulling tiles from a device counter), times sird_loss (autotune) or the
+fused swarm
 iteration (autotune_iterate) with HIP events, and checks that every
 candidate returns bitwise the same losses as the first -- the launch shape
 must never change results.  Choices are cached in a JSON file keyed by
@@ -18,6 +20,7 @@ from typing import Dict, List, Optional
 import numpy as np
 import torch
 
+from ._lib import SIRD_EINVAL, SirdError
 from .core import Batch, PsoParams, Swarm, pso_evaluate, sird_loss
 
 CACHE_ENV = "SIRD_AUTOTUNE_CACHE"
@@ -38,10 +41,13 @@ def shape_key(batch: Batch) -> str:
 def candidates(n_cu: int) -> List[Dict[str, int]]:
     out = []
     for block in (64, 128, 256, 512):
-        out.append(dict(block=block, persistent=0))
+        out.append(dict(block=block, persistent=0, waves_per_simd=0))
+    for block, caps in ((256, (2, 3, 4, 5)), (64, (3, 4, 5))):
+        for w in caps:
+            out.append(dict(block=block, persistent=0, waves_per_simd=w))
     for wpc in (4, 6, 8, 10, 12, 16):  # resident wavefronts per CU
-        out.append(dict(block=64, persistent=n_cu * wpc))
-    out.append(dict(block=256, persistent=n_cu * 8))
+        out.append(dict(block=64, persistent=n_cu * wpc, waves_per_simd=0))
+    out.append(dict(block=256, persistent=n_cu * 8, waves_per_simd=0))
     return out
 
 
@@ -98,11 +104,18 @@ def _search(batch: Batch, key: str, run, use_cache: bool, verbose: bool,
     times = {i: [] for i in range(len(cands))}
     for r in range(rounds):
         for i, cand in enumerate(cands):
+            if r > 0 and not times[i]:
+                continue  # the library refused this shape in round 0
             batch.configure(**cand)
             if r == 0 and i == 0:
                 for _ in range(max(1, warm // 5)):
                     run()
-            ms, out = run()
+            try:
+                ms, out = run()
+            except SirdError as e:
+                if r == 0 and e.status == SIRD_EINVAL:
+                    continue  # e.g. an LDS reservation beyond a block's limit
+                raise
             if r == 0:
                 h = out.cpu()
                 if ref is None:
@@ -110,8 +123,8 @@ def _search(batch: Batch, key: str, run, use_cache: bool, verbose: bool,
                 elif not torch.equal(h.view(torch.int64), ref.view(torch.int64)):
                     raise RuntimeError(f"launch shape {cand} changed the losses: kernel bug")
             times[i].append(ms)
-    results = sorted(((float(np.median(times[i])), cand) for i, cand in enumerate(cands)),
-                     key=lambda r: r[0])
+    results = sorted(((float(np.median(times[i])), cand) for i, cand in enumerate(cands)
+                      if times[i]), key=lambda r: r[0])
     if verbose:
         for ms, cand in results:
             print(f"autotune {cand}: {ms:.4f} ms", flush=True)

@@ -65,7 +65,7 @@ class Batch:
     lays out I, R and D observations per problem (the F_IRD costs)."""
 
     def __init__(self, specs: Sequence[ProblemSpec], dtype="f64", block=0, persistent=0,
-                 with_traj=False, device="cuda", obs_series=1):
+                 with_traj=False, device="cuda", obs_series=1, waves_per_simd=0):
         specs = list(specs)
         n = len(specs)
         self.obs_series = int(obs_series)
@@ -101,6 +101,7 @@ class Batch:
         b.dtype = SIRD_F32 if dtype in ("f32", SIRD_F32) else SIRD_F64
         b.block = int(block)
         b.persistent = int(persistent)
+        b.waves_per_simd = int(waves_per_simd)
         check(lib().sird_batch_plan(ctypes.byref(b), tab.ctypes.data, n, p_off, theta_off,
                                     obs_off, traj_off, box_off, self.obs_series, nt,
                                     ptr(self.probs_dev),
@@ -109,11 +110,13 @@ class Batch:
         self.c = b
 
     # ------------------------------------------------------------ config
-    def configure(self, block=None, persistent=None, dtype=None):
+    def configure(self, block=None, persistent=None, dtype=None, waves_per_simd=None):
         if block is not None:
             self.c.block = int(block)
         if persistent is not None:
             self.c.persistent = int(persistent)
+        if waves_per_simd is not None:
+            self.c.waves_per_simd = int(waves_per_simd)
         if dtype is not None:
             self.c.dtype = SIRD_F32 if dtype in ("f32", SIRD_F32) else SIRD_F64
         return self

@@ -368,16 +368,25 @@ struct PsoMove {
 };
 
 // Velocity and position update of local particle pl of problem P at swarm
-// iteration it: r1, r2 from Philox counter (it, pl, j/4, 1), word j%4, its
-// high and low 32 bits times 2^-32 (one block serves four dimensions); every
-// operation a single rounded multiply or add (the library is built without
-// contraction):
+// iteration it.  The random numbers of dimension j sit in slot
+// w = (j + 3) mod d: word w%4 of the Philox block with counter
+// (it, pl, w/4, 1), r1 its high and r2 its low 32 bits times 2^-32.  The
+// rotation puts the three trailing parameters (gamma, mu, I0) and the first
+// leading one in block 0, so the integration can start after one block and
+// move the later betas when it reaches them.  Every operation is a single
+// rounded multiply or add (the library is built without contraction):
 //   t = w v; t = t + (c1 r1)(pb - x); t = t + (c2 r2)(g - x);
 //   v = t;   x = min(max(x + v, lo), hi).
 // For the ramp model the positions of t1 and t2 (dimensions 2, 3) are then
 // swapped when t1 > t2, so that every particle describes a ramp.
 __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_problem &P,
                                                   int pl, uint64_t it);
+
+// Dimension whose random numbers are in slot w of a d-dimensional particle.
+__device__ __forceinline__ int move_slot_dim(int w, int d)
+{
+    return w >= 3 ? w - 3 : w + d - 3;
+}
 
 // Ramp model: keep t1 <= t2 (dimensions 2 and 3) of a theta-shaped array.
 __device__ __forceinline__ void ramp_order(double *x, const sird_problem &P, int pl)
@@ -403,7 +412,15 @@ __device__ __forceinline__ void pso_pbest_particle(double f, const sird_problem 
         const int d = P.n_seg + 3;
         const size_t n = (size_t)P.n_part;
         const size_t base = (size_t)P.theta_off + pl;
-        for (int j = 0; j < d; ++j) pbest_x[base + (size_t)j * n] = x[base + (size_t)j * n];
+        // eight loads in flight before their stores
+        for (int j0 = 0; j0 < d; j0 += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = x[base + (size_t)min(j0 + u, d - 1) * n];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u < d) pbest_x[base + (size_t)(j0 + u) * n] = t[u];
+        }
     }
 }
 
@@ -421,77 +438,152 @@ __device__ __forceinline__ T wave_uniform(T v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// One dimension of the move: offset o of the theta-shaped arrays, r the
-// Philox word whose high and low halves give r1 and r2, g, lo and hi the
-// dimension's global best and bounds.  Returns the new x.
-__device__ __forceinline__ double pso_move_dim(const PsoMove &m, size_t o, uint64_t r,
-                                               const double *g, const double *lo,
-                                               const double *hi)
+// The dimensions of one Philox block of a particle's move, loaded ahead of
+// the block's rounds so that the memory latency overlaps them.  Slots past
+// d load the last dimension again and are never stored.
+struct MoveBlock {
+    double x[4], v[4], pb[4];
+};
+
+__device__ __forceinline__ void pso_move_load(const PsoMove &m, const sird_problem &P, int pl,
+                                              int q, MoveBlock &b)
 {
-    const double r1 = (double)(uint32_t)(r >> 32) * 0x1.0p-32;
-    const double r2 = (double)(uint32_t)r * 0x1.0p-32;
-    const double xo = m.x[o];
-    double tv = m.w * m.v[o];
-    const double a1 = m.c1 * r1;
-    const double d1 = m.pbest_x[o] - xo;
-    const double a2 = m.c2 * r2;
-    const double d2 = *g - xo;
-    const double m1 = a1 * d1;
-    tv = tv + m1;
-    const double m2 = a2 * d2;
-    tv = tv + m2;
-    m.v[o] = tv;
-    double xn = xo + tv;
-    if (xn < *lo) xn = *lo;
-    if (xn > *hi) xn = *hi;
-    m.x[o] = xn;
-    return xn;
+    const int d = P.n_seg + 3;
+    const size_t n = (size_t)P.n_part;
+    const size_t base = (size_t)P.theta_off + pl;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int w = min(4 * q + s, d - 1);
+        const size_t o = base + (size_t)move_slot_dim(w, d) * n;
+        b.x[s] = m.x[o];
+        b.v[s] = m.v[o];
+        b.pb[s] = m.pbest_x[o];
+    }
+}
+
+// New velocity and position of the slots of block q from the values loaded
+// by pso_move_load; x and v are stored and the new positions returned by
+// slot in xn.
+__device__ __forceinline__ void pso_move_commit(const PsoMove &m, const sird_problem &P, int pl,
+                                                uint64_t it, int q, const MoveBlock &b,
+                                                double (&xn)[4])
+{
+    const int d = P.n_seg + 3;
+    const size_t n = (size_t)P.n_part;
+    const size_t base = (size_t)P.theta_off + pl;
+    const double *g = m.gbest_x + P.box_off;
+    const double *lo = m.lo + P.box_off;
+    const double *hi = m.hi + P.box_off;
+    const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int w = min(4 * q + s, d - 1);
+        const int j = move_slot_dim(w, d);
+        const double r1 = (double)(uint32_t)(r.w[s] >> 32) * 0x1.0p-32;
+        const double r2 = (double)(uint32_t)r.w[s] * 0x1.0p-32;
+        const double xo = b.x[s];
+        double tv = m.w * b.v[s];
+        const double a1 = m.c1 * r1;
+        const double d1 = b.pb[s] - xo;
+        const double a2 = m.c2 * r2;
+        const double d2 = g[j] - xo;
+        const double m1 = a1 * d1;
+        tv = tv + m1;
+        const double m2 = a2 * d2;
+        tv = tv + m2;
+        double x1 = xo + tv;
+        if (x1 < lo[j]) x1 = lo[j];
+        if (x1 > hi[j]) x1 = hi[j];
+        xn[s] = x1;
+        if (4 * q + s < d) {
+            const size_t o = base + (size_t)j * n;
+            m.v[o] = tv;
+            m.x[o] = x1;
+        }
+    }
+}
+
+__device__ __forceinline__ void pso_move_block(const PsoMove &m, const sird_problem &P, int pl,
+                                               uint64_t it, int q, double (&xn)[4])
+{
+    MoveBlock b;
+    pso_move_load(m, P, pl, q, b);
+    pso_move_commit(m, P, pl, it, q, b, xn);
+}
+
+// The same block with each slot loaded, updated and stored in turn: fewer
+// registers, for use while an integration's state is live (its memory
+// latency is then covered by the other wavefronts of the SIMD).
+__device__ __forceinline__ void pso_move_block_seq(const PsoMove &m, const sird_problem &P,
+                                                   int pl, uint64_t it, int q, double (&xn)[4])
+{
+    const int d = P.n_seg + 3;
+    const size_t n = (size_t)P.n_part;
+    const size_t base = (size_t)P.theta_off + pl;
+    const double *g = m.gbest_x + P.box_off;
+    const double *lo = m.lo + P.box_off;
+    const double *hi = m.hi + P.box_off;
+    const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (4 * q + s >= d) break;
+        const int j = move_slot_dim(4 * q + s, d);
+        const size_t o = base + (size_t)j * n;
+        const double r1 = (double)(uint32_t)(r.w[s] >> 32) * 0x1.0p-32;
+        const double r2 = (double)(uint32_t)r.w[s] * 0x1.0p-32;
+        const double xo = m.x[o];
+        double tv = m.w * m.v[o];
+        const double a1 = m.c1 * r1;
+        const double d1 = m.pbest_x[o] - xo;
+        const double a2 = m.c2 * r2;
+        const double d2 = g[j] - xo;
+        const double m1 = a1 * d1;
+        tv = tv + m1;
+        const double m2 = a2 * d2;
+        tv = tv + m2;
+        double x1 = xo + tv;
+        if (x1 < lo[j]) x1 = lo[j];
+        if (x1 > hi[j]) x1 = hi[j];
+        m.v[o] = tv;
+        m.x[o] = x1;
+        xn[s] = x1;
+    }
 }
 
 __device__ __forceinline__ void pso_move_particle(const PsoMove &m, const sird_problem &P,
                                                   int pl, uint64_t it)
 {
     const int d = P.n_seg + 3;
-    const size_t n = (size_t)P.n_part;
-    const double *lo = m.lo + P.box_off;
-    const double *hi = m.hi + P.box_off;
-    const double *g = m.gbest_x + P.box_off;
-    const size_t base = (size_t)P.theta_off + pl;
     for (int q = 0; 4 * q < d; ++q) {
-        const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
-        for (int jj = 0; jj < 4; ++jj) {
-            const int j = 4 * q + jj;
-            if (j >= d) break;
-            pso_move_dim(m, base + (size_t)j * n, r.w[jj], g + j, lo + j, hi + j);
-        }
+        double xn[4];
+        pso_move_block(m, P, pl, it, q, xn);
     }
     if (P.model == SIRD_MODEL_EULER_RAMP) ramp_order(m.x, P, pl);
 }
 
-// The same move for the ramp model (d = 7, so fully unrolled), with the new
-// position also returned in xr (t1 <= t2 as stored): the caller integrates
-// from registers instead of reading x back.
+// The same move for the ramp model (d = 7: two blocks, slots (gamma, mu,
+// I0, beta1) and (beta2, t1, t2)), with the new position also returned in
+// xr by dimension (t1 <= t2 as stored): the caller integrates from
+// registers instead of reading x back.
 __device__ __forceinline__ void pso_move_ramp(const PsoMove &m, const sird_problem &P, int pl,
                                               uint64_t it, double (&xr)[7])
 {
-    const size_t n = (size_t)P.n_part;
-    const double *lo = m.lo + P.box_off;
-    const double *hi = m.hi + P.box_off;
-    const double *g = m.gbest_x + P.box_off;
-    const size_t base = (size_t)P.theta_off + pl;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const Philox4x64 r = philox4x64_10(it, (uint64_t)pl, (uint64_t)q, 1, m.seed, P.stream);
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int j = 4 * q + jj;
-            if (j < 7) xr[j] = pso_move_dim(m, base + (size_t)j * n, r.w[jj], g + j, lo + j, hi + j);
-        }
-    }
+    double x0[4] = {0.0, 0.0, 0.0, 0.0}, x1[4] = {0.0, 0.0, 0.0, 0.0};
+    pso_move_block_seq(m, P, pl, it, 0, x0);
+    pso_move_block_seq(m, P, pl, it, 1, x1);
+    xr[4] = x0[0];
+    xr[5] = x0[1];
+    xr[6] = x0[2];
+    xr[0] = x0[3];
+    xr[1] = x1[0];
+    xr[2] = x1[1];
+    xr[3] = x1[2];
     if (xr[2] > xr[3]) {
         const double t = xr[2];
         xr[2] = xr[3];
         xr[3] = t;
+        const size_t n = (size_t)P.n_part;
+        const size_t base = (size_t)P.theta_off + pl;
         m.x[base + 2 * n] = xr[2];
         m.x[base + 3 * n] = xr[3];
     }

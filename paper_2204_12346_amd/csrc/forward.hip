@@ -65,10 +65,19 @@ __device__ __forceinline__ void stage_d(const FwdArgs &a, const sird_problem &P,
 {
     const int W = P.n_days;
     const double *y = a.obs + P.obs_off + (size_t)(a.obs_series - 1) * (W + 1);
-    for (int i = lane; i <= W; i += kWave) {
-        const double yi = y[i];
-        ly[2 * i] = yi;
-        ly[2 * i + 1] = a.cost.w_rel ? 1.0 / fmax(yi, 1.0) : 1.0;
+    // four loads in flight before their LDS stores
+    for (int i0 = lane; i0 <= W; i0 += 4 * kWave) {
+        double yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yv[u] = y[min(i0 + u * kWave, W)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * kWave;
+            if (i <= W) {
+                ly[2 * i] = yv[u];
+                ly[2 * i + 1] = a.cost.w_rel ? 1.0 / fmax(yv[u], 1.0) : 1.0;
+            }
+        }
     }
 }
 
@@ -139,14 +148,20 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             stage_d(a, P, lane, ly);
         wave_sync();
     }
-    // the ramp model's parameters (d = 7): from the move's registers when
-    // the kernel moves the swarm (idle lanes take the box's lower corner),
-    // else from x
+    // Moving the swarm first: the ramp model's parameters (d = 7) come from
+    // the move's registers (idle lanes take the box's lower corner); the
+    // RK4 model moves Philox block 0 (gamma, mu, I0, beta_0) here and each
+    // later block of four betas in the segment loop, four segments ahead of
+    // its last one, so the swarm's memory traffic is spread over the
+    // integration instead of stalling every wavefront at its start.
+    const bool lazy = MODEL == SIRD_MODEL_RK4_SEGMENTS && FUSED && a.do_move;
+    const uint64_t it = FUSED && a.do_move ? a.iter[0] - 1 : 0;
     double xr[7];
+    double mv0[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (MODEL == SIRD_MODEL_EULER_RAMP) {
         if (FUSED && a.do_move) {
             if (active) {
-                pso_move_ramp(a.mv, P, pl, a.iter[0] - 1, xr);
+                pso_move_ramp(a.mv, P, pl, it, xr);
             } else {
 #pragma unroll
                 for (int j = 0; j < 7; ++j) xr[j] = a.mv.lo[P.box_off + j];
@@ -155,14 +170,15 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
 #pragma unroll
             for (int j = 0; j < 7; ++j) xr[j] = th[(size_t)j * ld];
         }
-    } else if (FUSED && a.do_move && active) {
-        pso_move_particle(a.mv, P, pl, a.iter[0] - 1);
+    } else if (lazy && active) {
+        pso_move_block_seq(a.mv, P, pl, it, 0, mv0);
     }
+    const bool from_move = lazy && active;
 
     const bool ramp = MODEL == SIRD_MODEL_EULER_RAMP;
-    const double gamma = ramp ? xr[4] : th[(size_t)K * ld];
-    const double mu = ramp ? xr[5] : th[(size_t)(K + 1) * ld];
-    const double I0 = ramp ? xr[6] : th[(size_t)(K + 2) * ld];
+    const double gamma = ramp ? xr[4] : (from_move ? mv0[0] : th[(size_t)K * ld]);
+    const double mu = ramp ? xr[5] : (from_move ? mv0[1] : th[(size_t)(K + 1) * ld]);
+    const double I0 = ramp ? xr[6] : (from_move ? mv0[2] : th[(size_t)(K + 2) * ld]);
     const double N = P.N;
 
     SirdState<R> y;
@@ -223,10 +239,19 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         const double invN = 1.0 / N;
         const int seg = P.seg_days;
         int day = 0;
-        double beta_next = th[0];
+        double beta_next = from_move ? mv0[3] : th[0];
         for (int k = 0; k < K; ++k) {
             const double beta_k = beta_next;
-            if (k + 1 < K) beta_next = th[(size_t)(k + 1) * ld];  // prefetch
+            if (k + 1 < K) {
+                if (lazy && (k & 3) == 0) {
+                    // block k/4 + 1: slots k+4 .. k+7, beta_{k+1} .. beta_{k+4}
+                    double xn[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (active) pso_move_block_seq(a.mv, P, pl, it, k / 4 + 1, xn);
+                    beta_next = active ? xn[0] : th[(size_t)(k + 1) * ld];
+                } else {
+                    beta_next = th[(size_t)(k + 1) * ld];  // prefetch
+                }
+            }
             const int dend = (k == K - 1) ? W : (int)min((long)W, (long)(k + 1) * seg);
             if (day >= dend) continue;
             if (!WITH_S && day > 0) unscale(y, sc);
@@ -314,6 +339,25 @@ static CostPlan cost_plan(int kind)
     }
 }
 
+// LDS to reserve per block so that a compute unit (4 SIMDs, its LDS shared
+// by the blocks resident on it) holds at most waves_per_simd wavefronts per
+// SIMD: with wpb wavefronts per block that is nb = 4 waves_per_simd / wpb
+// blocks, so each block claims more than 1/(nb + 1) of the LDS (rounded up
+// to the 512-byte allocation unit) and at most 1/nb of it.  0 if no
+// reservation does it.
+static size_t occupancy_lds(int waves_per_simd, int wpb)
+{
+    int dev = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              dev) != hipSuccess || per_cu <= 0)
+        return 0;
+    const int nb = 4 * waves_per_simd / wpb;
+    if (nb < 1) return 0;
+    const size_t bytes = ((size_t)per_cu / (nb + 1) / 512 + 1) * 512;
+    return bytes <= (size_t)per_cu / nb ? bytes : 0;
+}
+
 template <typename R, bool TRAJ, bool FUSED, int NS, int ACC>
 static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const char *who)
 {
@@ -321,10 +365,17 @@ static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const c
     const int wpb = block / kWave;
     a.obs_series = b->obs_series;
     a.lds_stride = (NS == 3 ? 6 : 2) * (b->max_days + 1);
-    const size_t lds = TRAJ ? 0 : (size_t)wpb * a.lds_stride * sizeof(double);
+    size_t lds = TRAJ ? 0 : (size_t)wpb * a.lds_stride * sizeof(double);
     if (lds > 65536)
         return fail(SIRD_EINVAL, std::string(who) +
                                      ": block too large for the window length (LDS > 64 KiB)");
+    if (b->waves_per_simd > 0) {
+        const size_t cap = occupancy_lds(b->waves_per_simd, wpb);
+        if (cap == 0 || cap > 65536)
+            return fail(SIRD_EINVAL, std::string(who) +
+                                         ": waves_per_simd too small for the block size");
+        if (lds < cap) lds = cap;
+    }
     int grid;
     if (b->persistent > 0) {
         grid = (b->persistent + wpb - 1) / wpb;

@@ -44,6 +44,8 @@ int check_batch(const sird_batch *b, const char *who)
     if (b->block != 0 && (b->block < 64 || b->block > 1024 || b->block % 64 != 0))
         return fail(SIRD_EINVAL, w + ": block must be 0 or a multiple of 64 in [64, 1024]");
     if (b->persistent < 0) return fail(SIRD_EINVAL, w + ": persistent < 0");
+    if (b->waves_per_simd < 0 || b->waves_per_simd > 8)
+        return fail(SIRD_EINVAL, w + ": waves_per_simd must be in [0, 8]");
     if (b->persistent > 0 && !b->sched)
         return fail(SIRD_EINVAL, w + ": persistent launch needs sched counters");
     if (b->obs_series != 1 && b->obs_series != 3)

@@ -201,6 +201,13 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
                          dummy.data_ptr(), None) == L.SIRD_EINVAL
     b.c.block = 0
+    assert b.c.waves_per_simd == 0
+    for w in (-1, 9):
+        b.c.waves_per_simd = w
+        assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
+                             dummy.data_ptr(), None) == L.SIRD_EINVAL
+        assert b"waves_per_simd" in lib.sird_last_error()
+    b.c.waves_per_simd = 0
     ws = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 0)
     s = int(np.ceil(np.sqrt(300)))
     # 3 per checkpoint, 3 per 8-step chunk of one interval, one per day

@@ -92,14 +92,19 @@ def test_launch_shapes_are_bitwise_equivalent():
     theta = b.pack_theta(ths)
     obs = b.pack_obs([f.y for f in wl.fits])
     ref = S.sird_loss(b, theta, obs, "ssre").cpu().numpy()
-    for block, pers in [(64, 0), (128, 0), (512, 0), (640, 0), (64, 37), (256, 256),
-                        (256, 1), (128, 4096)]:
-        print(f"case launch block={block} persistent={pers}", flush=True)
-        b.configure(block=block, persistent=pers)
+    for block, pers, cap in [(64, 0, 0), (128, 0, 0), (512, 0, 0), (640, 0, 0), (64, 37, 0),
+                             (256, 256, 0), (256, 1, 0), (128, 4096, 0), (256, 0, 2),
+                             (256, 0, 4), (64, 0, 1), (64, 0, 5), (512, 0, 4), (64, 37, 3)]:
+        print(f"case launch block={block} persistent={pers} waves_per_simd={cap}", flush=True)
+        b.configure(block=block, persistent=pers, waves_per_simd=cap)
         for rep in range(2):  # the persistent counters must reset between launches
             got = S.sird_loss(b, theta, obs, "ssre").cpu().numpy()
-            assert np.array_equal(got, ref), (block, pers, rep)
-    b.configure(block=0, persistent=0)
+            assert np.array_equal(got, ref), (block, pers, cap, rep)
+    # a cap that no LDS reservation within one block's 64 KiB can enforce
+    b.configure(block=256, persistent=0, waves_per_simd=1)
+    with pytest.raises(S.SirdError, match="waves_per_simd"):
+        S.sird_loss(b, theta, obs, "ssre")
+    b.configure(block=0, persistent=0, waves_per_simd=0)
 
 
 def test_edge_cases():

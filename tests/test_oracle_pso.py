@@ -36,20 +36,22 @@ def test_init_uses_counter_blocks(orc):
 
 
 def test_one_step_by_hand(orc):
-    # two particles in 3-D, hand-set state; r from numpy's Philox
-    lo = np.array([0.0, 0.0, 0.0])
-    hi = np.array([1.0, 1.0, 1.0])
+    # two particles in 6-D (two Philox blocks), hand-set state; r from
+    # numpy's Philox, dimension j in slot (j + 3) mod d
+    d = 6
+    lo, hi = np.zeros(d), np.ones(d)
     s = orc.pso_init(2, lo, hi, seed=5, stream=2)
-    s.x[:] = [[0.5, 0.25, 0.75], [0.125, 0.5, 0.875]]
-    s.v[:] = [[0.0625, -0.125, 0.25], [0.5, 0.0, -0.25]]
-    s.pbest_x[:] = [[0.25, 0.5, 1.0], [0.0, 0.75, 0.5]]
-    s.gbest_x[:] = [0.0, 0.75, 0.5]
+    s.x[:] = [[0.5, 0.25, 0.75, 0.125, 0.625, 0.375], [0.125, 0.5, 0.875, 0.25, 0.0, 1.0]]
+    s.v[:] = [[0.0625, -0.125, 0.25, 0.5, -0.5, 0.0], [0.5, 0.0, -0.25, 0.125, 0.75, -1.0]]
+    s.pbest_x[:] = [[0.25, 0.5, 1.0, 0.0, 0.75, 0.5], [0.0, 0.75, 0.5, 1.0, 0.25, 0.5]]
+    s.gbest_x[:] = [0.0, 0.75, 0.5, 1.0, 0.25, 0.5]
     w, c1, c2, it = 0.7, 1.5, 1.5, 3
     x0, v0 = s.x.copy(), s.v.copy()
     orc.pso_move(s, it, w, c1, c2, lo, hi, seed=5, stream=2)
     for p in range(2):
-        for j in range(3):
-            word = int(np_block(it, p, j // 4, 1, 5, 2)[j % 4])
+        for j in range(d):
+            slot = (j + 3) % d
+            word = int(np_block(it, p, slot // 4, 1, 5, 2)[slot % 4])
             r1, r2 = (word >> 32) * 2.0 ** -32, (word & 0xFFFFFFFF) * 2.0 ** -32
             t = w * v0[p, j]
             t = t + (c1 * r1) * (s.pbest_x[p, j] - x0[p, j])
