@@ -167,8 +167,8 @@ def extra_tasks():
                                          launch=dict(C3_LAUNCH))))
     t.append(("gradients", "c4_gradients_65536x7300steps",
               lambda: X.gradients_per_s(*synth.c4())))
-    t.append(("gradients", "c4_gradients_65536x7300steps_interval8",
-              lambda: X.gradients_per_s(*synth.c4(), ckpt_interval=8)))
+    t.append(("gradients", "c4_gradients_65536x7300steps_interval10",
+              lambda: X.gradients_per_s(*synth.c4(), ckpt_interval=10)))
     # L-BFGS arms, and two arms with the Adam refinement the protocol names
     t.append(("time to fit", "time_to_fit_c2",
               lambda: X.time_to_fit(synth.c2(), adam_arms=((100, 64), (100, 1024)))))

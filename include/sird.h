@@ -321,7 +321,10 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
  *   grad_loss: optional particle-indexed upstream gradient (NULL = 1).
  *   grad_theta: output, theta-shaped: grad_loss[p] * dL/dtheta.
  *   loss_out: optional particle-indexed output of the loss itself.
- *   ckpt_interval: steps between checkpoints, 0 = ceil(sqrt(max_steps)).
+ *   ckpt_interval: steps between checkpoints, 0 = ceil(sqrt(max_steps))
+ *       rounded up to a multiple of 10.  Problems whose steps per day and
+ *       interval are both multiples of 10 are reversed 10 steps at a time
+ *       with no per-step tests (faster; the same result).
  *   workspace: device scratch of at least
  *       sird_loss_backward_workspace(batch, ckpt_interval) bytes, 256-byte
  *       aligned; contents on entry are ignored.

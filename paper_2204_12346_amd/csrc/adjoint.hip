@@ -149,6 +149,11 @@ __device__ __forceinline__ void rk4_adjoint_step(double S, double I, double &aS,
 
 // Steps replayed into registers at a time in the reverse sweep.
 constexpr int kChunk = 8;
+// Chunk length of the aligned sweep: when it divides both the steps per day
+// and the checkpoint interval, every day start, segment start and interval
+// start falls on a chunk start, so a chunk's steps are replayed and
+// reversed with no test between them.
+constexpr int kAlign = 10;
 
 __device__ __forceinline__ int seg_of(int n, int SS, int K)
 {
@@ -274,6 +279,7 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     int seg_lo = kr * SS;  // first step of segment kr
 
     const int n_ck = (T + a.s - 1) / a.s;
+    const bool aligned = spd % kAlign == 0 && a.s % kAlign == 0;
     // the checkpoint of the interval to reverse next, loaded one interval
     // ahead
     double cS, cI, cs_;
@@ -292,6 +298,111 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
             cS = active ? cp[0] : 0.0;
             cI = active ? cp[PS] : 0.0;
             cs_ = active ? cp[2 * PS] : 0.0;
+        }
+        if (aligned) {
+            // Aligned sweep: chunks of kAlign steps; the interval and every
+            // chunk are whole (T, s and the day are multiples of kAlign), a
+            // chunk lies in one segment and only its first step can start a
+            // day.  The operations are those of the general sweep below, in
+            // the same order, so the gradient is bitwise the same.
+            const int nc = (n1 - n0) / kAlign;
+            // pass 1: chunk start states 1 .. nc-2 to the workspace; the last
+            // chunk's stays in registers
+            double lastS = ckS, lastI = ckI, lasts = cks;
+            if (nc > 1) {
+                SirdState<double> yr;
+                yr.S = ckS;
+                yr.I = ckI;
+                yr.s = cks;
+                yr.Rr = yr.D = 0.0;
+                yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
+                int kf = seg_of(n0, SS, K);
+                StepConst<double> sf = sc;
+                set_beta(sf, th[(size_t)kf * ld], invN);
+                double *ip = in_ws + 3 * PS;
+                for (int c = 0; c < nc - 1; ++c) {
+                    const int st = n0 + c * kAlign;
+                    if (st % spd == 0) {
+                        if (kf < K - 1 && st == (kf + 1) * SS) {
+                            ++kf;
+                            set_beta(sf, th[(size_t)kf * ld], invN);
+                        }
+                        rescale(yr, sf);
+                    }
+#pragma unroll
+                    for (int i = 0; i < kAlign; ++i) rk4_step<double, false>(yr, sf);
+                    if (c + 1 < nc - 1) {
+                        if (active) {
+                            ip[0] = yr.S;
+                            ip[PS] = yr.I;
+                            ip[2 * PS] = yr.s;
+                        }
+                        ip += 3 * PS;
+                    }
+                }
+                lastS = yr.S;
+                lastI = yr.I;
+                lasts = yr.s;
+            }
+            // pass 2: chunks last to first, the next one's start state and
+            // day-start Dhat loaded before the current one is walked
+            double nS, nI, ns, nD;
+            auto load_chunk = [&](int c) {
+                if (c == 0) {
+                    nS = ckS;
+                    nI = ckI;
+                    ns = cks;
+                } else if (c == nc - 1) {
+                    nS = lastS;
+                    nI = lastI;
+                    ns = lasts;
+                } else {
+                    const double *sp = in_ws + (size_t)(3 * c) * PS;
+                    nS = active ? sp[0] : 0.0;
+                    nI = active ? sp[PS] : 0.0;
+                    ns = active ? sp[2 * PS] : 0.0;
+                }
+                const int cs = n0 + c * kAlign;
+                nD = (active && cs % spd == 0) ? day_ws[(size_t)(cs / spd) * PS] : 0.0;
+            };
+            load_chunk(nc - 1);
+            for (int c = nc - 1; c >= 0; --c) {
+                const int cs = n0 + c * kAlign;
+                SirdState<double> yr;
+                yr.S = nS;
+                yr.I = nI;
+                yr.s = ns;
+                yr.Rr = yr.D = 0.0;
+                yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
+                const double Dd = nD;
+                if (c > 0) load_chunk(c - 1);
+                // the chunk is in the reverse's segment kr
+                const bool day_start = cs % spd == 0;
+                if (day_start) rescale(yr, sc);
+                double Sa[kAlign], Ia[kAlign];
+#pragma unroll
+                for (int j = 0; j < kAlign; ++j) {
+                    Sa[j] = yr.S;
+                    Ia[j] = yr.I;
+                    rk4_step<double, false>(yr, sc);
+                }
+#pragma unroll
+                for (int j = kAlign - 1; j >= 0; --j)
+                    rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, h3, g);
+                if (day_start) {
+                    const int i = cs / spd;
+                    aD += cost_grad(KIND, i, W, Dd, ly[i], lw[i], imax);
+                    if (cs == seg_lo && kr > 0) {
+                        // the chunk's first step opened segment kr
+                        if (active) gout[(size_t)kr * ld] = (g.beta * invN) * gl;
+                        g.beta = 0.0;
+                        --kr;
+                        seg_lo -= SS;
+                        set_beta(sc, th[(size_t)kr * ld], invN);
+                    }
+                }
+            }
+            continue;
         }
         const int n_chunks = (n1 - n0 + kChunk - 1) / kChunk;
         // pass 1: replay the interval from its checkpoint with exactly the
@@ -495,11 +606,14 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     }
 }
 
+// The checkpoint interval: as given, else ceil(sqrt(T)) rounded up to a
+// multiple of kAlign (so that problems whose steps per day are a multiple
+// of kAlign take the aligned sweep).
 static int resolve_interval(const sird_batch *b, int ckpt_interval)
 {
     if (ckpt_interval > 0) return ckpt_interval;
-    int s = (int)std::ceil(std::sqrt((double)b->max_steps));
-    return s < 1 ? 1 : s;
+    const int s = (int)std::ceil(std::sqrt((double)b->max_steps));
+    return (s + kAlign - 1) / kAlign * kAlign;
 }
 
 // Workspace slots per particle: 3 per checkpoint (S, I, s), 3 per chunk of

@@ -22,12 +22,13 @@ from .core import (Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm, pso_
 # Checkpoint interval of the adjoint that the refinement drivers use when
 # the workspace allows: the reverse sweep replays 8 steps at a time into
 # registers, so an interval of 8 leaves nothing else to replay.
-SHORT_INTERVAL = 8
+SHORT_INTERVAL = 10
 
 
 def refine_interval(batch: Batch, budget_bytes=1 << 28) -> int:
-    """ckpt_interval for sird_loss_backward on this batch: 8 when its
-    workspace fits budget_bytes, else 0 (ceil(sqrt(T)))."""
+    """ckpt_interval for sird_loss_backward on this batch: 10 when its
+    workspace fits budget_bytes, else 0 (ceil(sqrt(T)) rounded up to a
+    multiple of 10)."""
     if sird_loss_backward_workspace(batch, SHORT_INTERVAL) <= budget_bytes:
         return SHORT_INTERVAL
     return 0

@@ -209,7 +209,7 @@ def test_batch_plan_and_per_call_checks_on_host(L):
         assert b"waves_per_simd" in lib.sird_last_error()
     b.c.waves_per_simd = 0
     ws = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 0)
-    s = int(np.ceil(np.sqrt(300)))
+    s = int(np.ceil(np.sqrt(300) / 10)) * 10
     # 3 per checkpoint, 3 per 8-step chunk of one interval, one per day
     assert ws == (3 * int(np.ceil(300 / s)) + 3 * int(np.ceil(s / 8)) + 46) * 165 * 8
     # too small a workspace is reported before anything is enqueued

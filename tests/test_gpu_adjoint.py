@@ -127,15 +127,19 @@ def test_full_size_gradient_workload_sampled():
         assert_grad_close(gg[p], gr, f"particle {p}")
 
 
-@pytest.mark.parametrize("spd", [1, 3, 8])
+@pytest.mark.parametrize("spd", [1, 3, 8, 10, 20])
 def test_adjoint_few_steps_per_day_and_zero_beta(spd):
     """Steps per day below and at the 8-step replay chunk (several day starts
     in a chunk, or exactly one at its start), a segment with beta = 0, and
-    segments shorter than a chunk: against the oracle's forward-mode
-    gradient, and bitwise the same for every checkpoint interval."""
+    segments shorter than a chunk; with 10 or 20 steps per day, one-day
+    segments and intervals that are multiples of 10 (the aligned 10-step
+    sweep) next to intervals that are not (the general one): against the
+    oracle's forward-mode gradient, and bitwise the same for every
+    checkpoint interval."""
     f = synth.c2().fits[0]
     f.spd = spd
-    f.seg_days = 2 if spd == 1 else f.seg_days  # segments of 2 steps when spd = 1
+    # segments of 2 steps when spd = 1, of one day when spd >= 10
+    f.seg_days = 2 if spd == 1 else (1 if spd >= 10 else f.seg_days)
     f.K = min(f.K, (f.W + f.seg_days - 1) // f.seg_days)
     f.lo, f.hi = np.concatenate([f.lo[:f.K], f.lo[-3:]]), np.concatenate([f.hi[:f.K], f.hi[-3:]])
     th = random_theta(f, 40, seed=11)
@@ -145,7 +149,7 @@ def test_adjoint_few_steps_per_day_and_zero_beta(spd):
     theta, obs = b.pack_theta([th]), b.pack_obs([f.y])
     prob = oracle_problem(f)
     ref = None
-    for s in (0, 1, 5, 13):
+    for s in (0, 1, 5, 13, 10, 30):
         print(f"case spd={spd} interval={s}", flush=True)
         g, _ = S.sird_loss_backward(b, theta, obs, "ssre", ckpt_interval=s)
         h = b.unpack_theta(g)[0]
