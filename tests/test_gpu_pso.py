@@ -8,7 +8,8 @@ import torch
 import oracle
 import synth
 import paper_2204_12346_amd as S
-from gpu_helpers import make_batch, need_gpu, oracle_problem
+from gpu_helpers import (TOL64, assert_loss_close, kappa, make_batch, need_gpu,
+                         oracle_problem)
 
 pytestmark = pytest.mark.gpu
 
@@ -186,6 +187,7 @@ def test_resume_is_bitwise():
 
 
 @pytest.mark.parametrize("dtype,launch", [("f64", dict(block=256, persistent=0)),
+                                          ("f64", dict(block=256, persistent=0, waves_per_simd=4)),
                                           ("f64", dict(block=64, persistent=300)),
                                           ("f32", dict(block=128, persistent=0))])
 def test_fused_iterate_equals_loss_plus_step(dtype, launch):
@@ -220,3 +222,43 @@ def test_fused_iterate_equals_loss_plus_step(dtype, launch):
     for other in states[1:]:
         for a, c in zip(states[0], other):
             assert np.array_equal(a, c, equal_nan=True)
+
+
+def test_full_size_fused_evaluate_sampled():
+    """The benchmark's step at full size (512 regions x 1024 particles, the
+    benchmark's launch): after two iterations, one pso_evaluate with the
+    move.  For every 16th region the whole move is checked bitwise against
+    the oracle's swarm update of the state before it, and two particles'
+    losses against the oracle's loss of the moved positions."""
+    from bench import C3_LAUNCH
+    wl = synth.c3()
+    b = make_batch(wl.fits, **C3_LAUNCH)
+    params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
+                         wl.c2, wl.seed)
+    sw = S.Swarm(b)
+    obs = b.pack_obs([f.y for f in wl.fits])
+    S.pso_init(b, params, sw)
+    S.pso_evaluate(b, params, sw, obs, "ssre", move_first=False)
+    S.pso_gbest(b, params, sw)
+    S.pso_evaluate(b, params, sw, obs, "ssre", move_first=True)
+    S.pso_gbest(b, params, sw)
+    torch.cuda.synchronize()
+    regions = list(range(0, len(wl.fits), 16))
+    before = {r: _swarm_to_oracle(b, sw, r) for r in regions}
+    it = int(sw.iter[0].item())
+    print(f"case full-size fused evaluate, iteration {it}", flush=True)
+    S.pso_evaluate(b, params, sw, obs, "ssre", move_first=True)
+    torch.cuda.synchronize()
+    f_all = b.split_particles(sw.f)
+    for r in regions:
+        f = wl.fits[r]
+        ref = before[r]
+        oracle.pso_move(ref, it - 1, wl.w, wl.c1, wl.c2, f.lo, f.hi, wl.seed, f.stream)
+        got = _swarm_to_oracle(b, sw, r)
+        assert np.array_equal(got.x, ref.x), f"region {r}: positions"
+        assert np.array_equal(got.v, ref.v), f"region {r}: velocities"
+        prob = oracle_problem(f)
+        for p in (r % f.n_part, f.n_part - 1):
+            L = oracle.loss_batch(prob, ref.x[p:p + 1], f.y, "ssre")
+            kap = [kappa("ssre", oracle.integrate(prob, ref.x[p])[3], f.y)]
+            assert_loss_close(f_all[r][p:p + 1], L, kap, TOL64, f"region {r} particle {p}")
