@@ -262,3 +262,41 @@ def test_full_size_fused_evaluate_sampled():
             L = oracle.loss_batch(prob, ref.x[p:p + 1], f.y, "ssre")
             kap = [kappa("ssre", oracle.integrate(prob, ref.x[p])[3], f.y)]
             assert_loss_close(f_all[r][p:p + 1], L, kap, TOL64, f"region {r} particle {p}")
+
+
+@pytest.mark.parametrize("launch", [dict(block=256, persistent=0),
+                                    dict(block=256, persistent=0, waves_per_simd=4),
+                                    dict(block=64, persistent=300)])
+def test_fused_move_every_block_layout(launch):
+    """The fused kernel moves Philox block 0 (gamma, mu, I0, beta_1) before
+    integrating and each later block of betas as the segment loop reaches
+    it: for 1 to 13 segments, segments past the window end (never
+    integrated, still moved) and ragged tiles, the fused sequence leaves
+    bitwise the state of n x [sird_loss; pso_step]."""
+    shapes = [(30, 3, 30, 1, 70), (30, 2, 10, 2, 64), (40, 1, 10, 4, 65), (50, 2, 10, 5, 1),
+              (20, 5, 5, 9, 100), (60, 2, 5, 12, 33), (45, 4, 3, 13, 128), (7, 10, 1, 8, 64)]
+    specs = [S.ProblemSpec(W, spd, seg, K, 1e6, n_part=n, stream=r)
+             for r, (W, spd, seg, K, n) in enumerate(shapes)]
+    los = [np.concatenate([np.full(s.K, 0.05), [0.05, 0.001, 100.0]]) for s in specs]
+    his = [np.concatenate([np.full(s.K, 0.5), [0.2, 0.01, 1000.0]]) for s in specs]
+    ys = [np.array([2.0 * i + 0.05 * i * i for i in range(s.W + 1)]) for s in specs]
+    states = []
+    for mode in ("unfused", "fused"):
+        print(f"case fused move layout {launch} {mode}", flush=True)
+        b = S.Batch(specs, **launch)
+        params = S.PsoParams(b, los, his, 0.7, 1.5, 1.5, 21)
+        sw = S.Swarm(b, hist_len=6)
+        obs = b.pack_obs(ys)
+        S.pso_init(b, params, sw)
+        if mode == "unfused":
+            for _ in range(6):
+                S.sird_loss(b, sw.x, obs, "ssre", sw.f)
+                S.pso_step(b, params, sw)
+        else:
+            S.sird_pso_iterate(b, params, sw, obs, "ssre", 6)
+        torch.cuda.synchronize()
+        states.append([t.cpu().numpy().copy() for t in
+                       (sw.x, sw.v, sw.pbest_x, sw.pbest_f, sw.gbest_x, sw.gbest_f,
+                        sw.gbest_idx, sw.iter, sw.hist_f, sw.hist_idx, sw.f)])
+    for a, c in zip(*states):
+        assert np.array_equal(a, c, equal_nan=True)
