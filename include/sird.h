@@ -286,9 +286,11 @@ int pso_step(const sird_batch *batch, const pso_params *params, const pso_state 
 /* The two halves of a swarm iteration with the swarm update fused into the
  * integration (Sec. 3.3).  pso_evaluate: if move_first, first complete the
  * previous iteration's velocity/position update (counter iter[0] - 1,
- * operations as in pso_step step 3); then integrate every particle and
- * write state->f = loss(state->x) as sird_loss does; then update the
- * personal bests as in pso_step step 1.  pso_gbest: pso_step step 2 for
+ * operations as in pso_step step 3; for the RK4 model the kernel moves
+ * Philox block 0 before integrating and the later blocks of betas as the
+ * integration reaches them, with the same result); then integrate every
+ * particle and write state->f = loss(state->x) as sird_loss does; then
+ * update the personal bests as in pso_step step 1.  pso_gbest: pso_step step 2 for
  * iteration it = iter[0] (global best, history row it), then iter[0] = it+1.
  * The sequence
  *     pso_evaluate(0); pso_gbest; { pso_evaluate(1); pso_gbest; } x (n-1);
