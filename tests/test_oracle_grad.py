@@ -3,8 +3,11 @@ projected Adam step.
 
 The gradient is checked against (a) a closed form: with beta = 0 the RK4
 solution is I_n = I0 R(-lam h)^n exactly, so dD/dgamma, dD/dmu and dD/dI0
-are explicit; and (b) Richardson-extrapolated central differences of the
-oracle's own loss, which share no code with the tangent recursion.
+are explicit; (b) Richardson-extrapolated central differences of the
+oracle's own loss, which share no code with the tangent recursion; and (c)
+the complex step (Squire & Trapp 1998): the discrete RK4 loss evaluated
+here in complex arithmetic with theta_j + i 1e-30, whose imaginary part
+over 1e-30 is the derivative to rounding, with no cancellation.
 """
 import numpy as np
 import pytest
@@ -108,3 +111,62 @@ def test_adam_descends_a_quadratic(orc):
     for t in range(1, 3001):
         orc.adam_step(th, 2 * (th - a), m, v, lo, hi, t, lr=1e-2)
     np.testing.assert_allclose(th[0], a, atol=1e-3)
+
+
+def rk4_loss_complex(theta, W, spd, seg_days, K, N_, R0, D0, y, kind):
+    """The discrete loss in complex arithmetic, one column per direction:
+    theta is (d, m) complex.  Classical RK4 on (S, I, R, D) with f =
+    (-b S I, b S I - (gamma + mu) I, gamma I, mu I), b = beta_k / N, the
+    segment of step n min(n // (seg_days spd), K - 1) for all four stages,
+    h = 1/spd; Dhat_i = D after i spd steps."""
+    beta, gamma, mu, I0 = theta[:K], theta[K], theta[K + 1], theta[K + 2]
+    h = 1.0 / spd
+    S = N_ - I0 - R0 - D0
+    I = I0 + 0j
+    Rr = np.zeros_like(I) + R0
+    D = np.zeros_like(I) + D0
+
+    def f(S, I, b):
+        p = b * S * I
+        return -p, p - (gamma + mu) * I, gamma * I, mu * I
+
+    Dhat = [D]
+    for n in range(W * spd):
+        b = beta[min(n // (seg_days * spd), K - 1)] / N_
+        k1 = f(S, I, b)
+        k2 = f(S + h / 2 * k1[0], I + h / 2 * k1[1], b)
+        k3 = f(S + h / 2 * k2[0], I + h / 2 * k2[1], b)
+        k4 = f(S + h * k3[0], I + h * k3[1], b)
+        S, I, Rr, D = [v + h / 6 * (a + 2 * bb + 2 * c + e) for v, a, bb, c, e in
+                       zip((S, I, Rr, D), k1, k2, k3, k4)]
+        if (n + 1) % spd == 0:
+            Dhat.append(D)
+    Dhat = np.array(Dhat)  # (W+1, m)
+    yy = np.asarray(y)[:, None]
+    if kind == "ssre":
+        r = (Dhat[1:] - yy[1:]) / np.maximum(yy[1:], 1.0)
+        return np.sum(r * r, axis=0)
+    e = yy - Dhat
+    return np.sum(e * e, axis=0) / (W + 1)
+
+
+@pytest.mark.parametrize("kind", ["ssre", "mse"])
+def test_forward_mode_matches_complex_step(orc, kind):
+    K, W, spd, seg = 5, 45, 4, 10
+    R0, D0 = 30.0, 4.0
+    prob = orc.Problem(W=W, spd=spd, seg_days=seg, K=K, N=N, R0=R0, D0=D0)
+    truth = orc.integrate(prob, [0.3, 0.25, 0.2, 0.15, 0.12, 0.1, 0.004, 2500.0])[3]
+    rng = np.random.default_rng(12)
+    y = truth * (1 + rng.normal(0, 0.05, W + 1))
+    y[0] = D0
+    th = np.array([0.28, 0.26, 0.18, 0.16, 0.13, 0.11, 0.0035, 2200.0])
+    d = th.size
+    hc = 1e-30
+    cols = np.tile(th[:, None], (1, d)).astype(np.complex128)
+    cols[np.arange(d), np.arange(d)] += 1j * hc
+    cs = np.imag(rk4_loss_complex(cols, W, spd, seg, K, N, R0, D0, y, kind)) / hc
+    L0 = np.real(rk4_loss_complex(th[:, None].astype(np.complex128), W, spd, seg, K, N, R0,
+                                  D0, y, kind))[0]
+    L, g = orc.loss_grad_fwd(prob, th, y, kind)
+    assert L == pytest.approx(L0, rel=1e-12)
+    np.testing.assert_allclose(g, cs, rtol=1e-9, atol=1e-12 * np.max(np.abs(cs)))
