@@ -18,6 +18,7 @@
 // tiles.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 
 #include "device.h"
@@ -347,11 +348,17 @@ static CostPlan cost_plan(int kind)
 // reservation does it.
 static size_t occupancy_lds(int waves_per_simd, int wpb)
 {
-    int dev = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
-                              dev) != hipSuccess || per_cu <= 0)
-        return 0;
+    // LDS per compute unit of each device, queried once
+    static std::atomic<int> lds_per_cu[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+    int per_cu = dev < 64 ? lds_per_cu[dev].load(std::memory_order_relaxed) : 0;
+    if (per_cu <= 0) {
+        if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                  dev) != hipSuccess || per_cu <= 0)
+            return 0;
+        if (dev < 64) lds_per_cu[dev].store(per_cu, std::memory_order_relaxed);
+    }
     const int nb = 4 * waves_per_simd / wpb;
     if (nb < 1) return 0;
     const size_t bytes = ((size_t)per_cu / (nb + 1) / 512 + 1) * 512;
