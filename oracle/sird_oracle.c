@@ -11,11 +11,11 @@
  *   - the SIRD right-hand side, eq. (SIRD) of Sec. 2.2, in the natural
  *     state (S, I, R, D);
  *   - a piecewise-constant transmission rate beta_k on segments of
- *     seg_days days (the build's replacement for the ramp of eq. (beta));
+ *     seg_days days (the library's replacement for the ramp of eq. (beta));
  *     the segment index is taken from the step index, so all four stages of
  *     a step use the same beta; the last segment extends to the end;
  *   - the ramp of eq. (beta) itself, for the Euler variant of Sec. 3.1/3.3;
- *   - classical RK4 with a fixed step h = 1/spd (the build's integrator),
+ *   - classical RK4 with a fixed step h = 1/spd (the library's integrator),
  *     and forward Euler (the scheme named in Sec. 3.1 and Sec. 3.3);
  *   - the low-level costs MXSE, MSE, MAE, MAPE of Sec. 3.1 on the deceased
  *     compartment, plus the sum of squared relative errors (SSRE);

@@ -159,3 +159,36 @@ def test_adjoint_few_steps_per_day_and_zero_beta(spd):
                 assert_grad_close(h[p], oracle.loss_grad_fwd(prob, th[p], f.y, "ssre")[1],
                                   f"spd {spd} particle {p}")
         assert np.array_equal(h, ref), s
+
+
+def test_mixed_sweeps_in_one_batch_equal_single_launches():
+    """Problems with 10 and 20 steps per day take the aligned 10-step sweep,
+    one with 3 the general sweep; in one batch each gradient is bitwise
+    its single-problem launch's, and within the oracle's tolerance."""
+    base = synth.c2().fits[0]
+    fits = []
+    for spd, W, K in ((10, 60, 5), (3, 45, 4), (20, 30, 3)):
+        f = synth.c2().fits[0]
+        f.spd, f.W, f.K, f.seg_days = spd, W, K, 14
+        f.y = base.y[:W + 1]
+        f.lo = np.concatenate([base.lo[:K], base.lo[-3:]])
+        f.hi = np.concatenate([base.hi[:K], base.hi[-3:]])
+        fits.append(f)
+    n_parts = [70, 33, 64]
+    ths = [random_theta(f, n, seed=20 + r) for r, (f, n) in enumerate(zip(fits, n_parts))]
+    for th, f in zip(ths, fits):
+        th[:, :f.K] *= 0.5
+    b = make_batch(fits, n_parts)
+    print("case mixed sweeps batch", flush=True)
+    g, _ = S.sird_loss_backward(b, b.pack_theta(ths), b.pack_obs([f.y for f in fits]), "ssre",
+                                ckpt_interval=30)
+    G = b.unpack_theta(g)
+    for r, f in enumerate(fits):
+        b1 = make_batch([f], [n_parts[r]])
+        g1, _ = S.sird_loss_backward(b1, b1.pack_theta([ths[r]]), b1.pack_obs([f.y]), "ssre",
+                                     ckpt_interval=30)
+        assert np.array_equal(G[r], b1.unpack_theta(g1)[0]), f"problem {r}"
+        prob = oracle_problem(f)
+        for p in (0, n_parts[r] - 1):
+            assert_grad_close(G[r][p], oracle.loss_grad_fwd(prob, ths[r][p], f.y, "ssre")[1],
+                              f"problem {r} particle {p}")
