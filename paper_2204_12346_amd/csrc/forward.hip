@@ -261,7 +261,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             for (; day < dend; ++day) {
                 if (WITH_S) rescale(y, sc);
                 const DayObs o = day_obs(day + 1);
-#pragma unroll 2
+#pragma unroll 4
                 for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
                 emit(day + 1, o);
             }
