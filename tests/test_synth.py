@@ -87,3 +87,21 @@ def test_window_construction_matches_the_paper():
         assert f.hi[5] == g["mu_hi"] and f.hi[2] == f.hi[3] == g["t_hi"]
         assert np.all(f.lo[:6] == 0.0)
     assert delta * (len(wl.fits) - 1) + tau == T  # the last window ends on day T
+
+
+def test_paper_timing_case_matches_the_paper_setup():
+    """The paper's swarm settings and timing case (Sec. 3.3), stored in
+    tests/golden/pso_setup_sec3_3.txt, are those of the paper workload."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "pso_setup_sec3_3.txt")
+    g = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            g[k] = float(v)
+    wl = synth.paper()
+    (f,) = wl.fits
+    assert f.n_part == g["particles"] and wl.iters == g["iterations"]
+    assert wl.w == g["inertia"] and wl.c1 == g["cognitive"] and wl.c2 == g["social"]
+    assert f.W == g["timing_days"] and wl.loss == "ird_mxse"
+    assert f.model == "euler_ramp" and f.spd == 1
