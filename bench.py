@@ -93,6 +93,20 @@ def build_workload(name, dtype):
     return wl, b, params, sw, obs
 
 
+def host_cpu():
+    """Model name of the host CPU and its logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
+
 def cpu_baseline(wl, budget_s):
     """Oracle throughput on the host cores (OpenMP over particles, as the
     oracle stands): whole-batch loss evaluations of the workload (every
@@ -129,6 +143,7 @@ def cpu_baseline(wl, budget_s):
             break
     dt1 = time.perf_counter() - t1
     return {"value": work / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"whole-batch loss evaluations of the same workload, stopped after "
                       f"{budget_s:.0f} s: {work:.3e} particle-steps in {dt:.1f} s",
             "single_thread_value": w1 / dt1,
