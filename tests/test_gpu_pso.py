@@ -131,12 +131,16 @@ def test_run_batched_uneven_workload_reduced():
     _run_compare(wl, wl.fits, [64 + 37 * r for r in range(12)], 15)
 
 
-def test_graph_replay_equals_eager():
+@pytest.mark.parametrize("launch", [dict(), dict(block=256, persistent=0, waves_per_simd=4)])
+def test_graph_replay_equals_eager(launch):
+    """HIP-graph replays (with host work between them) leave bitwise the
+    eager sequence's state, also in the batched workload's launch shape."""
     wl = synth.c3(regions=list(range(8)))
     n_parts = [128] * 8
     results = []
     for mode in ("eager", "graph"):
-        b = make_batch(wl.fits, n_parts)
+        print(f"case graph {launch} {mode}", flush=True)
+        b = make_batch(wl.fits, n_parts, **launch)
         params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
                              wl.c2, wl.seed)
         sw = S.Swarm(b, hist_len=12)
