@@ -161,3 +161,73 @@ def test_run_equals_stepwise_and_resume(orc):
             orc.pso_move(s, it, 0.7, 1.5, 1.5, lo, hi, seed=7, stream=3)
     assert np.array_equal(s.x, final.x) and np.array_equal(s.pbest_f, final.pbest_f)
     assert np.all(np.diff(hf) <= 0)
+
+
+def _bests_case(orc, pbest_f, f, gbest_f):
+    """Swarm of len(pbest_f) particles in 2-D with the given personal bests
+    and global best; returns (margin, swarm) after pso_bests(f)."""
+    P = len(pbest_f)
+    s = orc.pso_init(P, np.zeros(2), np.ones(2), seed=1)
+    s.pbest_f[:] = pbest_f
+    s.gbest_f[0] = gbest_f
+    s.gbest_idx[0] = -1 if np.isinf(gbest_f) else 0
+    m = orc.pso_bests(s, np.array(f, dtype=np.float64))
+    return m, s
+
+
+# The near-tie margin is the smallest relative gap |a - b| / max(|a|, |b|)
+# over the comparisons that decided an outcome of the update (Sec. 3.3's
+# personal and global bests).  Each case below makes one of the three kinds
+# of comparison the smallest, with dyadic gaps whose value is exact.
+def test_margin_personal_best_comparison_decides(orc):
+    # f vs pbest: 4 vs 3 -> 1/4, 30 vs 32 -> 1/16 (improves); winner 3 vs
+    # runner-ups 30, 100: 0.9, 0.97; the global best stays 3 (no decision)
+    m, s = _bests_case(orc, [3.0, 32.0, 100.0], [4.0, 30.0, np.nan], 3.0)
+    assert m == 0.0625
+    assert list(s.pbest_f) == [3.0, 30.0, 100.0]
+
+
+def test_margin_winner_vs_runner_up_decides(orc):
+    # no finite f: no personal-best comparison; argmin 15 vs 16 -> 1/16,
+    # vs 40 -> 0.625; no previous global best
+    m, s = _bests_case(orc, [16.0, 15.0, 40.0], [np.nan] * 3, np.inf)
+    assert m == 0.0625
+    assert s.gbest_idx[0] == 1 and s.gbest_f[0] == 15.0
+
+
+def test_margin_new_best_vs_previous_global_best_decides(orc):
+    # winner 7 vs runner-up 50: 0.86; 7 replaces the global best 8: 1/8
+    m, s = _bests_case(orc, [7.0, 50.0], [np.nan, np.nan], 8.0)
+    assert m == 0.125
+    assert s.gbest_idx[0] == 0 and s.gbest_f[0] == 7.0
+
+
+def test_margin_excludes_equal_values_and_unchanged_best(orc):
+    # f equal to pbest (both particles) and the exact tie 5 == 5 between
+    # particles 0 and 1 decide identically in any implementation; the
+    # global best equal to the winner is unchanged: only 5 vs 40 counts
+    m, s = _bests_case(orc, [5.0, 5.0, 40.0], [5.0, 5.0, np.nan], 5.0)
+    assert m == 0.875
+    assert s.gbest_idx[0] == 0
+
+
+def test_margin_excludes_non_finite_sides(orc):
+    # pbest +inf (never evaluated) vs f = 3 is no near decision; 8 vs 4 ->
+    # 0.5; afterwards 3 vs 4 -> 0.25
+    m, _ = _bests_case(orc, [np.inf, 4.0], [3.0, 8.0], np.inf)
+    assert m == 0.25
+    # nothing finite decided anything
+    m, _ = _bests_case(orc, [np.inf], [np.nan], np.inf)
+    assert m == np.inf
+
+
+def test_run_records_the_margin_of_each_update(orc):
+    prob = orc.Problem(W=20, spd=2, seg_days=20, K=1, N=1e6)
+    y = orc.integrate(prob, [0.3, 0.1, 0.01, 100.0])[3]
+    lo, hi = np.array([0.0, 0.0, 0.0, 100.0]), np.array([1.0, 0.5, 0.05, 100.0])
+    hf, hidx, hm, _ = orc.pso_run(prob, y, "ssre", 16, lo, hi, 0.7, 1.5, 1.5, 3, 0, 6)
+    s = orc.pso_init(16, lo, hi, seed=3)
+    for it in range(6):
+        m = orc.pso_bests(s, orc.loss_batch(prob, s.x, y, "ssre"))
+        assert m == hm[it] and s.gbest_idx[0] == hidx[it]
+        orc.pso_move(s, it, 0.7, 1.5, 1.5, lo, hi, seed=3)
