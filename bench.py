@@ -1,17 +1,27 @@
 """Throughput benchmark of the calibration hot path on one MI355X.
 
-One step = one swarm iteration over the whole batch, as sird_pso_iterate
-runs it: pso_evaluate (the previous iteration's Philox velocity/position
-update, RK4 over every particle's window fused with the cost, personal
-bests -- one kernel) then pso_gbest (per-problem argmin, iteration
-advance).  Default workload: 512 independent
-synthetic regions of uneven window (28..365 days) and population, 1024
-particles each, 14-day beta segments, dt = 0.1 day, FP64.
+One step = one swarm iteration over the whole batch: the previous
+iteration's Philox velocity/position update, RK4 over every particle's
+window fused with the cost and the personal best (one kernel,
+pso_evaluate), then the per-problem global best (pso_gbest).  Default
+workload: 512 independent synthetic regions of uneven window (28..365
+days) and population, 1024 particles each, 14-day beta segments, dt = 0.1
+day, FP64, the K timed iterations captured in one HIP graph.
 
-Prints one JSON line: particle-RK4-steps/s of the timed steps, the roofline
-of the dominant kernel (the forward integration, timed per launch with HIP
-events on the stream it runs on) and the oracle's throughput on the host
-cores on a bounded sample of the same workload.
+Prints one JSON line:
+  * value: particle-RK4-steps/s of the K graph-replayed steps (M1), with
+    the same K steps run eagerly beside it;
+  * roofline: the fused integration kernel (timed per launch with HIP
+    events on its stream in the eager pass) against the FP64 vector peak,
+    at the algorithmic 49 flops per particle-step;
+  * time_to_fit (M2): wall time to reach 1e-6 of the best loss on the
+    8192-particle segmented fit, plain swarm vs swarm + adjoint refinement;
+  * gradients: loss + gradient per second of 65536 parameter vectors over
+    7300 steps;
+  * other_workloads: the other configurations, one number each;
+  * cpu_baseline: the oracle on the host cores on a bounded sample of the
+    same workload, and per configuration (stated samples).
+The full results of the other workloads go to stderr as one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|paper] [--dtype f64|f32]
 """
@@ -34,11 +44,13 @@ sys.path.insert(0, ROOT)
 # bench.py --autotune) picks.
 C3_LAUNCH = dict(block=256, persistent=0, waves_per_simd=4)
 
-# Algorithmic work of one particle-step of the FP64 forward: the RK4 step
-# on (s = b S, I, D) issues 3 mul + 3 add + 16 fma = 22 VALU instructions =
-# 38 flops (an FMA counts 2).  The per-day cost and the swarm update fused
-# into the same kernel are not counted.
-FLOPS_PER_STEP = 38
+# Algorithmic work of one particle-step of classical RK4 on eq. (SIRD)
+# with the state (S, I, D): four right-hand sides (p = b S I, p - lam I,
+# mu I) and the stage and update combinations, 8 mul + 3 add + 19 fma =
+# 49 flops (an FMA counts 2).  The kernel issues fewer: on (s = b S, I, D)
+# its step is 3 mul + 3 add + 16 fma = 22 VALU instructions = 38 flops.
+FLOPS_PER_STEP = 49
+FLOPS_ISSUED_PER_STEP = 38
 VALU_PER_STEP = 22
 # The paper's scheme (forward Euler with the beta ramp): the ramp costs a
 # subtract and an fma (3 flops), the step 2 mul + 5 fma (12 flops).
@@ -55,7 +67,8 @@ MEASURED_TRAFFIC = {
            "summary": "profiles/k_forward_fused_batched_512x1024.md"},
 }
 
-METRIC = "particle·RK4-steps/sec"
+METRIC = ("particle·RK4-steps/sec and wall-time-to-fit at fixed loss, "
+          "plain PSO vs PSO+adjoint")
 UNIT = "particle·RK4-steps/s"
 
 
@@ -107,20 +120,27 @@ def host_cpu():
     return f"{model}, {os.cpu_count()} logical CPUs visible"
 
 
+def _threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def _progress(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(wl, budget_s):
     """Oracle throughput on the host cores (OpenMP over particles, as the
     oracle stands): whole-batch loss evaluations of the workload (every
     particle of every problem, parameters uniform in each box), repeated
     while the elapsed time is below budget_s (at least one)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = _threads()
     rng = np.random.default_rng(0)
     thetas = [f.lo + rng.uniform(0, 1, (f.n_part, f.d)) * (f.hi - f.lo) for f in wl.fits]
     probs = [oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0,
                             model=1 if f.model == "euler_ramp" else 0) for f in wl.fits]
     three = wl.loss.startswith("ird")
     work = 0
-    reps = 0
     t0 = time.perf_counter()
     while True:
         for f, th, prob in zip(wl.fits, thetas, probs):
@@ -129,7 +149,6 @@ def cpu_baseline(wl, budget_s):
             work += f.n_part * f.T
             if time.perf_counter() - t0 > budget_s:
                 break
-        reps += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
@@ -151,6 +170,83 @@ def cpu_baseline(wl, budget_s):
                                     f"{w1:.3e} particle-steps in {dt1:.1f} s"}
 
 
+def oracle_per_config():
+    """The oracle beside every other configuration, on the host cores
+    (OpenMP over particles; the gradient sample over a thread pool, since
+    the oracle's forward mode takes one vector per call):
+      constant beta: the whole swarm run (256 x 200 iterations);
+      segmented: 100 of the 1000 iterations, extrapolated linearly;
+      gradients: forward-mode gradients of 1024 of the 65536 vectors;
+      rolling windows: one window's 16 restarts x 20 of the 300 iterations,
+        extrapolated linearly to 300 iterations and 52 windows (swarm only);
+      the paper's timing case: the whole run (10000 x 100 Euler iterations)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    import synth
+    threads = _threads()
+    out = {"cores": threads, "host": host_cpu(), "kind": "oracle"}
+
+    def prob_of(f):
+        return oracle.Problem(f.W, f.spd, f.seg_days, f.K, f.N, f.R0, f.D0,
+                              model=1 if f.model == "euler_ramp" else 0)
+
+    def run(wl, f, iters):
+        t0 = time.perf_counter()
+        if f.model == "euler_ramp":
+            oracle.pso_run_model(prob_of(f), f.obs3, wl.loss, f.n_part, f.lo, f.hi, wl.w,
+                                 wl.c1, wl.c2, wl.seed, f.stream, iters, nthreads=threads)
+        else:
+            oracle.pso_run(prob_of(f), f.y, wl.loss, f.n_part, f.lo, f.hi, wl.w, wl.c1, wl.c2,
+                           wl.seed, f.stream, iters, nthreads=threads)
+        return time.perf_counter() - t0
+
+    wl = synth.c1()
+    f = wl.fits[0]
+    t = run(wl, f, wl.iters)
+    out["c1_constant_beta_256x200"] = {
+        "seconds": t, "particle_steps_per_s": f.n_part * f.T * wl.iters / t,
+        "sample": "whole run"}
+    _progress("oracle c1 done")
+    wl = synth.c2()
+    f = wl.fits[0]
+    t = run(wl, f, 100)
+    out["c2_segmented_8192x1000"] = {
+        "seconds_extrapolated": t * wl.iters / 100,
+        "particle_steps_per_s": f.n_part * f.T * 100 / t,
+        "sample": "100 of 1000 iterations, extrapolated linearly"}
+    _progress("oracle c2 done")
+    wl, thetas = synth.c4()
+    f = wl.fits[0]
+    prob = prob_of(f)
+    sample = thetas[np.linspace(0, len(thetas) - 1, 1024).astype(int)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda th: oracle.loss_grad_fwd(prob, th, f.y, "ssre"), sample))
+    t = time.perf_counter() - t0
+    out["c4_gradients_65536x7300"] = {
+        "gradients_per_s": len(sample) / t, "seconds_extrapolated": t * len(thetas) / len(sample),
+        "sample": "forward-mode gradients of 1024 vectors spread over the 65536"}
+    _progress("oracle c4 done")
+    wl = synth.c5(windows=[0])
+    t = sum(run(wl, f, 20) for f in wl.fits)
+    steps = sum(f.n_part * f.T for f in wl.fits) * 20
+    out["c5_rolling_52x16x4096x300"] = {
+        "seconds_extrapolated": t * (wl.iters / 20) * 52,
+        "particle_steps_per_s": steps / t,
+        "sample": "one window's 16 restarts x 20 of 300 iterations, extrapolated to 300 "
+                  "iterations and 52 windows; swarm only"}
+    _progress("oracle c5 done")
+    wl = synth.paper()
+    f = wl.fits[0]
+    t = run(wl, f, wl.iters)
+    out["paper_euler_ramp_10000x100"] = {
+        "seconds": t, "seconds_per_iteration": t / wl.iters,
+        "particle_steps_per_s": f.n_part * f.T * wl.iters / t, "sample": "whole run"}
+    _progress("oracle paper case done")
+    return out
+
+
 def copy_probe(mib):
     """A plain device copy of known size (for scaling HBM byte counters)."""
     import torch
@@ -166,38 +262,34 @@ def copy_probe(mib):
 
 def extra_tasks():
     """The other configurations, each measured once (see experiments.py):
-    (group, name, thunk) in run order."""
+    (name, thunk) in run order."""
     import synth
     from paper_2204_12346_amd import experiments as X
-    t = [("single-fit swarms", "c1_constant_beta_256x60d",
+    t = [("c1_constant_beta_256x60d",
           lambda: X.swarm_throughput(synth.c1(), "f64", iters=200, graph_chunk=20,
                                      launch=dict(block=64)))]
     for dt in ("f64", "f32"):
-        t.append(("single-fit swarms", f"c2_segmented_8192x180d_{dt}",
+        t.append((f"c2_segmented_8192x180d_{dt}",
                   lambda dt=dt: X.swarm_throughput(synth.c2(), dt, iters=200, graph_chunk=20,
                                                    launch=dict(block=64))))
-    # the batched workload with its iterations captured in HIP graphs
-    t.append(("single-fit swarms", "c3_batched_512x1024_graph",
-              lambda: X.swarm_throughput(synth.c3(), "f64", iters=50, warmup=5, graph_chunk=10,
-                                         launch=dict(C3_LAUNCH))))
-    t.append(("gradients", "c4_gradients_65536x7300steps",
-              lambda: X.gradients_per_s(*synth.c4())))
-    t.append(("gradients", "c4_gradients_65536x7300steps_interval10",
+    t.append(("c4_gradients_65536x7300steps", lambda: X.gradients_per_s(*synth.c4())))
+    t.append(("c4_gradients_65536x7300steps_interval10",
               lambda: X.gradients_per_s(*synth.c4(), ckpt_interval=10)))
-    # L-BFGS arms, and two arms with the Adam refinement the protocol names
-    t.append(("time to fit", "time_to_fit_c2",
-              lambda: X.time_to_fit(synth.c2(), adam_arms=((100, 64), (100, 1024)))))
+    # M2: plain swarm against swarm + refinement of the top k by the adjoint
+    # (projected L-BFGS, and the projected Adam the protocol names, with a
+    # decaying step)
+    t.append(("time_to_fit_c2",
+              lambda: X.time_to_fit(synth.c2(), pso_first=(100,), ks=(32, 1024),
+                                    adam_arms=((100, 32),), adam_lr_end=1e-5)))
     for dt in ("f64", "f32"):
-        t.append(("the paper's own timing case", f"paper_euler_ramp_ird_mxse_10000x92d_{dt}",
+        t.append((f"paper_euler_ramp_ird_mxse_10000x92d_{dt}",
                   lambda dt=dt: X.paper_iteration(synth.paper(), dt)))
-    t.append(("repetition study", "rep_1000x10000x36d", lambda: X.repetition(synth.rep())))
-    t.append(("window-wise calibration", "windows_139x10000x36d",
-              lambda: X.window_wise(synth.windows())))
-    t.append(("rolling windows", "c5_rolling_52x16x4096",
+    t.append(("rep_1000x10000x36d", lambda: X.repetition(synth.rep())))
+    t.append(("c5_rolling_52x16x4096",
               lambda: X.rolling_forecast(synth.c5(), synth.c5_series()["truth"], restarts=16,
                                          launch=dict(C3_LAUNCH))))
     # the configuration names Adam for the refinement
-    t.append(("rolling windows", "c5_rolling_52x16x4096_adam",
+    t.append(("c5_rolling_52x16x4096_adam",
               lambda: X.rolling_forecast(synth.c5(), synth.c5_series()["truth"], restarts=16,
                                          launch=dict(C3_LAUNCH), method="adam")))
     return t
@@ -205,18 +297,73 @@ def extra_tasks():
 
 def extras(only=None):
     res = {}
-    group = None
-    for g, name, fn in extra_tasks():
+    for name, fn in extra_tasks():
         if only is not None and name != only:
             continue
-        if g != group:
-            print(f"# extras: {g} ...", file=sys.stderr, flush=True)
-            group = g
+        _progress(f"extras: {name} ...")
         res[name] = fn()
     if only is not None and not res:
         raise SystemExit(f"unknown extra {only!r}: one of "
-                         + ", ".join(n for _, n, _ in extra_tasks()))
+                         + ", ".join(n for n, _ in extra_tasks()))
     return res
+
+
+def summarize(ex):
+    """The compact blocks of the JSON line from the full extras."""
+    out = {}
+    ttf = ex.get("time_to_fit_c2")
+    if ttf:
+        arms = {k: v for k, v in ttf.items() if isinstance(v, dict) and "median_s" in v}
+        rel = "1e-06"
+        med = {k: v["median_s"].get(rel) for k, v in arms.items()}
+        ref_arms = {k: m for k, m in med.items() if k != "plain" and m is not None}
+        best = min(ref_arms, key=ref_arms.get) if ref_arms else None
+        out["time_to_fit"] = {
+            "workload": "one fit: 8192 particles, 180 days, 13 beta segments, dt 0.1, FP64; "
+                        f"{len(ttf['seeds'])} Philox seeds, median wall seconds from pso_init",
+            "L_best": ttf["L_best"], "target": "loss <= L_best (1 + 1e-6)",
+            "plain_median_s": med.get("plain"),
+            "plain_cap_iterations": ttf["plain_cap_iterations"],
+            "best_adjoint_arm": best, "best_adjoint_median_s": ref_arms.get(best),
+            "median_s_by_arm": med,
+            "median_s_1e-3_by_arm": {k: v["median_s"].get("0.001") for k, v in arms.items()},
+        }
+    g = ex.get("c4_gradients_65536x7300steps")
+    if g:
+        g10 = ex.get("c4_gradients_65536x7300steps_interval10", {})
+        out["gradients"] = {
+            "workload": "65536 parameter vectors x 7300 RK4 steps (365 days, dt 0.05), "
+                        "13 segments, SSRE, FP64",
+            "gradients_per_s": g["gradients_per_s"],
+            "ms_loss_and_gradient": g["ms_loss_and_gradient"],
+            "ms_forward_saving_checkpoints": g["ms_forward_saving_checkpoints"],
+            "ms_reverse_sweep": g["ms_reverse_sweep"],
+            "gradients_per_s_self_contained": g["gradients_per_s_self_contained"],
+            "ckpt_interval": g["ckpt_interval"],
+            "gradients_per_s_interval10": g10.get("gradients_per_s"),
+        }
+    o = {}
+    for k in ("c1_constant_beta_256x60d", "c2_segmented_8192x180d_f64",
+              "c2_segmented_8192x180d_f32"):
+        if k in ex:
+            o[k] = {"ms_per_iteration": ex[k]["ms_per_iteration"],
+                    "particle_steps_per_s": ex[k]["particle_steps_per_s"]}
+    for k in ("paper_euler_ramp_ird_mxse_10000x92d_f64", "paper_euler_ramp_ird_mxse_10000x92d_f32"):
+        if k in ex:
+            o[k] = {"ms_per_iteration_mean": ex[k]["ms_per_iteration_mean"],
+                    "ms_per_iteration_std": ex[k]["ms_per_iteration_std"]}
+    if "rep_1000x10000x36d" in ex:
+        r = ex["rep_1000x10000x36d"]
+        o["rep_1000x10000x36d"] = {"seconds_swarm": r["seconds_swarm"],
+                                   "particle_steps_per_s": r["particle_steps_per_s"]}
+    for k in ("c5_rolling_52x16x4096", "c5_rolling_52x16x4096_adam"):
+        if k in ex:
+            r = ex[k]
+            o[k] = {"seconds_swarm": r["seconds_swarm"], "seconds_refine": r["seconds_refine"],
+                    "rel_err_cum_deaths_h14_median": r["rel_err_cum_deaths_h14"][50]}
+    if o:
+        out["other_workloads"] = o
+    return out
 
 
 def main():
@@ -232,7 +379,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="search the launch shape before timing instead of the recorded one")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the other workloads (single fits, gradients, rolling windows)")
+                    help="skip the other workloads (single fits, gradients, time to fit, ...)")
     ap.add_argument("--extra", default=None,
                     help="run only this one of the other workloads and print its JSON")
     args = ap.parse_args()
@@ -260,22 +407,33 @@ def main():
     kind = wl.loss
 
     S.pso_init(b, params, sw)
-    tuned = None
     if args.autotune:
         from paper_2204_12346_amd import autotune
         tuned = autotune.autotune_iterate(b, params, sw, obs, kind, use_cache=False,
                                           verbose=True)
-        print(f"# autotuned launch: {tuned}", file=sys.stderr, flush=True)
+        _progress(f"autotuned launch: {tuned}")
     S.sird_pso_iterate(b, params, sw, obs, kind, args.warmup)
+    # the K timed iterations captured in one HIP graph (uploaded when created)
+    graph = S.Graph(b, params, sw, obs, kind, iters_per_launch=args.steps)
     torch.cuda.synchronize()
-    print(f"# warmup done: {args.warmup} steps", file=sys.stderr, flush=True)
+    _progress(f"warmup done: {args.warmup} steps; graph of {args.steps} iterations ready")
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    start.record(stream)
+    graph.launch(1, stream=stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    graph.close()
+
+    # the same K iterations eagerly, each evaluate launch between HIP events
+    # on its stream: the kernel time of the roofline
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
     start.record(stream)
     for i in range(args.steps):
         ev[i][0].record(stream)
@@ -285,9 +443,10 @@ def main():
     S.pso_complete_move(b, params, sw)
     end.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(end)
+    eager_ms = start.elapsed_time(end)
     fwd_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
+    _progress(f"timed: graph {total_ms / args.steps:.4f} ms/step, eager "
+              f"{eager_ms / args.steps:.4f} ms/step, evaluate kernel {fwd_ms:.4f} ms")
 
     steps_per_iter = b.particle_steps
     value = steps_per_iter * args.steps / (total_ms / 1e3)
@@ -299,8 +458,37 @@ def main():
     traffic = None
     if meas and meas["sources"] == kernel_source_hash() and args.dtype == "f64":
         traffic = meas["bytes"]
-    flops_step = FLOPS_PER_STEP_EULER_RAMP if args.workload == "paper" else FLOPS_PER_STEP
+    paper = args.workload == "paper"
+    flops_step = FLOPS_PER_STEP_EULER_RAMP if paper else FLOPS_PER_STEP
     achieved = flops_step * steps_per_iter / (fwd_ms / 1e3)
+    roof = {
+        "kernel": ("k_forward fused (pso_evaluate: move + Euler with the beta ramp + "
+                   "F_IRD^MXSE + pbest)" if paper else
+                   "k_forward fused (pso_evaluate: move + RK4 + cost + pbest)"),
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP64_VECTOR / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_VECTOR,
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch",
+        "algorithmic_bytes": alg_bytes,
+        "kernel_ms": fwd_ms,
+        "flops_per_particle_step": flops_step,
+    }
+    if not paper:
+        issued = FLOPS_ISSUED_PER_STEP * steps_per_iter / (fwd_ms / 1e3)
+        roof["issued_flops_per_particle_step"] = FLOPS_ISSUED_PER_STEP
+        roof["frac_issued"] = issued / PEAK_FP64_VECTOR
+        roof["valu_issue_frac"] = ((VALU_PER_STEP * steps_per_iter / (fwd_ms / 1e3)) /
+                                   (256 * 4 * 16 * 2.4e9))
+    workloads = {
+        "c3": "batched uneven fits: 512 regions x 1024 particles, W 28..365 days, 14-day "
+              "beta segments, dt 0.1 day, iterations replayed from one HIP graph",
+        "c2": "one fit: 8192 particles, 180 days, 13 beta segments, dt 0.1",
+        "c1": "one fit: 256 particles, 60 days, constant beta, dt 0.1",
+        "paper": "the paper's timing case: one fit, 10000 particles, 92 days, forward Euler "
+                 "at one step per day with the beta ramp, F_IRD^MXSE"}
     out = {
         "metric": METRIC,
         "value": value,
@@ -315,47 +503,29 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {
-            "workload": {"c3": "batched uneven fits: 512 regions x 1024 particles, "
-                               "W 28..365 days, 14-day beta segments, dt 0.1 day",
-                         "c2": "one fit: 8192 particles, 180 days, 13 beta segments, dt 0.1",
-                         "c1": "one fit: 256 particles, 60 days, constant beta, dt 0.1",
-                         "paper": "the paper's timing case: one fit, 10000 particles, 92 days, "
-                                  "forward Euler at one step per day with the beta ramp, "
-                                  "F_IRD^MXSE"
-                         }[args.workload],
+            "workload": workloads[args.workload],
             "problems": b.n_prob,
             "particles": b.total_particles,
             "particle_steps_per_step": steps_per_iter,
             "loss": kind,
             "launch": {"block": b.c.block, "persistent": b.c.persistent,
-                       "waves_per_simd": b.c.waves_per_simd},
+                       "waves_per_simd": b.c.waves_per_simd, "timing": "hipGraph replay"},
         },
-        "roofline": {
-            "kernel": ("k_forward fused (pso_evaluate: move + Euler with the beta ramp + "
-                       "F_IRD^MXSE + pbest)" if args.workload == "paper" else
-                       "k_forward fused (pso_evaluate: move + RK4 + cost + pbest)"),
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP64_VECTOR / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VECTOR,
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch",
-            "algorithmic_bytes": alg_bytes,
-            "kernel_ms": fwd_ms,
-            "flops_per_particle_step": flops_step,
-            "valu_issue_frac": None if args.workload == "paper" else
-                               (VALU_PER_STEP * steps_per_iter / (fwd_ms / 1e3)) /
-                               (256 * 4 * 16 * 2.4e9),
-        },
+        "eager": {"ms_per_step": eager_ms / args.steps,
+                  "value": steps_per_iter * args.steps / (eager_ms / 1e3)},
+        "roofline": roof,
         "wall_s": wall,
     }
     if not args.no_extras and args.workload == "c3":
-        out["extras"] = extras()
+        ex = extras()
+        print("# extras " + json.dumps(ex), file=sys.stderr, flush=True)
+        out.update(summarize(ex))
     if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        _progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    print(json.dumps(out))
+        if not args.no_extras and args.workload == "c3":
+            out["cpu_baseline"]["per_config"] = oracle_per_config()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

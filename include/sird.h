@@ -254,9 +254,24 @@ int sird_integrate(const sird_batch *batch, const double *theta, double *traj,
  *          deaths (obs_series = 1), or I, R and cumulative D (3).
  *   loss_kind: one of SIRD_LOSS_* (the IRD kinds need obs_series = 3).
  *   loss:  output, particle-indexed.
- * Errors: SIRD_EINVAL (null pointer, bad kind or batch), SIRD_EHIP. */
+ *   ckpt_interval, workspace, ws_bytes: optional.  With workspace NULL
+ *          only the losses are computed (ckpt_interval and ws_bytes are
+ *          ignored).  With a workspace (at least
+ *          sird_loss_backward_workspace(batch, ckpt_interval) bytes,
+ *          256-byte aligned) the losses come from the forward pass of the
+ *          discrete adjoint, which also saves in the workspace the state
+ *          every ckpt_interval steps, the daily deceased counts and the
+ *          loss; sird_loss_backward with from_forward = 1 then starts at
+ *          the reverse sweep.  This form needs what sird_loss_backward
+ *          needs (SIRD_F64, the RK4 model, a deceased-count cost); its
+ *          losses equal that call's loss_out bitwise and the workspace-free
+ *          losses to rounding (it carries S beside s = (beta/N) S).
+ * Errors: SIRD_EINVAL (null pointer, bad kind or batch, a workspace form the
+ * adjoint does not support), SIRD_ENOSPACE (workspace too small),
+ * SIRD_EHIP. */
 int sird_loss(const sird_batch *batch, const double *theta, const double *obs,
-              int loss_kind, double *loss, void *stream);
+              int loss_kind, double *loss, int ckpt_interval, void *workspace,
+              size_t ws_bytes, void *stream);
 
 /* Initialise the swarm (Sec. 3.3): x = lo + u (hi - lo) with u from
  * Philox4x64-10 (Salmon et al. 2011) under key (seed, problem.stream) and
@@ -327,9 +342,16 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
  *       rounded up to a multiple of 10.  Problems whose steps per day and
  *       interval are both multiples of 10 are reversed 10 steps at a time
  *       with no per-step tests (faster; the same result).
+ *   from_forward: 0 = run the forward pass here (contents of the workspace
+ *       on entry are ignored); 1 = the workspace holds the forward pass of
+ *       a sird_loss call with a workspace on the same batch, theta, obs,
+ *       loss_kind and ckpt_interval, and only the reverse sweep runs (the
+ *       gradient is bitwise that of from_forward = 0; the saved forward
+ *       stays valid, so the call may be repeated, e.g. with another
+ *       grad_loss).
  *   workspace: device scratch of at least
  *       sird_loss_backward_workspace(batch, ckpt_interval) bytes, 256-byte
- *       aligned; contents on entry are ignored.
+ *       aligned.
  * The deceased-count costs are piecewise smooth: MXSE takes the first day
  * attaining the maximum, MAE/MAPE take sign(0) = 0.
  * Errors: SIRD_EINVAL, SIRD_ENOSPACE (workspace too small), SIRD_EHIP.
@@ -337,8 +359,8 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
  * (SIRD_EINVAL otherwise). */
 int sird_loss_backward(const sird_batch *batch, const double *theta, const double *obs,
                        int loss_kind, const double *grad_loss, double *grad_theta,
-                       double *loss_out, int ckpt_interval, void *workspace,
-                       size_t ws_bytes, void *stream);
+                       double *loss_out, int ckpt_interval, int from_forward,
+                       void *workspace, size_t ws_bytes, void *stream);
 
 /* Workspace bytes needed by sird_loss_backward (0 on a bad batch). */
 size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval);

@@ -79,7 +79,7 @@ def lib():
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                          _D, _I64, _D, _D, _D, _D, _D, _D, ctypes.c_int]
-        L.orc_loss_grad_fwd.argtypes = prob + [_D, _D, ctypes.c_int, _D, _D]
+        L.orc_loss_grad_fwd.argtypes = prob + [_D, _D, ctypes.c_int, _D, _D, _D]
         _IP = ctypes.POINTER(ctypes.c_int)
         L.orc_lbfgs_propose.argtypes = [ctypes.c_int] * 4 + [_D, _D, _D, _D, _D, _D, _D, _IP,
                                                              _IP, _D, _D, _D, _D]
@@ -268,13 +268,17 @@ def pso_run(prob: Problem, y, kind, P, lo, hi, w, c1, c2, seed, stream, iters, n
 
 
 # ------------------------------------------------------------- gradient
-def loss_grad_fwd(prob: Problem, theta, y, kind="ssre"):
-    """(loss, dloss/dtheta) of one parameter vector by forward-mode tangents."""
+def loss_grad_fwd(prob: Problem, theta, y, kind="ssre", with_scale=False):
+    """(loss, dloss/dtheta) of one parameter vector by forward-mode tangents;
+    with_scale also returns per component the sum over days of the absolute
+    terms the gradient adds up (the size its rounding is relative to)."""
     th, yy = _f64(theta), _f64(y)
     L = np.zeros(1)
     g = np.zeros(prob.d)
-    lib().orc_loss_grad_fwd(*prob.args(), _dp(th), _dp(yy), _kind(kind), _dp(L), _dp(g))
-    return float(L[0]), g
+    sc = np.zeros(prob.d) if with_scale else None
+    lib().orc_loss_grad_fwd(*prob.args(), _dp(th), _dp(yy), _kind(kind), _dp(L), _dp(g),
+                            _dp(sc))
+    return (float(L[0]), g, sc) if with_scale else (float(L[0]), g)
 
 
 def adam_step(theta, grad, m, v, lo, hi, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

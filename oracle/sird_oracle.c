@@ -478,9 +478,13 @@ static double cost_dDhat(int kind, int W, int i, double Dhat, double y, int argm
     }
 }
 
+/* scale (may be NULL): per component, the sum over days of the absolute
+ * values of the terms dl/dDhat_i * dDhat_i/dtheta_j that the gradient adds
+ * up -- the size the component's rounding error is relative to when the
+ * terms cancel. */
 void orc_loss_grad_fwd(int W, int spd, int seg_days, int K, double N, double R0,
                        double D0, const double *theta, const double *y, int kind,
-                       double *loss, double *grad)
+                       double *loss, double *grad, double *scale)
 {
     int d = K + 3;
     long T = (long)W * spd;
@@ -504,6 +508,7 @@ void orc_loss_grad_fwd(int W, int spd, int seg_days, int K, double N, double R0,
         yd[0] = yd[1] = yd[2] = yd[3] = 0.0;
         if (j == K + 2) { yd[0] = -1.0; yd[1] = 1.0; } /* dS0/dI0 = -1, dI0/dI0 = 1 */
         double g = cost_dDhat(kind, W, 0, Dhat[0], y[0], argmax) * yd[3];
+        double gs = fabs(g);
         for (long n = 0; n < T; ++n) {
             int k = seg_of_step(n, seg_days, spd, K);
             double beta = theta[k];
@@ -531,10 +536,13 @@ void orc_loss_grad_fwd(int W, int spd, int seg_days, int K, double N, double R0,
             }
             if ((n + 1) % spd == 0) {
                 int i = (int)((n + 1) / spd);
-                g = g + cost_dDhat(kind, W, i, Dhat[i], y[i], argmax) * yd[3];
+                double term = cost_dDhat(kind, W, i, Dhat[i], y[i], argmax) * yd[3];
+                g = g + term;
+                gs = gs + fabs(term);
             }
         }
         grad[j] = g;
+        if (scale) scale[j] = gs;
     }
     free(days);
 }

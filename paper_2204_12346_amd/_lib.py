@@ -99,14 +99,14 @@ SIGNATURES = {
     "sird_plan_tiles": (_I, [_P, _I, _P, _I]),
     "sird_batch_plan": (_I, [_B, _P, _I, _I64, _I64, _I64, _I64, _I64, _I, _I, _P, _P, _P]),
     "sird_integrate": (_I, [_B, _P, _P, _P]),
-    "sird_loss": (_I, [_B, _P, _P, _I, _P, _P]),
+    "sird_loss": (_I, [_B, _P, _P, _I, _P, _I, _P, ctypes.c_size_t, _P]),
     "pso_init": (_I, [_B, _PP, _PS, _P]),
     "pso_step": (_I, [_B, _PP, _PS, _P]),
     "sird_pso_iterate": (_I, [_B, _PP, _PS, _P, _I, _I, _P]),
     "pso_evaluate": (_I, [_B, _PP, _PS, _P, _I, _I, _P]),
     "pso_gbest": (_I, [_B, _PP, _PS, _P]),
     "pso_complete_move": (_I, [_B, _PP, _PS, _P]),
-    "sird_loss_backward": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _P, ctypes.c_size_t, _P]),
+    "sird_loss_backward": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),
     "sird_loss_backward_workspace": (ctypes.c_size_t, [_B, _I]),
     "pso_topk": (_I, [_B, _P, _I, _P, _P]),
     "sird_gather": (_I, [_B, _P, _P, _B, _P, _P, _I, _P]),

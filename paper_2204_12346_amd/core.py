@@ -27,6 +27,53 @@ def _kind(kind):
     return LOSS[kind] if isinstance(kind, str) else int(kind)
 
 
+class Args:
+    """Device array arguments of one call, checked before their addresses
+    reach the C ABI.  Calling the object checks one argument -- a torch
+    tensor (not a host array) of the given dtype, contiguous, holding at
+    least n elements; None passes only where the argument is optional --
+    and returns its address; device() then checks that every argument and
+    its batch are on one GPU.  Raises TypeError or ValueError, so a bad
+    argument never reaches a kernel."""
+
+    def __init__(self, batch: "Batch"):
+        self.batch = batch
+        self.seen = []
+
+    def __call__(self, t, n, name, dtype=torch.float64, optional=False, batch=None):
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name}: a device tensor is required")
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch tensor on the batch's GPU, "
+                            f"got {type(t).__name__}")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: tensor is not contiguous")
+        if t.numel() < n:
+            raise ValueError(f"{name}: {t.numel()} elements, the call needs {n}")
+        self.seen.append((t, name, batch or self.batch))
+        return t.data_ptr()
+
+    def workspace(self, ws, nbytes, name="workspace"):
+        """(address, size in bytes) of a workspace tensor of any dtype
+        holding at least nbytes."""
+        ptr_ = self(ws, 0, name, dtype=None)
+        size = ws.numel() * ws.element_size()
+        if size < nbytes:
+            raise ValueError(f"{name}: {size} bytes, the call needs {nbytes}")
+        return ptr_, size
+
+    def device(self):
+        for t, name, b in self.seen:
+            if b.device.type != "cuda":
+                raise ValueError(f"{name}: the batch lives on {b.device}, not on a GPU")
+            if t.device != b.device:
+                raise ValueError(f"{name}: tensor on {t.device}, the batch on {b.device}")
+
+
 class ProblemSpec:
     """One calibration window.  model "rk4": theta = (beta_1..beta_K, gamma,
     mu, I0) with beta piecewise constant on K segments of seg_days;
@@ -93,7 +140,10 @@ class Batch:
         check(nt if nt < 0 else 0, "sird_plan_tiles")
         self.n_tiles = nt
         self.tiles_host = tiles[:nt]
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.probs_dev = torch.from_numpy(tab.view(np.uint8).copy()).to(self.device)
         self.tiles_dev = torch.from_numpy(tiles.view(np.uint8).copy()).to(self.device)
         self.sched_dev = torch.zeros(2, dtype=torch.int32, device=self.device)
@@ -235,7 +285,10 @@ class PsoParams:
         self.hi = hi if isinstance(hi, torch.Tensor) else batch.pack_box(hi)
         p = _lib.pso_params()
         p.w, p.c1, p.c2, p.seed = float(w), float(c1), float(c2), int(seed)
-        p.lo, p.hi = ptr(self.lo), ptr(self.hi)
+        a = Args(batch)
+        p.lo = a(self.lo, batch.box_len, "lo")
+        p.hi = a(self.hi, batch.box_len, "hi")
+        a.device()
         self.c = p
 
 
@@ -243,15 +296,31 @@ class PsoParams:
 def sird_integrate(batch: Batch, theta, traj=None, stream=None):
     if traj is None:
         traj = torch.empty(max(batch.traj_len, 1), dtype=torch.float64, device=batch.device)
-    check(lib().sird_integrate(ctypes.byref(batch.c), ptr(theta), ptr(traj),
-                               stream_handle(stream)), "sird_integrate")
+    a = Args(batch)
+    args = (a(theta, batch.theta_len, "theta"), a(traj, batch.traj_len, "traj"))
+    a.device()
+    check(lib().sird_integrate(ctypes.byref(batch.c), *args, stream_handle(stream)),
+          "sird_integrate")
     return traj
 
 
-def sird_loss(batch: Batch, theta, obs, kind="ssre", loss=None, stream=None):
+def sird_loss(batch: Batch, theta, obs, kind="ssre", loss=None, stream=None,
+              workspace=None, ckpt_interval=0):
+    """Losses of every particle.  With a workspace (a device tensor of at
+    least sird_loss_backward_workspace(batch, ckpt_interval) bytes) the
+    adjoint's forward pass computes them and saves its checkpoints there for
+    sird_loss_backward(..., from_forward=True)."""
     if loss is None:
         loss = batch.empty_particles()
-    check(lib().sird_loss(ctypes.byref(batch.c), ptr(theta), ptr(obs), _kind(kind), ptr(loss),
+    a = Args(batch)
+    args = (a(theta, batch.theta_len, "theta"), a(obs, batch.obs_len, "obs"), _kind(kind),
+            a(loss, batch.total_particles, "loss"))
+    if workspace is None:
+        ws, nbytes = None, 0
+    else:
+        ws, nbytes = a.workspace(workspace, sird_loss_backward_workspace(batch, ckpt_interval))
+    a.device()
+    check(lib().sird_loss(ctypes.byref(batch.c), *args, int(ckpt_interval), ws, nbytes,
                           stream_handle(stream)), "sird_loss")
     return loss
 
@@ -268,15 +337,21 @@ def pso_step(batch: Batch, params: PsoParams, swarm: Swarm, stream=None):
 
 def sird_pso_iterate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre",
                      n_iters=1, stream=None):
+    a = Args(batch)
+    o = a(obs, batch.obs_len, "obs")
+    a.device()
     check(lib().sird_pso_iterate(ctypes.byref(batch.c), ctypes.byref(params.c),
-                                 ctypes.byref(swarm.c), ptr(obs), _kind(kind), int(n_iters),
+                                 ctypes.byref(swarm.c), o, _kind(kind), int(n_iters),
                                  stream_handle(stream)), "sird_pso_iterate")
 
 
 def pso_evaluate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre",
                  move_first=False, stream=None):
+    a = Args(batch)
+    o = a(obs, batch.obs_len, "obs")
+    a.device()
     check(lib().pso_evaluate(ctypes.byref(batch.c), ctypes.byref(params.c),
-                             ctypes.byref(swarm.c), ptr(obs), _kind(kind), int(bool(move_first)),
+                             ctypes.byref(swarm.c), o, _kind(kind), int(bool(move_first)),
                              stream_handle(stream)), "pso_evaluate")
 
 
@@ -297,25 +372,38 @@ def sird_loss_backward_workspace(batch: Batch, ckpt_interval=0):
 
 def sird_loss_backward(batch: Batch, theta, obs, kind="ssre", grad_loss=None,
                        grad_theta=None, loss_out=None, ckpt_interval=0, workspace=None,
-                       stream=None):
-    """Returns (grad_theta, loss_out)."""
+                       stream=None, from_forward=False):
+    """Returns (grad_theta, loss_out).  from_forward: the workspace holds
+    the forward pass of sird_loss(..., workspace=workspace) on the same
+    theta, obs, kind and interval; only the reverse sweep runs."""
     if grad_theta is None:
         grad_theta = batch.empty_theta()
+    nbytes = sird_loss_backward_workspace(batch, ckpt_interval)
     if workspace is None:
-        nbytes = sird_loss_backward_workspace(batch, ckpt_interval)
+        if from_forward:
+            raise ValueError("from_forward needs the workspace sird_loss filled")
         workspace = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=batch.device)
-    check(lib().sird_loss_backward(ctypes.byref(batch.c), ptr(theta), ptr(obs), _kind(kind),
-                                   ptr(grad_loss), ptr(grad_theta), ptr(loss_out),
-                                   int(ckpt_interval), ptr(workspace), workspace.numel(),
-                                   stream_handle(stream)), "sird_loss_backward")
+    a = Args(batch)
+    args = (a(theta, batch.theta_len, "theta"), a(obs, batch.obs_len, "obs"), _kind(kind),
+            a(grad_loss, batch.total_particles, "grad_loss", optional=True),
+            a(grad_theta, batch.theta_len, "grad_theta"),
+            a(loss_out, batch.total_particles, "loss_out", optional=True))
+    ws, size = a.workspace(workspace, nbytes)
+    a.device()
+    check(lib().sird_loss_backward(ctypes.byref(batch.c), *args, int(ckpt_interval),
+                                   int(bool(from_forward)), ws, size, stream_handle(stream)),
+          "sird_loss_backward")
     return grad_theta, loss_out
 
 
 def pso_topk(batch: Batch, pbest_f, k, idx_out=None, stream=None):
     if idx_out is None:
         idx_out = torch.empty((batch.n_prob, k), dtype=torch.int64, device=batch.device)
-    check(lib().pso_topk(ctypes.byref(batch.c), ptr(pbest_f), int(k), ptr(idx_out),
-                         stream_handle(stream)), "pso_topk")
+    a = Args(batch)
+    args = (a(pbest_f, batch.total_particles, "pbest_f"), int(k),
+            a(idx_out, batch.n_prob * int(k), "idx_out", dtype=torch.int64))
+    a.device()
+    check(lib().pso_topk(ctypes.byref(batch.c), *args, stream_handle(stream)), "pso_topk")
     return idx_out
 
 
@@ -323,17 +411,25 @@ def sird_gather(src: Batch, src_theta, src_lo, dst: Batch, idx, k, dst_theta=Non
                 stream=None):
     if dst_theta is None:
         dst_theta = dst.empty_theta()
-    check(lib().sird_gather(ctypes.byref(src.c), ptr(src_theta), ptr(src_lo), ctypes.byref(dst.c),
-                            ptr(dst_theta), ptr(idx), int(k), stream_handle(stream)),
-          "sird_gather")
+    a = Args(src)
+    sa = (a(src_theta, src.theta_len, "src_theta"), a(src_lo, src.box_len, "src_lo"))
+    da = (a(dst_theta, dst.theta_len, "dst_theta", batch=dst),
+          a(idx, src.n_prob * int(k), "idx", dtype=torch.int64))
+    a.device()
+    check(lib().sird_gather(ctypes.byref(src.c), *sa, ctypes.byref(dst.c), *da, int(k),
+                            stream_handle(stream)), "sird_gather")
     return dst_theta
 
 
 def sird_adam_step(batch: Batch, theta, grad, m, v, lo, hi, t, lr=1e-3, beta1=0.9,
                    beta2=0.999, eps=1e-8, stream=None):
     p = _lib.adam_params(lr, beta1, beta2, eps)
-    check(lib().sird_adam_step(ctypes.byref(batch.c), ptr(theta), ptr(grad), ptr(m), ptr(v),
-                               ptr(lo), ptr(hi), int(t), ctypes.byref(p),
+    a = Args(batch)
+    args = [a(t_, batch.theta_len, n)
+            for t_, n in ((theta, "theta"), (grad, "grad"), (m, "m"), (v, "v"))]
+    args += [a(lo, batch.box_len, "lo"), a(hi, batch.box_len, "hi")]
+    a.device()
+    check(lib().sird_adam_step(ctypes.byref(batch.c), *args, int(t), ctypes.byref(p),
                                stream_handle(stream)), "sird_adam_step")
 
 
@@ -348,6 +444,9 @@ class LbfgsState:
         P = max(batch.total_particles, 1)
         f64 = dict(dtype=torch.float64, device=dev)
         self.m = int(m)
+        a = Args(batch)
+        a(theta, batch.theta_len, "theta")
+        a.device()
         self.theta = theta.detach().clone()
         self.grad = torch.zeros(th, **f64)
         self.f = torch.zeros(P, **f64)
@@ -371,12 +470,18 @@ class LbfgsState:
 
 
 def sird_lbfgs_propose(batch: Batch, st: LbfgsState, lo, hi, stream=None):
-    check(lib().sird_lbfgs_propose(ctypes.byref(batch.c), ctypes.byref(st.c), ptr(lo), ptr(hi),
+    a = Args(batch)
+    box = (a(lo, batch.box_len, "lo"), a(hi, batch.box_len, "hi"))
+    a.device()
+    check(lib().sird_lbfgs_propose(ctypes.byref(batch.c), ctypes.byref(st.c), *box,
                                    stream_handle(stream)), "sird_lbfgs_propose")
 
 
 def sird_lbfgs_accept(batch: Batch, st: LbfgsState, lo, hi, c1=1e-4, stream=None):
-    check(lib().sird_lbfgs_accept(ctypes.byref(batch.c), ctypes.byref(st.c), ptr(lo), ptr(hi),
+    a = Args(batch)
+    box = (a(lo, batch.box_len, "lo"), a(hi, batch.box_len, "hi"))
+    a.device()
+    check(lib().sird_lbfgs_accept(ctypes.byref(batch.c), ctypes.byref(st.c), *box,
                                   float(c1), stream_handle(stream)), "sird_lbfgs_accept")
 
 
@@ -386,8 +491,11 @@ class Graph:
     def __init__(self, batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre",
                  iters_per_launch=1):
         h = ctypes.c_void_p()
+        a = Args(batch)
+        o = a(obs, batch.obs_len, "obs")
+        a.device()
         check(lib().sird_graph_create(ctypes.byref(batch.c), ctypes.byref(params.c),
-                                      ctypes.byref(swarm.c), ptr(obs), _kind(kind),
+                                      ctypes.byref(swarm.c), o, _kind(kind),
                                       int(iters_per_launch), ctypes.byref(h)),
               "sird_graph_create")
         self.h = h

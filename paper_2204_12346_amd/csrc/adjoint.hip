@@ -31,6 +31,13 @@
 // s alone, to rounding.  Recomputation is deterministic (same operations
 // from the same stored state), so the gradient is bitwise independent of
 // the checkpoint interval.
+//
+// The kernel runs in one of three modes: both passes (sird_loss_backward on
+// its own), the forward pass alone (sird_loss given a workspace: the loss,
+// and everything the reverse sweep reads, saved in the workspace), or the
+// reverse sweep alone from such a workspace (sird_loss_backward with
+// from_forward).  The saved forward is the same code as the forward pass of
+// the first mode, so the gradient is bitwise the same either way.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -56,8 +63,12 @@ struct BwdArgs {
     int obs_series;  // 1 or 3; the deceased counts are the last series
     int s;          // checkpoint interval in steps
     int n_ck_max;   // checkpoints per particle
+    int max_days;   // max W over problems (Dhat slots per particle - 1)
     int lds_stride;
 };
+
+// Modes of k_backward.
+enum BwdMode { kBoth = 0, kFwdOnly = 1, kRevOnly = 2 };
 
 // dl/dDhat_i of the cost; imax is the day MXSE takes its maximum on.
 __device__ __forceinline__ double cost_grad(int kind, int i, int W, double D, double y,
@@ -161,7 +172,7 @@ __device__ __forceinline__ int seg_of(int n, int SS, int K)
     return k > K - 1 ? K - 1 : k;
 }
 
-template <int KIND>
+template <int KIND, int MODE>
 __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
 {
     extern __shared__ double lds[];
@@ -189,6 +200,9 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     double *const ck_ws = a.ws + (size_t)(P.p_off + pc);    // checkpoint m: 3m .. 3m+2 (S, I, s)
     double *const in_ws = ck_ws + (size_t)(3 * a.n_ck_max) * PS;  // chunk c: 3c .. 3c+2
     double *const day_ws = in_ws + (size_t)(3 * ((a.s + kChunk - 1) / kChunk)) * PS;  // Dhat_i
+    // the forward pass's results the reverse sweep needs besides the
+    // checkpoints and Dhat: the day MXSE peaks on, and the loss
+    double *const tail_ws = day_ws + (size_t)(a.max_days + 1) * PS;
 
     {
         // deceased counts: the last of the obs_series blocks of W+1 values
@@ -214,6 +228,11 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     // segment change and the rescale s = b S at the start of a day, the
     // checkpoint (S, I, s) before every s-th step, the cost and Dhat at the
     // end of a day.
+    int imax = 0;
+    if constexpr (MODE == kRevOnly) {
+        imax = active ? (int)tail_ws[0] : 0;
+        if (active && a.loss_out) a.loss_out[P.p_off + pl] = tail_ws[PS];
+    } else {
     SirdState<double> y;
     y.S = N - I0 - P.R0 - P.D0;
     y.I = I0;
@@ -222,7 +241,6 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     y.s = 0.0;
     y.eS = y.eI = y.eR = y.eD = 0.0;
     double acc = 0.0;
-    int imax = 0;
     cost_accum(KIND, acc, y.D, ly[0], lw[0], 0);
     if (active) day_ws[0] = y.D;
     {
@@ -262,6 +280,14 @@ __global__ void __launch_bounds__(256) k_backward(BwdArgs a)
     }
     const double L = cost_finish(KIND, acc, W);
     if (active && a.loss_out) a.loss_out[P.p_off + pl] = L;
+    if constexpr (MODE == kFwdOnly) {
+        if (active) {
+            tail_ws[0] = (double)imax;
+            tail_ws[PS] = L;
+        }
+        return;
+    }
+    }
 
     // ---------------------------------------------------- reverse sweep
     const double gl = a.grad_loss ? a.grad_loss[P.p_off + pc] : 1.0;
@@ -619,49 +645,68 @@ static int resolve_interval(const sird_batch *b, int ckpt_interval)
 // Workspace slots per particle: 3 per checkpoint (S, I, s), 3 per chunk of
 // one replayed interval (the first and last chunks' slots go unused: the
 // first starts at the checkpoint, the last one's start stays in registers),
-// and Dhat of every day.
+// Dhat of every day, the day MXSE peaks on and the loss.
 static size_t ws_slots(const sird_batch *b, int s)
 {
     const int64_t n_ck = (b->max_steps + s - 1) / s;
     const int64_t n_chunk = ((int64_t)s + kChunk - 1) / kChunk;
-    return (size_t)(3 * n_ck + 3 * n_chunk + b->max_days + 1);
+    return (size_t)(3 * n_ck + 3 * n_chunk + b->max_days + 1 + 2);
 }
 
-}  // namespace sird
-
-using namespace sird;
-
-extern "C" size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval)
+template <int MODE>
+static void launch_backward(int kind, int grid, int block, size_t lds, hipStream_t s,
+                            const BwdArgs &a)
 {
-    if (check_batch(batch, "sird_loss_backward_workspace")) return 0;
-    if (ckpt_interval < 0) return 0;
-    const int s = resolve_interval(batch, ckpt_interval);
-    return ws_slots(batch, s) * (size_t)batch->total_particles * sizeof(double);
+    switch (kind) {
+    case SIRD_LOSS_SSRE:
+        hipLaunchKernelGGL((k_backward<SIRD_LOSS_SSRE, MODE>), dim3(grid), dim3(block), lds, s, a);
+        break;
+    case SIRD_LOSS_MSE:
+        hipLaunchKernelGGL((k_backward<SIRD_LOSS_MSE, MODE>), dim3(grid), dim3(block), lds, s, a);
+        break;
+    case SIRD_LOSS_MXSE:
+        hipLaunchKernelGGL((k_backward<SIRD_LOSS_MXSE, MODE>), dim3(grid), dim3(block), lds, s, a);
+        break;
+    case SIRD_LOSS_MAE:
+        hipLaunchKernelGGL((k_backward<SIRD_LOSS_MAE, MODE>), dim3(grid), dim3(block), lds, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_backward<SIRD_LOSS_MAPE, MODE>), dim3(grid), dim3(block), lds, s,
+                           a);
+        break;
+    }
 }
 
-extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
-                                  const double *obs, int loss_kind, const double *grad_loss,
-                                  double *grad_theta, double *loss_out, int ckpt_interval,
-                                  void *workspace, size_t ws_bytes, void *stream)
+size_t adjoint_workspace_bytes(const sird_batch *b, int ckpt_interval)
 {
-    int st = check_batch(batch, "sird_loss_backward");
+    return ws_slots(b, resolve_interval(b, ckpt_interval)) * (size_t)b->total_particles *
+           sizeof(double);
+}
+
+int adjoint_enqueue(const sird_batch *batch, const double *theta, const double *obs,
+                    int loss_kind, const double *grad_loss, double *grad_theta,
+                    double *loss_out, int ckpt_interval, int mode, void *workspace,
+                    size_t ws_bytes, hipStream_t stream, const char *who)
+{
+    const std::string w(who);
+    int st = check_batch(batch, who);
     if (st) return st;
-    if (!theta || !obs || !grad_theta || !workspace)
-        return fail(SIRD_EINVAL, "sird_loss_backward: NULL array");
+    if (!theta || !obs || !workspace) return fail(SIRD_EINVAL, w + ": NULL array");
+    if (mode != kFwdOnly && !grad_theta) return fail(SIRD_EINVAL, w + ": grad_theta is NULL");
+    if (mode == kFwdOnly && !loss_out) return fail(SIRD_EINVAL, w + ": loss is NULL");
     if (batch->dtype != SIRD_F64)
-        return fail(SIRD_EINVAL, "sird_loss_backward: only SIRD_F64 batches are supported");
+        return fail(SIRD_EINVAL, w + ": the adjoint supports SIRD_F64 batches only");
     if (loss_kind < SIRD_LOSS_SSRE || loss_kind > SIRD_LOSS_MAPE)
-        return fail(SIRD_EINVAL, "sird_loss_backward: loss_kind must be a deceased-count cost");
+        return fail(SIRD_EINVAL, w + ": the adjoint needs a deceased-count cost (loss_kind 0..4)");
     if (batch->models != 1 << SIRD_MODEL_RK4_SEGMENTS)
-        return fail(SIRD_EINVAL, "sird_loss_backward: only the RK4 segment model is supported");
-    if (ckpt_interval < 0) return fail(SIRD_EINVAL, "sird_loss_backward: ckpt_interval < 0");
-    if (batch->obs_len < 1)
-        return fail(SIRD_EINVAL, "sird_loss_backward: batch planned without obs");
+        return fail(SIRD_EINVAL, w + ": the adjoint supports the RK4 segment model only");
+    if (ckpt_interval < 0) return fail(SIRD_EINVAL, w + ": ckpt_interval < 0");
+    if (batch->obs_len < 1) return fail(SIRD_EINVAL, w + ": batch planned without obs");
     if (((uintptr_t)workspace & 255) != 0)
-        return fail(SIRD_EINVAL, "sird_loss_backward: workspace not 256-byte aligned");
+        return fail(SIRD_EINVAL, w + ": workspace not 256-byte aligned");
     const int s = resolve_interval(batch, ckpt_interval);
-    const size_t need = ws_slots(batch, s) * (size_t)batch->total_particles * sizeof(double);
-    if (ws_bytes < need) return fail(SIRD_ENOSPACE, "sird_loss_backward: workspace too small");
+    if (ws_bytes < adjoint_workspace_bytes(batch, ckpt_interval))
+        return fail(SIRD_ENOSPACE, w + ": workspace too small");
     BwdArgs a{};
     a.probs = batch->probs;
     a.tiles = batch->tiles;
@@ -676,29 +721,42 @@ extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
     a.obs_series = batch->obs_series;
     a.s = s;
     a.n_ck_max = (int)((batch->max_steps + s - 1) / s);
+    a.max_days = batch->max_days;
     a.lds_stride = 2 * (batch->max_days + 1);
     const int block = 256;
     const size_t lds = (size_t)(block / kWave) * a.lds_stride * sizeof(double);
-    if (lds > 65536) return fail(SIRD_EINVAL, "sird_loss_backward: window too long for LDS");
+    if (lds > 65536) return fail(SIRD_EINVAL, w + ": window too long for LDS");
     const int grid = tile_blocks(batch->n_tiles);
     if (grid == 0) return SIRD_OK;
-    hipStream_t s_ = (hipStream_t)stream;
-    switch (loss_kind) {
-    case SIRD_LOSS_SSRE:
-        hipLaunchKernelGGL(k_backward<SIRD_LOSS_SSRE>, dim3(grid), dim3(block), lds, s_, a);
-        break;
-    case SIRD_LOSS_MSE:
-        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MSE>, dim3(grid), dim3(block), lds, s_, a);
-        break;
-    case SIRD_LOSS_MXSE:
-        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MXSE>, dim3(grid), dim3(block), lds, s_, a);
-        break;
-    case SIRD_LOSS_MAE:
-        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MAE>, dim3(grid), dim3(block), lds, s_, a);
-        break;
-    default:
-        hipLaunchKernelGGL(k_backward<SIRD_LOSS_MAPE>, dim3(grid), dim3(block), lds, s_, a);
-        break;
-    }
-    return hip_status(hipGetLastError(), "sird_loss_backward");
+    if (mode == kFwdOnly)
+        launch_backward<kFwdOnly>(loss_kind, grid, block, lds, stream, a);
+    else if (mode == kRevOnly)
+        launch_backward<kRevOnly>(loss_kind, grid, block, lds, stream, a);
+    else
+        launch_backward<kBoth>(loss_kind, grid, block, lds, stream, a);
+    return hip_status(hipGetLastError(), who);
+}
+
+}  // namespace sird
+
+using namespace sird;
+
+extern "C" size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval)
+{
+    if (check_batch(batch, "sird_loss_backward_workspace")) return 0;
+    if (ckpt_interval < 0) return 0;
+    return adjoint_workspace_bytes(batch, ckpt_interval);
+}
+
+extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
+                                  const double *obs, int loss_kind, const double *grad_loss,
+                                  double *grad_theta, double *loss_out, int ckpt_interval,
+                                  int from_forward, void *workspace, size_t ws_bytes,
+                                  void *stream)
+{
+    if (from_forward != 0 && from_forward != 1)
+        return fail(SIRD_EINVAL, "sird_loss_backward: from_forward must be 0 or 1");
+    return adjoint_enqueue(batch, theta, obs, loss_kind, grad_loss, grad_theta, loss_out,
+                           ckpt_interval, from_forward ? kRevOnly : kBoth, workspace, ws_bytes,
+                           (hipStream_t)stream, "sird_loss_backward");
 }

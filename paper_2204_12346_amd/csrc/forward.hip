@@ -467,7 +467,8 @@ int forward_iterate(const sird_batch *b, const PsoMove &mv, const pso_state *st,
 using namespace sird;
 
 extern "C" int sird_loss(const sird_batch *batch, const double *theta, const double *obs,
-                         int loss_kind, double *loss, void *stream)
+                         int loss_kind, double *loss, int ckpt_interval, void *workspace,
+                         size_t ws_bytes, void *stream)
 {
     int st = check_batch(batch, "sird_loss");
     if (st) return st;
@@ -475,6 +476,10 @@ extern "C" int sird_loss(const sird_batch *batch, const double *theta, const dou
     st = check_kind(batch, loss_kind, "sird_loss");
     if (st) return st;
     if (batch->obs_len < 1) return fail(SIRD_EINVAL, "sird_loss: batch planned without obs");
+    if (workspace)  // the adjoint's forward pass, saving its checkpoints
+        return adjoint_enqueue(batch, theta, obs, loss_kind, nullptr, nullptr, loss,
+                               ckpt_interval, 1, workspace, ws_bytes, (hipStream_t)stream,
+                               "sird_loss");
     return forward_loss(batch, theta, obs, loss_kind, loss, (hipStream_t)stream);
 }
 

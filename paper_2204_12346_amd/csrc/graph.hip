@@ -49,16 +49,27 @@ extern "C" int sird_graph_create(const sird_batch *batch, const pso_params *para
     r = pso_iterate_enqueue(batch, params, state, obs, loss_kind, iters_per_launch, cs);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
-    (void)hipStreamDestroy(cs);
     if (r != SIRD_OK || e2 != hipSuccess) {
+        (void)hipStreamDestroy(cs);
         if (g) (void)hipGraphDestroy(g);
         return r != SIRD_OK ? r : hip_status(e2, "sird_graph_create(end capture)");
     }
     hipGraphExec_t x = nullptr;
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
         (void)hipGraphDestroy(g);
         return hip_status(e, "sird_graph_create(instantiate)");
+    }
+    // upload the executable graph now, so that the first launch does not
+    // pay for it
+    e = hipGraphUpload(x, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return hip_status(e, "sird_graph_create(upload)");
     }
     GraphHandle *h = new (std::nothrow) GraphHandle;
     if (!h) {

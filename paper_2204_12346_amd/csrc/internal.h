@@ -36,4 +36,15 @@ int integ_block(const sird_batch *b);
 // wavefront per tile.
 inline int tile_blocks(int n_tiles) { return (n_tiles + 3) / 4; }
 
+// The discrete adjoint (adjoint.hip).  mode 0: forward pass and reverse
+// sweep; 1: the forward pass alone, saving the loss and what the reverse
+// sweep reads in the workspace (loss_out required); 2: the reverse sweep
+// alone from a workspace that mode 1 filled with the same theta, obs, kind
+// and interval.  All host checks run before anything is enqueued.
+int adjoint_enqueue(const sird_batch *batch, const double *theta, const double *obs,
+                    int loss_kind, const double *grad_loss, double *grad_theta,
+                    double *loss_out, int ckpt_interval, int mode, void *workspace,
+                    size_t ws_bytes, hipStream_t stream, const char *who);
+size_t adjoint_workspace_bytes(const sird_batch *b, int ckpt_interval);
+
 }  // namespace sird

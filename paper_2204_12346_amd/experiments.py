@@ -2,7 +2,7 @@
 throughput, gradients per second, time-to-fit of plain swarm vs swarm +
 adjoint refinement, the rolling-window fit + 14-day forecast, the paper's
 own timing case (one swarm iteration of its Euler + ramp model under
-F_IRD^MXSE), its window-wise calibration and its repetition study.
+F_IRD^MXSE) and its repetition study.
 
 Each function builds its batch from ``synth`` inputs, times device work with
 HIP events (or wall clock where the protocol is wall time) and returns a
@@ -72,7 +72,11 @@ def swarm_throughput(wl, dtype="f64", iters=200, warmup=10, graph_chunk=10,
 
 
 def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
-    """Loss + gradient of every parameter vector (sird_loss_backward)."""
+    """Loss + gradient of every parameter vector, as the autograd path runs
+    it: sird_loss saving the adjoint's checkpoints, then the reverse sweep
+    alone (sird_loss_backward from_forward).  Also timed: the self-contained
+    sird_loss_backward (both passes in one launch, as the refinement uses
+    it) and the plain loss kernel."""
     f = wl.fits[0]
     b = Batch([ProblemSpec.from_fit(f, len(thetas))])
     theta = b.pack_theta([thetas])
@@ -81,34 +85,53 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
     loss = b.empty_particles()
     ws = torch.empty(sird_loss_backward_workspace(b, ckpt_interval), dtype=torch.uint8,
                      device=b.device)
-    sird_loss_backward(b, theta, obs, wl.loss, grad_theta=grad, loss_out=loss,
-                       ckpt_interval=ckpt_interval, workspace=ws)
-    e0, e1 = _events()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
+
+    def timed(fn):
+        fn()  # warm
+        e0, e1 = _events()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def fwd_ckpt():
+        sird_loss(b, theta, obs, wl.loss, loss, workspace=ws, ckpt_interval=ckpt_interval)
+
+    def rev():
+        sird_loss_backward(b, theta, obs, wl.loss, grad_theta=grad, ckpt_interval=ckpt_interval,
+                           workspace=ws, from_forward=True)
+
+    def pair():
+        fwd_ckpt()
+        rev()
+
+    def full():
         sird_loss_backward(b, theta, obs, wl.loss, grad_theta=grad, loss_out=loss,
                            ckpt_interval=ckpt_interval, workspace=ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_b = e0.elapsed_time(e1) / reps
-    sird_loss(b, theta, obs, wl.loss, loss)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        sird_loss(b, theta, obs, wl.loss, loss)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_f = e0.elapsed_time(e1) / reps
-    return {"gradients_per_s": len(thetas) / (ms_b / 1e3), "ms_backward": ms_b,
-            "ckpt_interval": ckpt_interval or "ceil(sqrt(T))",
-            "ms_forward": ms_f, "backward_over_forward": ms_b / ms_f,
+
+    ms_pair = timed(pair)
+    ms_fc = timed(fwd_ckpt)
+    fwd_ckpt()
+    ms_rev = timed(rev)
+    ms_full = timed(full)
+    ms_f = timed(lambda: sird_loss(b, theta, obs, wl.loss, loss))
+    n = len(thetas)
+    return {"gradients_per_s": n / (ms_pair / 1e3), "ms_loss_and_gradient": ms_pair,
+            "ms_forward_saving_checkpoints": ms_fc, "ms_reverse_sweep": ms_rev,
+            "gradients_per_s_reverse_sweep": n / (ms_rev / 1e3),
+            "ms_self_contained_backward": ms_full,
+            "gradients_per_s_self_contained": n / (ms_full / 1e3),
+            "ms_forward": ms_f, "reverse_over_forward": ms_rev / ms_f,
+            "ckpt_interval": ckpt_interval or "ceil(sqrt(T)) rounded up to 10",
             "particle_steps": b.particle_steps, "workspace_bytes": int(ws.numel())}
 
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
                 ks=(64, 1024, 4096), refine_steps=2000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6),
-                chunk=50, method="lbfgs", adam_arms=()) -> Dict:
+                chunk=50, method="lbfgs", adam_arms=(), adam_lr_end=None) -> Dict:
     """Wall time from pso_init until the loss is within rel of the best
     loss any run of either arm found (L_best), per seed:
       plain arm: swarm iterations (graph chunks of `chunk`), capped;
@@ -116,7 +139,9 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
       personal bests with gradients from the discrete adjoint: projected
       L-BFGS rounds (method "lbfgs", I0 in log coordinates) or projected
       Adam steps ("adam"); one arm per (I', k), plus projected Adam arms
-      for the (I', k) in adam_arms (judged against the same L_best).  A round on k vectors of
+      for the (I', k) in adam_arms (judged against the same L_best).  Adam's
+      step is lr, or decays geometrically from lr to adam_lr_end over the
+      refine_steps steps when adam_lr_end is given.  A round on k vectors of
       one window costs about the same wall time for any k up to a few
       thousand (one wavefront per 64 vectors), so a larger k refines more
       starting points, and so more basins, at little extra cost.
@@ -164,7 +189,8 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
             best = sw.gbest_f[0].item()  # synchronises
             curve = [(time.perf_counter() - t0, best, 0)]
             if meth == "adam":
-                _adam_curve(b, sw, params, obs, wl.loss, k, refine_steps, lr, t0, curve)
+                _adam_curve(b, sw, params, obs, wl.loss, k, refine_steps, lr, t0, curve,
+                            lr_end=adam_lr_end)
             else:
                 _lbfgs_curve(b, sw, params, obs, wl.loss, k, refine_steps, t0, curve)
             curves[arm][seed] = curve
@@ -183,6 +209,7 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
            "refine_steps_cap": refine_steps, "k": list(ks), "pso_first": list(pso_first)}
     if method == "adam" or adam_arms:
         res["lr"] = lr
+        res["lr_end"] = adam_lr_end
     for arm, runs in curves.items():
         entry = {"final_loss": [runs[s][-1][1] for s in seeds],
                  "wall_s": [runs[s][-1][0] for s in seeds], "median_s": {}}
@@ -204,9 +231,11 @@ def _median(ts):
     return None if not np.isfinite(m) else m
 
 
-def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=25):
+def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=25,
+                lr_end=None):
     """Projected Adam from the top-k personal bests, appending
-    (elapsed s, best loss so far, Adam step) every check_every steps."""
+    (elapsed s, best loss so far, Adam step) every check_every steps; the
+    step decays geometrically from lr to lr_end when lr_end is given."""
     from .core import pso_topk, sird_adam_step, sird_gather
     idx = pso_topk(b, sw.pbest_f, k)
     specs = [s.with_particles(k) for s in b.specs]
@@ -223,7 +252,8 @@ def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=2
     for t in range(1, steps + 1):
         sird_loss_backward(rb, theta, obs, kind, grad_theta=grad, loss_out=loss,
                            ckpt_interval=ci, workspace=ws)
-        sird_adam_step(rb, theta, grad, m, v, params.lo, params.hi, t, lr=lr)
+        lr_t = lr if lr_end is None else lr * (lr_end / lr) ** ((t - 1) / max(steps - 1, 1))
+        sird_adam_step(rb, theta, grad, m, v, params.lo, params.hi, t, lr=lr_t)
         if t % check_every == 0:
             cur = float(torch.nan_to_num(loss, nan=float("inf")).min().item())
             best = min(best, cur)
@@ -401,48 +431,3 @@ def repetition(wl, horizon=21, launch=None) -> Dict:
             "particle_steps_per_s": b.particle_steps * wl.iters / t_pso,
             "loss": q(L), "params": {n: q(th[:, j]) for j, n in enumerate(names)},
             f"extension_day_{horizon}_bands": bands}
-
-
-def window_wise(wl, launch=None) -> Dict:
-    """The window-wise calibration (Sec. 3.1, 4.1): every window of the
-    series in one batch through wl.iters swarm iterations, then the fitted
-    I, R, D of each window's global best.  Returns the time, R^2 of D (the
-    paper's goodness-of-fit statistic; also of I and R) over the windows,
-    and the fitting bands: per day, the spread (max - min) of the fitted D
-    over the windows that cover it, relative to the observed D."""
-    b, params, sw, obs = _setup(wl, "f64", launch)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pso_init(b, params, sw)
-    sird_pso_iterate(b, params, sw, obs, wl.loss, wl.iters)
-    torch.cuda.synchronize()
-    t_pso = time.perf_counter() - t0
-    th = b.unpack_box(sw.gbest_x)
-    trajs = fit.forecast(b.specs, [t[None, :] for t in th], 0, device=b.device)
-    r2s = {"D": [], "I": [], "R": []}
-    delta = 3
-    T = len(wl.fits) * delta + wl.fits[0].W
-    lo_band = np.full(T, np.inf)
-    hi_band = np.full(T, -np.inf)
-    obs_D = np.full(T, np.nan)
-    for i, (f, tr) in enumerate(zip(wl.fits, trajs)):
-        o = np.asarray(f.obs3).reshape(3, -1)
-        for c, name in ((1, "I"), (2, "R"), (3, "D")):
-            r2s[name].append(r2(o[c - 1], tr[0, c]))
-        days = slice(delta * i, delta * i + f.W + 1)
-        lo_band[days] = np.minimum(lo_band[days], tr[0, 3])
-        hi_band[days] = np.maximum(hi_band[days], tr[0, 3])
-        obs_D[days] = o[2]
-    ok = np.isfinite(lo_band) & (obs_D > 0)
-    width = (hi_band[ok] - lo_band[ok]) / obs_D[ok]
-
-    def q(v):
-        return {p: float(np.quantile(v, p / 100)) for p in (5, 50, 95)}
-
-    return {"windows": b.n_prob, "particles_per_window": wl.fits[0].n_part,
-            "iterations": wl.iters, "seconds_swarm": t_pso,
-            "particle_steps_per_s": b.particle_steps * wl.iters / t_pso,
-            "r2_D_mean": float(np.mean(r2s["D"])), "r2_D": q(r2s["D"]),
-            "r2_I_mean": float(np.mean(r2s["I"])), "r2_R_mean": float(np.mean(r2s["R"])),
-            "final_loss": q(sw.gbest_f.cpu().numpy()),
-            "band_width_rel_D": q(width)}

@@ -296,38 +296,3 @@ def rep(n_rep=1000, n_part=10000, iters=100, t0=20):
     with its own Philox stream (the repetition study of Sec. 4.2)."""
     fits = [_paper_fit(35, t0, n_part, r) for r in range(n_rep)]
     return Workload("rep", fits, iters=iters, seed=7, loss="ird_mxse", w=0.5, c1=0.5, c2=0.5)
-
-
-def windows_regimes(days=450):
-    """Daily beta of the window-wise series: regimes of U{30..90} days,
-    beta per regime ~ U[0.07, 0.14] (seed 9); gamma = 0.1, mu = 0.002 and
-    I0 = 1000.  The range keeps R_eff between 0.7 and 1.4: over 450 days
-    the series peaks near 6e5 active cases and ends near 7e4 deaths, the
-    size of the paper's Polish data."""
-    rng = np.random.default_rng(9)
-    beta = np.zeros(days)
-    t = 0
-    while t < days:
-        L = int(rng.integers(30, 91))
-        beta[t:t + L] = rng.uniform(0.07, 0.14)
-        t += L
-    return beta
-
-
-def windows(n_part=10000, iters=100, tau=35, delta=3):
-    """floor(1 + (T - tau)/delta) = 139 windows [delta i, delta i + tau] of
-    the 450-day series (T = 449), each started from the observed I, R, D of
-    its first day; window i has Philox stream i."""
-    z = _load("windows")
-    obs = z["obs"]
-    T = obs.shape[1] - 1
-    fits = []
-    for i in range(1 + (T - tau) // delta):
-        t0 = delta * i
-        I0, R0, D0 = (float(v) for v in obs[:, t0])
-        lo, hi = paper_box(tau, I0)
-        fits.append(Fit(W=tau, spd=1, seg_days=1, K=4, N=POLAND_N, R0=R0, D0=D0, lo=lo, hi=hi,
-                        y=obs[2, t0:t0 + tau + 1].copy(), n_part=n_part, stream=i,
-                        obs3=obs[:, t0:t0 + tau + 1].reshape(-1).copy(), model="euler_ramp"))
-    return Workload("windows", fits, iters=iters, seed=9, loss="ird_mxse", w=0.5, c1=0.5,
-                    c2=0.5)

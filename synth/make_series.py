@@ -77,24 +77,7 @@ def make_paper():
     return dict(obs=np.stack([yI, yR, yD]), truth=truth)
 
 
-def make_windows():
-    """450 days of I, R, D from RK4 with daily piecewise-constant beta
-    (regimes of weeks to months), with the count noise of make_paper."""
-    beta = synth.windows_regimes(450)
-    days = 449
-    prob = oracle.Problem(W=days, spd=10, seg_days=1, K=days, N=synth.POLAND_N)
-    theta = np.concatenate([beta[:days], [0.1, 0.002, 1000.0]])
-    truth = oracle.integrate(prob, theta)
-    rng = np.random.default_rng(9)
-    yI = synth.noisy_level(truth[1], rng)
-    yI[0] = truth[1, 0]
-    yR = synth.noisy_cumulative(truth[2], "negbin", rng)
-    yD = synth.noisy_cumulative(truth[3], "negbin", rng)
-    return dict(obs=np.stack([yI, yR, yD]), truth=truth, beta=beta)
-
-
-MAKERS = dict(c1=make_c1, c2=make_c2, c3=make_c3, c4=make_c4, c5=make_c5, paper=make_paper,
-              windows=make_windows)
+MAKERS = dict(c1=make_c1, c2=make_c2, c3=make_c3, c4=make_c4, c5=make_c5, paper=make_paper)
 
 
 def main(names=None):

@@ -13,7 +13,9 @@ Parity criteria (FP64 unless stated):
   * losses: |L_gpu - L_ref| <= eps max(L_ref, kappa), where kappa is the
     first-order sensitivity of the cost to relative changes of the model's
     deceased values (sum of |dl/dDhat_i| |Dhat_i|), so that a loss near zero
-    (a noise-free fit) is judged by the size of its terms, not by itself.
+    (a noise-free fit) is judged by the size of its terms, not by itself;
+  * gradients: per component |g_j - g_ref,j| <= 1e-6 |g_ref,j| + 1e-10 scale_j,
+    scale_j the sum of the absolute terms the component adds up.
 """
 import numpy as np
 import torch
@@ -132,3 +134,41 @@ def kappa_ird(kind, traj, obs3):
             k = kappa(low, yh / r, yo / r)
         worst = max(worst, k)
     return worst
+
+
+GRAD_RTOL = 1e-6
+# Floor of the per-component criterion, relative to the component's own
+# scale: the sum over days of |dl/dDhat_i| |dDhat_i/dtheta_j| (the terms the
+# component adds up).  Forward mode and the complex step agree to ~3e-14 of
+# it on the segmented workload, near its truth included.
+GRAD_SCALE_FLOOR = 1e-10
+
+
+def oracle_grad(prob, theta, y, kind):
+    """(gradient, per-component scale) of the oracle's forward mode."""
+    _, g, sc = oracle.loss_grad_fwd(prob, theta, y, kind, with_scale=True)
+    return g, sc
+
+
+def assert_grad_close(got, ref, scale, what="", worst=None):
+    """|g_j - g_ref,j| <= 1e-6 |g_ref,j| + 1e-10 scale_j for every component
+    j; worst (a list) collects the largest |g_j - g_ref,j| / |g_ref,j|."""
+    got, ref, scale = np.asarray(got), np.asarray(ref), np.asarray(scale)
+    err = np.abs(got - ref)
+    tol = GRAD_RTOL * np.abs(ref) + GRAD_SCALE_FLOOR * scale
+    bad = ~(err <= tol)
+    if bad.any():
+        j = int(np.argmax(bad))
+        raise AssertionError(f"{what}: component {j}: gpu={got[j]!r} ref={ref[j]!r} "
+                             f"scale={scale[j]!r}")
+    if worst is not None:
+        nz = ref != 0
+        worst.append(float(np.max(err[nz] / np.abs(ref[nz]))) if nz.any() else 0.0)
+
+
+def near_truth(f, n, seed):
+    """n parameter vectors within 1e-3 (relative) of the synthetic truth:
+    every segment's beta then shapes the deaths and its gradient matters."""
+    rng = np.random.default_rng(seed)
+    t = np.asarray(f.truth, dtype=np.float64)
+    return t * (1 + 1e-3 * rng.standard_normal((n, t.size)))

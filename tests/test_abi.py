@@ -152,16 +152,16 @@ def test_device_calls_reject_bad_arguments_without_a_gpu(L):
     lib = L.lib()
     null = ctypes.c_void_p()
     # NULL batch
-    assert lib.sird_loss(None, null, null, 0, null, None) == L.SIRD_EINVAL
+    assert lib.sird_loss(None, null, null, 0, null, 0, None, 0, None) == L.SIRD_EINVAL
     assert lib.sird_integrate(None, null, null, None) == L.SIRD_EINVAL
     assert lib.pso_step(None, None, None, None) == L.SIRD_EINVAL
-    assert lib.sird_loss_backward(None, null, null, 0, null, null, null, 0, null, 0,
+    assert lib.sird_loss_backward(None, null, null, 0, null, null, null, 0, 0, null, 0,
                                   None) == L.SIRD_EINVAL
     assert lib.sird_graph_launch(None, 1, None) == L.SIRD_EINVAL
     assert lib.sird_graph_destroy(None) == 0
     # an unplanned batch
     b = L.sird_batch()
-    assert lib.sird_loss(ctypes.byref(b), null, null, 0, null, None) == L.SIRD_EINVAL
+    assert lib.sird_loss(ctypes.byref(b), null, null, 0, null, 0, None, 0, None) == L.SIRD_EINVAL
     assert b"not planned" in lib.sird_last_error() or b"n_prob" in lib.sird_last_error()
     assert lib.sird_loss_backward_workspace(ctypes.byref(b), 0) == 0
 
@@ -182,39 +182,40 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     dummy = torch.zeros(8, dtype=torch.float64)
     for kind in (-1, 9):
         assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), kind,
-                             dummy.data_ptr(), None) == L.SIRD_EINVAL
+                             dummy.data_ptr(), 0, None, 0, None) == L.SIRD_EINVAL
         assert b"unknown loss_kind" in lib.sird_last_error()
     # the F_IRD kinds need the I and R series too
     for kind in (5, 8):
         assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), kind,
-                             dummy.data_ptr(), None) == L.SIRD_EINVAL
+                             dummy.data_ptr(), 0, None, 0, None) == L.SIRD_EINVAL
         assert b"obs_series = 3" in lib.sird_last_error()
     b.c.models = 0
     assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
-                         dummy.data_ptr(), None) == L.SIRD_EINVAL
+                         dummy.data_ptr(), 0, None, 0, None) == L.SIRD_EINVAL
     b.c.models = 1
     b.c.dtype = 7
     assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
-                         dummy.data_ptr(), None) == L.SIRD_EINVAL
+                         dummy.data_ptr(), 0, None, 0, None) == L.SIRD_EINVAL
     b.c.dtype = 0
     b.c.block = 96
     assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
-                         dummy.data_ptr(), None) == L.SIRD_EINVAL
+                         dummy.data_ptr(), 0, None, 0, None) == L.SIRD_EINVAL
     b.c.block = 0
     assert b.c.waves_per_simd == 0
     for w in (-1, 9):
         b.c.waves_per_simd = w
         assert lib.sird_loss(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0,
-                             dummy.data_ptr(), None) == L.SIRD_EINVAL
+                             dummy.data_ptr(), 0, None, 0, None) == L.SIRD_EINVAL
         assert b"waves_per_simd" in lib.sird_last_error()
     b.c.waves_per_simd = 0
     ws = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 0)
     s = int(np.ceil(np.sqrt(300) / 10)) * 10
-    # 3 per checkpoint, 3 per 8-step chunk of one interval, one per day
-    assert ws == (3 * int(np.ceil(300 / s)) + 3 * int(np.ceil(s / 8)) + 46) * 165 * 8
+    # 3 per checkpoint, 3 per 8-step chunk of one interval, one per day, the
+    # day MXSE peaks on and the loss
+    assert ws == (3 * int(np.ceil(300 / s)) + 3 * int(np.ceil(s / 8)) + 46 + 2) * 165 * 8
     # too small a workspace is reported before anything is enqueued
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
-                                dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 16, None)
+                                dummy.data_ptr(), None, 0, 0, ctypes.c_void_p(4096), 16, None)
     assert st == L.SIRD_ENOSPACE
 
 
@@ -233,11 +234,11 @@ def test_ramp_model_and_three_series_batches_on_host(L):
     dummy = torch.zeros(8, dtype=torch.float64)
     # gradients exist for the RK4 model with a deceased-count cost only
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
-                                dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 1 << 40, None)
+                                dummy.data_ptr(), None, 0, 0, ctypes.c_void_p(4096), 1 << 40, None)
     assert st == L.SIRD_EINVAL and b"RK4 segment model" in lib.sird_last_error()
     b.c.models = 1
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 5, None,
-                                dummy.data_ptr(), None, 0, ctypes.c_void_p(4096), 1 << 40, None)
+                                dummy.data_ptr(), None, 0, 0, ctypes.c_void_p(4096), 1 << 40, None)
     assert st == L.SIRD_EINVAL and b"deceased-count" in lib.sird_last_error()
 
 
@@ -253,3 +254,31 @@ def test_layout_round_trip_on_host():
         np.testing.assert_array_equal(a, c)
     # SoA: parameter j of particle p of problem 0 is at j*7 + p
     assert t[2 * 7 + 4].item() == th[0][4, 2]
+
+
+def test_loss_with_checkpoint_workspace_checks_on_host(L):
+    """sird_loss with a workspace is the adjoint's forward pass: it takes
+    what sird_loss_backward takes, and refuses the rest before enqueueing."""
+    import torch
+    from paper_2204_12346_amd import core
+    specs = [core.ProblemSpec(30, 10, 14, 3, 1e6, n_part=100, stream=0)]
+    b = core.Batch(specs, device="cpu")
+    lib = L.lib()
+    d = torch.zeros(8, dtype=torch.float64).data_ptr()
+    big = ctypes.c_void_p(4096)
+    need = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 10)
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, 10, big, need - 1, None) == L.SIRD_ENOSPACE
+    assert b"workspace too small" in lib.sird_last_error()
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, -1, big, 1 << 40, None) == L.SIRD_EINVAL
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 5, d, 10, big, 1 << 40, None) == L.SIRD_EINVAL
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 1, d, 10, ctypes.c_void_p(4096 + 8), 1 << 40,
+                         None) == L.SIRD_EINVAL
+    assert b"256-byte aligned" in lib.sird_last_error()
+    b.c.dtype = L.SIRD_F32
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, 10, big, 1 << 40, None) == L.SIRD_EINVAL
+    assert b"SIRD_F64" in lib.sird_last_error()
+    b.c.dtype = L.SIRD_F64
+    # the reverse sweep alone takes from_forward = 1, nothing else
+    assert lib.sird_loss_backward(ctypes.byref(b.c), d, d, 0, None, d, None, 10, 2, big,
+                                  1 << 40, None) == L.SIRD_EINVAL
+    assert b"from_forward" in lib.sird_last_error()

@@ -246,32 +246,3 @@ def test_ramp_edge_cases_against_oracle():
                    for t in trajs]
             assert_loss_close(got[r], ref, np.nan_to_num(kap), TOL64, f"{kind}/problem {r}")
     assert np.isnan(got[3][5])
-
-
-def test_window_wise_batch_equals_single_windows():
-    """Windows with their own start states and streams run in one batch
-    exactly as alone."""
-    wl = synth.windows(n_part=128, iters=8)
-    fits = wl.fits[::40]  # 4 windows
-    b = _batch(fits, [f.n_part for f in fits])
-    params = S.PsoParams(b, [f.lo for f in fits], [f.hi for f in fits], wl.w, wl.c1, wl.c2,
-                         wl.seed)
-    sw = S.Swarm(b, hist_len=wl.iters)
-    S.pso_init(b, params, sw)
-    S.sird_pso_iterate(b, params, sw, b.pack_obs([f.obs3 for f in fits]), wl.loss, wl.iters)
-    hist = sw.hist_f.cpu().numpy()
-    for r, f in enumerate(fits):
-        one = _batch([f], [f.n_part])
-        p1 = S.PsoParams(one, [f.lo], [f.hi], wl.w, wl.c1, wl.c2, wl.seed)
-        s1 = S.Swarm(one, hist_len=wl.iters)
-        S.pso_init(one, p1, s1)
-        S.sird_pso_iterate(one, p1, s1, one.pack_obs([f.obs3]), wl.loss, wl.iters)
-        assert np.array_equal(s1.hist_f.cpu().numpy()[:, 0], hist[:, r]), r
-    # and the oracle's swarm on the first window agrees up to its first near-tie
-    f = fits[0]
-    hf, hidx, hm, _ = oracle.pso_run_model(oracle_problem_model(f), f.obs3, wl.loss, f.n_part,
-                                           f.lo, f.hi, wl.w, wl.c1, wl.c2, wl.seed, f.stream,
-                                           wl.iters, nthreads=8)
-    tie = np.nonzero(hm < NEAR_TIE)[0]
-    upto = int(tie[0]) if len(tie) else wl.iters
-    np.testing.assert_allclose(hist[:upto, 0], hf[:upto], rtol=1e-11)

@@ -10,7 +10,8 @@ import synth
 import paper_2204_12346_amd as S
 from paper_2204_12346_amd import autotune, fit
 from paper_2204_12346_amd.autograd import SirdLoss
-from gpu_helpers import TOL64, assert_traj_close, make_batch, need_gpu, oracle_problem, random_theta
+from gpu_helpers import (TOL64, assert_grad_close, assert_traj_close, make_batch, near_truth,
+                         need_gpu, oracle_grad, oracle_problem, random_theta)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,22 +92,31 @@ def test_gather_and_adam_match_oracle():
         assert np.all(back[r] >= wl.fits[r].lo) and np.all(back[r] <= wl.fits[r].hi)
 
 
-def test_autograd_function_matches_oracle_gradient():
+@pytest.mark.parametrize("interval", [0, None])
+def test_autograd_function_matches_oracle_gradient(interval):
+    """SirdLoss: forward = sird_loss saving the adjoint's checkpoints,
+    backward = the reverse sweep alone (sqrt(T) checkpoints, or the
+    default 10-step ones)."""
     f = synth.c2().fits[0]
     P = 16
     th = random_theta(f, P, seed=6)
     th[:, :f.K] *= 0.5
+    th[P - 4:] = near_truth(f, 4, seed=61)
     b = make_batch([f], [P])
     theta = b.pack_theta([th]).requires_grad_(True)
     obs = b.pack_obs([f.y])
-    loss = SirdLoss.apply(theta, b, obs, "ssre", 0)
+    loss = SirdLoss.apply(theta, b, obs, "ssre", interval)
     w = torch.linspace(0.5, 2.0, P, dtype=torch.float64, device=theta.device)
     (loss[:P] * w).sum().backward()
     g = b.unpack_theta(theta.grad)[0]
     prob = oracle_problem(f)
     for p in range(P):
-        gr = oracle.loss_grad_fwd(prob, th[p], f.y, "ssre")[1] * w[p].item()
-        np.testing.assert_allclose(g[p], gr, rtol=1e-6, atol=1e-9 * np.abs(gr).max())
+        gr, sc = oracle_grad(prob, th[p], f.y, "ssre")
+        assert_grad_close(g[p], gr * w[p].item(), sc * abs(w[p].item()), f"particle {p}")
+    # the same as the self-contained backward, bitwise
+    g_full, L_full = S.sird_loss_backward(b, theta.detach(), obs, "ssre", grad_loss=w,
+                                          loss_out=b.empty_particles())
+    assert torch.equal(theta.grad, g_full) and torch.equal(loss.detach(), L_full)
 
 
 def test_refine_topk_lowers_the_loss_on_noise_free_data():

@@ -20,7 +20,7 @@ def _maker():
 
 def test_stored_series_regenerate_bitwise(orc):
     m = _maker()
-    for name in ("c1", "c2", "c4", "c5", "c3", "paper", "windows"):
+    for name in ("c1", "c2", "c4", "c5", "c3", "paper"):
         fresh = m.MAKERS[name]()
         stored = synth._load(name)
         assert set(fresh) == set(stored)
@@ -52,41 +52,9 @@ def test_paper_shaped_workloads():
     o = f.obs3.reshape(3, -1)
     assert o.shape == (3, 93) and tuple(o[:, 0]) == (f.lo[6], f.R0, f.D0)
     assert np.all(np.diff(o[1]) >= 0) and np.all(np.diff(o[2]) >= 0)
-    ww = synth.windows()
-    assert len(ww.fits) == 139  # floor(1 + (449 - 35)/3)
-    for i, g in enumerate(ww.fits[::23]):
-        assert g.W == 35 and g.lo[6] == g.hi[6] and g.hi[2] == g.hi[3] == 28.0
-    assert [g.stream for g in ww.fits] == list(range(139))
     r = synth.rep(n_rep=3)
     assert all(np.array_equal(g.obs3, r.fits[0].obs3) for g in r.fits)
     assert [g.stream for g in r.fits] == [0, 1, 2]
-
-
-def test_window_construction_matches_the_paper():
-    """The paper's own numbers for the window-wise calibration (Sec. 3.1),
-    stored in tests/golden/windows_sec3_1.txt: 139 windows of tau + 1
-    observations every delta days over T + 1 days, and the narrowed box."""
-    import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "windows_sec3_1.txt")
-    g = {}
-    for line in open(path):
-        if line.strip() and not line.startswith("#"):
-            k, v = line.split()
-            g[k] = float(v)
-    T, tau, delta = int(g["T"]), int(g["tau"]), int(g["delta"])
-    assert (1 + (T - tau) // delta) == int(g["windows"])
-    wl = synth.windows(n_part=1, tau=tau, delta=delta)
-    assert len(wl.fits) == int(g["windows"])
-    obs = synth._load("windows")["obs"]
-    assert obs.shape[1] - 1 == T
-    for i, f in enumerate(wl.fits):
-        assert f.W == tau and f.model == "euler_ramp"
-        np.testing.assert_array_equal(f.obs3.reshape(3, tau + 1),
-                                      obs[:, delta * i:delta * i + tau + 1])
-        assert f.hi[0] == f.hi[1] == g["beta_hi"] and f.hi[4] == g["gamma_hi"]
-        assert f.hi[5] == g["mu_hi"] and f.hi[2] == f.hi[3] == g["t_hi"]
-        assert np.all(f.lo[:6] == 0.0)
-    assert delta * (len(wl.fits) - 1) + tau == T  # the last window ends on day T
 
 
 def test_paper_timing_case_matches_the_paper_setup():
