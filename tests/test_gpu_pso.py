@@ -8,12 +8,10 @@ import torch
 import oracle
 import synth
 import paper_2204_12346_amd as S
-from gpu_helpers import (TOL64, assert_loss_close, kappa, make_batch, need_gpu,
-                         oracle_problem)
+from gpu_helpers import (TOL64, assert_loss_close, compared_iterations, kappa,
+                         loss_discrepancy, make_batch, need_gpu, oracle_problem)
 
 pytestmark = pytest.mark.gpu
-
-NEAR_TIE = 1e-9  # relative margin below which a swarm decision is a near-tie
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -92,8 +90,14 @@ def test_step_lockstep_bitwise(regions, n_parts):
     assert np.all(np.isfinite(hf[:6])) and np.all(np.isnan(hf[6:]))
 
 
-def _run_compare(wl, fits, n_parts, iters, kind="ssre"):
-    b = make_batch(fits, n_parts)
+def _run_compare(wl, fits, n_parts, iters, kind="ssre", launch=None, min_compared=None,
+                 pool=False):
+    """The whole swarm run on the GPU (fused iterations) against the
+    oracle's, problem by problem: gbest indices equal and gbest losses
+    within 1e-11 up to the first near-tie of the oracle's run.  pool: run
+    the problems' oracles side by side on one thread each."""
+    from concurrent.futures import ThreadPoolExecutor
+    b = make_batch(fits, n_parts, **(launch or {}))
     params = S.PsoParams(b, [f.lo for f in fits], [f.hi for f in fits], wl.w, wl.c1, wl.c2,
                          wl.seed)
     sw = S.Swarm(b, hist_len=iters)
@@ -103,16 +107,37 @@ def _run_compare(wl, fits, n_parts, iters, kind="ssre"):
     torch.cuda.synchronize()
     gh_f = sw.hist_f.cpu().numpy()
     gh_i = sw.hist_idx.cpu().numpy()
+    pbx = b.unpack_theta(sw.pbest_x)
+    pbf = b.split_particles(sw.pbest_f)
+    nt = 1 if pool else 0
+
+    def oracle_side(r):
+        f = fits[r]
+        prob = oracle_problem(f)
+        run = oracle.pso_run(prob, f.y, kind, n_parts[r], f.lo, f.hi, wl.w, wl.c1, wl.c2,
+                             wl.seed, f.stream, iters, nthreads=nt)
+        at_pbest = oracle.loss_batch(prob, pbx[r], f.y, kind, nthreads=nt)
+        return run, at_pbest
+
+    if pool:
+        with ThreadPoolExecutor(16) as ex:
+            res = list(ex.map(oracle_side, range(len(fits))))
+    else:
+        res = [oracle_side(r) for r in range(len(fits))]
+    delta = max(loss_discrepancy(pbf[r], res[r][1]) for r in range(len(fits)))
+    assert delta < 1e-11, f"personal-best losses off the oracle's by {delta:.2e}"
+    need = min(iters, 20) if min_compared is None else min_compared
+    shortest = iters
     for r, f in enumerate(fits):
-        hf, hidx, hm, _ = oracle.pso_run(oracle_problem(f), f.y, kind, n_parts[r], f.lo, f.hi,
-                                         wl.w, wl.c1, wl.c2, wl.seed, f.stream, iters,
-                                         nthreads=8)
-        tie = np.nonzero(hm < NEAR_TIE)[0]
-        upto = int(tie[0]) if len(tie) else iters
-        print(f"problem {r}: comparing {upto} of {iters} iterations", flush=True)
-        assert upto >= min(iters, 20), f"oracle near-tie too early ({upto})"
-        np.testing.assert_array_equal(gh_i[:upto, r], hidx[:upto])
-        np.testing.assert_allclose(gh_f[:upto, r], hf[:upto], rtol=1e-11, atol=0)
+        hf, hidx, hm, _ = res[r][0]
+        upto, thr = compared_iterations(hm, delta, iters)
+        shortest = min(shortest, upto)
+        assert upto >= need, f"problem {r}: oracle near-tie too early ({upto})"
+        np.testing.assert_array_equal(gh_i[:upto, r], hidx[:upto], err_msg=f"problem {r}")
+        np.testing.assert_allclose(gh_f[:upto, r], hf[:upto], rtol=1e-11, atol=0,
+                                   err_msg=f"problem {r}")
+    print(f"{len(fits)} problems: loss discrepancy {delta:.2e}, near-tie threshold {thr:.1e}, "
+          f"at least {shortest} of {iters} iterations compared", flush=True)
     return b, sw
 
 
@@ -121,14 +146,24 @@ def test_full_run_constant_beta_workload():
     _run_compare(wl, wl.fits, [256], wl.iters)
 
 
-def test_run_segmented_beta_workload_reduced():
+def test_run_segmented_beta_workload_full_population():
+    """8192 particles, 13 segments, 180 days: 150 iterations."""
     wl = synth.c2()
-    _run_compare(wl, wl.fits, [1024], 25)
+    _run_compare(wl, wl.fits, [wl.fits[0].n_part], 150, min_compared=100)
 
 
-def test_run_batched_uneven_workload_reduced():
+def test_run_batched_uneven_workload_ragged_populations():
     wl = synth.c3(regions=list(range(12)))
     _run_compare(wl, wl.fits, [64 + 37 * r for r in range(12)], 15)
+
+
+def test_run_batched_uneven_workload_full():
+    """All 512 regions x 1024 particles in the benchmark's launch shape,
+    10 iterations, every region against its own oracle run."""
+    from bench import C3_LAUNCH
+    wl = synth.c3()
+    _run_compare(wl, wl.fits, [f.n_part for f in wl.fits], 10, launch=C3_LAUNCH,
+                 min_compared=10, pool=True)
 
 
 @pytest.mark.parametrize("launch", [dict(), dict(block=256, persistent=0, waves_per_simd=4)])
