@@ -365,6 +365,28 @@ int sird_loss_backward(const sird_batch *batch, const double *theta, const doubl
 /* Workspace bytes needed by sird_loss_backward (0 on a bad batch). */
 size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval);
 
+/* Bytes of the device scratch behind sird_loss_backward_static (32 MiB per
+ * GPU the library runs on, held until the process ends). */
+#define SIRD_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * self-contained sird_loss_backward (from_forward = 0) with its workspace in
+ * a library-owned static device array of SIRD_STATIC_SCRATCH_BYTES, one per
+ * GPU.  Same arguments, meaning and result (bitwise) as sird_loss_backward
+ * without workspace, ws_bytes and from_forward; the caller still owns theta,
+ * obs, grad_loss, grad_theta and loss_out.  The call allocates nothing; its
+ * first call on a device, made with that device current, looks up that
+ * device's array.  Every call on one GPU shares that GPU's array (its
+ * contents on entry are not read), so calls that overlap on one GPU race:
+ * order them on one stream.
+ * Errors: as sird_loss_backward; SIRD_ENOSPACE when
+ * sird_loss_backward_workspace(batch, ckpt_interval) exceeds
+ * SIRD_STATIC_SCRATCH_BYTES (nothing is enqueued). */
+int sird_loss_backward_static(const sird_batch *batch, const double *theta, const double *obs,
+                              int loss_kind, const double *grad_loss, double *grad_theta,
+                              double *loss_out, int ckpt_interval, void *stream);
+
 /* Indices (local to each problem) of the k particles with the smallest
  * pbest_f, ordered by (pbest_f, index), NaN last.  idx_out: device [n_prob][k];
  * problems with fewer than k particles pad with -1.  Up to k = 32 the

@@ -11,11 +11,12 @@ from .core import (Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm,
                    pso_complete_move, sird_lbfgs_accept, sird_lbfgs_propose,
                    pso_evaluate, pso_gbest, pso_init, pso_step, pso_topk, sird_adam_step,
                    sird_gather, sird_integrate, sird_loss, sird_loss_backward,
-                   sird_loss_backward_workspace, sird_pso_iterate)
+                   sird_loss_backward_static, sird_loss_backward_workspace, sird_pso_iterate)
 
 __all__ = [
     "Batch", "Graph", "LbfgsState", "ProblemSpec", "PsoParams", "Swarm", "LOSS", "SirdError",
     "pso_complete_move", "pso_evaluate", "pso_gbest", "pso_init", "pso_step", "pso_topk",
     "sird_adam_step", "sird_gather", "sird_integrate", "sird_lbfgs_accept",
-    "sird_lbfgs_propose", "sird_loss", "sird_loss_backward", "sird_loss_backward_workspace", "sird_pso_iterate",
+    "sird_lbfgs_propose", "sird_loss", "sird_loss_backward", "sird_loss_backward_static",
+    "sird_loss_backward_workspace", "sird_pso_iterate",
 ]

@@ -108,6 +108,7 @@ SIGNATURES = {
     "pso_complete_move": (_I, [_B, _PP, _PS, _P]),
     "sird_loss_backward": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),
     "sird_loss_backward_workspace": (ctypes.c_size_t, [_B, _I]),
+    "sird_loss_backward_static": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _P]),
     "pso_topk": (_I, [_B, _P, _I, _P, _P]),
     "sird_gather": (_I, [_B, _P, _P, _B, _P, _P, _I, _P]),
     "sird_adam_step": (_I, [_B, _P, _P, _P, _P, _P, _P, _I64,

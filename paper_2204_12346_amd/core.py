@@ -396,6 +396,29 @@ def sird_loss_backward(batch: Batch, theta, obs, kind="ssre", grad_loss=None,
     return grad_theta, loss_out
 
 
+# Bytes of the static device scratch behind sird_loss_backward_static.
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def sird_loss_backward_static(batch: Batch, theta, obs, kind="ssre", grad_loss=None,
+                              grad_theta=None, loss_out=None, ckpt_interval=0, stream=None):
+    """sird_loss_backward with the library's static per-GPU workspace: the
+    C call allocates nothing (pass grad_theta, and loss_out if wanted, to
+    allocate nothing here either).  Returns (grad_theta, loss_out)."""
+    if grad_theta is None:
+        grad_theta = batch.empty_theta()
+    a = Args(batch)
+    args = (a(theta, batch.theta_len, "theta"), a(obs, batch.obs_len, "obs"), _kind(kind),
+            a(grad_loss, batch.total_particles, "grad_loss", optional=True),
+            a(grad_theta, batch.theta_len, "grad_theta"),
+            a(loss_out, batch.total_particles, "loss_out", optional=True))
+    a.device()
+    check(lib().sird_loss_backward_static(ctypes.byref(batch.c), *args, int(ckpt_interval),
+                                          stream_handle(stream)),
+          "sird_loss_backward_static")
+    return grad_theta, loss_out
+
+
 def pso_topk(batch: Batch, pbest_f, k, idx_out=None, stream=None):
     if idx_out is None:
         idx_out = torch.empty((batch.n_prob, k), dtype=torch.int64, device=batch.device)

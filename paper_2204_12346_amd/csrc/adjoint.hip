@@ -41,6 +41,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -165,6 +166,8 @@ constexpr int kChunk = 8;
 // start falls on a chunk start, so a chunk's steps are replayed and
 // reversed with no test between them.
 constexpr int kAlign = 10;
+// Threads per block of k_backward (four wavefronts).
+constexpr int kBwdBlock = 256;
 
 __device__ __forceinline__ int seg_of(int n, int SS, int K)
 {
@@ -173,7 +176,7 @@ __device__ __forceinline__ int seg_of(int n, int SS, int K)
 }
 
 template <int KIND, int MODE>
-__global__ void __launch_bounds__(256) k_backward(BwdArgs a)
+__global__ void __launch_bounds__(kBwdBlock) k_backward(BwdArgs a)
 {
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
@@ -683,15 +686,17 @@ size_t adjoint_workspace_bytes(const sird_batch *b, int ckpt_interval)
            sizeof(double);
 }
 
-int adjoint_enqueue(const sird_batch *batch, const double *theta, const double *obs,
-                    int loss_kind, const double *grad_loss, double *grad_theta,
-                    double *loss_out, int ckpt_interval, int mode, void *workspace,
-                    size_t ws_bytes, hipStream_t stream, const char *who)
+// Host checks of a gradient call that do not concern the workspace; fills
+// every field of *a but ws, and the launch shape.
+static int adjoint_prepare(const sird_batch *batch, const double *theta, const double *obs,
+                           int loss_kind, const double *grad_loss, double *grad_theta,
+                           double *loss_out, int ckpt_interval, int mode, BwdArgs *a,
+                           int *grid, size_t *lds, const char *who)
 {
     const std::string w(who);
     int st = check_batch(batch, who);
     if (st) return st;
-    if (!theta || !obs || !workspace) return fail(SIRD_EINVAL, w + ": NULL array");
+    if (!theta || !obs) return fail(SIRD_EINVAL, w + ": NULL array");
     if (mode != kFwdOnly && !grad_theta) return fail(SIRD_EINVAL, w + ": grad_theta is NULL");
     if (mode == kFwdOnly && !loss_out) return fail(SIRD_EINVAL, w + ": loss is NULL");
     if (batch->dtype != SIRD_F64)
@@ -702,39 +707,60 @@ int adjoint_enqueue(const sird_batch *batch, const double *theta, const double *
         return fail(SIRD_EINVAL, w + ": the adjoint supports the RK4 segment model only");
     if (ckpt_interval < 0) return fail(SIRD_EINVAL, w + ": ckpt_interval < 0");
     if (batch->obs_len < 1) return fail(SIRD_EINVAL, w + ": batch planned without obs");
-    if (((uintptr_t)workspace & 255) != 0)
-        return fail(SIRD_EINVAL, w + ": workspace not 256-byte aligned");
     const int s = resolve_interval(batch, ckpt_interval);
-    if (ws_bytes < adjoint_workspace_bytes(batch, ckpt_interval))
-        return fail(SIRD_ENOSPACE, w + ": workspace too small");
-    BwdArgs a{};
-    a.probs = batch->probs;
-    a.tiles = batch->tiles;
-    a.theta = theta;
-    a.obs = obs;
-    a.grad_loss = grad_loss;
-    a.grad = grad_theta;
-    a.loss_out = loss_out;
-    a.ws = (double *)workspace;
-    a.P = batch->total_particles;
-    a.n_tiles = batch->n_tiles;
-    a.obs_series = batch->obs_series;
-    a.s = s;
-    a.n_ck_max = (int)((batch->max_steps + s - 1) / s);
-    a.max_days = batch->max_days;
-    a.lds_stride = 2 * (batch->max_days + 1);
-    const int block = 256;
-    const size_t lds = (size_t)(block / kWave) * a.lds_stride * sizeof(double);
-    if (lds > 65536) return fail(SIRD_EINVAL, w + ": window too long for LDS");
-    const int grid = tile_blocks(batch->n_tiles);
+    *a = BwdArgs{};
+    a->probs = batch->probs;
+    a->tiles = batch->tiles;
+    a->theta = theta;
+    a->obs = obs;
+    a->grad_loss = grad_loss;
+    a->grad = grad_theta;
+    a->loss_out = loss_out;
+    a->P = batch->total_particles;
+    a->n_tiles = batch->n_tiles;
+    a->obs_series = batch->obs_series;
+    a->s = s;
+    a->n_ck_max = (int)((batch->max_steps + s - 1) / s);
+    a->max_days = batch->max_days;
+    a->lds_stride = 2 * (batch->max_days + 1);
+    *lds = (size_t)(kBwdBlock / kWave) * a->lds_stride * sizeof(double);
+    if (*lds > 65536) return fail(SIRD_EINVAL, w + ": window too long for LDS");
+    *grid = tile_blocks(batch->n_tiles);
+    return SIRD_OK;
+}
+
+static int adjoint_launch(int mode, int loss_kind, int grid, size_t lds, hipStream_t stream,
+                          const BwdArgs &a, const char *who)
+{
     if (grid == 0) return SIRD_OK;
     if (mode == kFwdOnly)
-        launch_backward<kFwdOnly>(loss_kind, grid, block, lds, stream, a);
+        launch_backward<kFwdOnly>(loss_kind, grid, kBwdBlock, lds, stream, a);
     else if (mode == kRevOnly)
-        launch_backward<kRevOnly>(loss_kind, grid, block, lds, stream, a);
+        launch_backward<kRevOnly>(loss_kind, grid, kBwdBlock, lds, stream, a);
     else
-        launch_backward<kBoth>(loss_kind, grid, block, lds, stream, a);
+        launch_backward<kBoth>(loss_kind, grid, kBwdBlock, lds, stream, a);
     return hip_status(hipGetLastError(), who);
+}
+
+int adjoint_enqueue(const sird_batch *batch, const double *theta, const double *obs,
+                    int loss_kind, const double *grad_loss, double *grad_theta,
+                    double *loss_out, int ckpt_interval, int mode, void *workspace,
+                    size_t ws_bytes, hipStream_t stream, const char *who)
+{
+    const std::string w(who);
+    BwdArgs a;
+    int grid = 0;
+    size_t lds = 0;
+    int st = adjoint_prepare(batch, theta, obs, loss_kind, grad_loss, grad_theta, loss_out,
+                             ckpt_interval, mode, &a, &grid, &lds, who);
+    if (st) return st;
+    if (!workspace) return fail(SIRD_EINVAL, w + ": NULL array");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(SIRD_EINVAL, w + ": workspace not 256-byte aligned");
+    if (ws_bytes < adjoint_workspace_bytes(batch, ckpt_interval))
+        return fail(SIRD_ENOSPACE, w + ": workspace too small");
+    a.ws = (double *)workspace;
+    return adjoint_launch(mode, loss_kind, grid, lds, stream, a, who);
 }
 
 }  // namespace sird
@@ -759,4 +785,68 @@ extern "C" int sird_loss_backward(const sird_batch *batch, const double *theta,
     return adjoint_enqueue(batch, theta, obs, loss_kind, grad_loss, grad_theta, loss_out,
                            ckpt_interval, from_forward ? kRevOnly : kBoth, workspace, ws_bytes,
                            (hipStream_t)stream, "sird_loss_backward");
+}
+
+// ------------------------------------------------ allocation-free gradient
+// Workspace of sird_loss_backward_static: one array per GPU, placed by the
+// loader with the code object and held until the process ends.  Host code
+// never passes its name to a kernel (on the host the name is a stand-in,
+// not a device address): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SIRD_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch (set up on the first call made
+// with that device current), or a negative status.
+int static_scratch(void **out, const char *who)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, who);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SIRD_EINVAL, std::string(who) + ": device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SIRD_EHIP, std::string(who) + ": hipGetSymbolAddress(scratch): " +
+                                       hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SIRD_OK;
+}
+
+}  // namespace
+
+extern "C" int sird_loss_backward_static(const sird_batch *batch, const double *theta,
+                                         const double *obs, int loss_kind,
+                                         const double *grad_loss, double *grad_theta,
+                                         double *loss_out, int ckpt_interval, void *stream)
+{
+    const char *who = "sird_loss_backward_static";
+    BwdArgs a;
+    int grid = 0;
+    size_t lds = 0;
+    int st = adjoint_prepare(batch, theta, obs, loss_kind, grad_loss, grad_theta, loss_out,
+                             ckpt_interval, kBoth, &a, &grid, &lds, who);
+    if (st) return st;
+    const size_t need = adjoint_workspace_bytes(batch, ckpt_interval);
+    if (need > (size_t)SIRD_STATIC_SCRATCH_BYTES)
+        return fail(SIRD_ENOSPACE,
+                    std::string(who) + ": the batch needs " + std::to_string(need) +
+                        " bytes of workspace, above the static scratch of " +
+                        std::to_string((size_t)SIRD_STATIC_SCRATCH_BYTES) +
+                        "; use sird_loss_backward with a workspace");
+    void *ws = nullptr;
+    st = static_scratch(&ws, who);
+    if (st) return st;
+    a.ws = (double *)ws;
+    return adjoint_launch(kBoth, loss_kind, grid, lds, (hipStream_t)stream, a, who);
 }

@@ -33,7 +33,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("sird_integrate", "sird_loss", "pso_step", "sird_loss_backward"):
         assert required in names
-    assert len(names) == 23, names
+    assert len(names) == 24, names
 
 
 def test_library_exports_every_declared_symbol(L):
@@ -282,3 +282,33 @@ def test_loss_with_checkpoint_workspace_checks_on_host(L):
     assert lib.sird_loss_backward(ctypes.byref(b.c), d, d, 0, None, d, None, 10, 2, big,
                                   1 << 40, None) == L.SIRD_EINVAL
     assert b"from_forward" in lib.sird_last_error()
+
+
+def test_static_gradient_entry_checks_on_host(L):
+    """sird_loss_backward_static: argument checks and the scratch limit are
+    reported before any HIP call (so they run without a GPU)."""
+    import torch
+    from paper_2204_12346_amd import core
+    text = open(HEADER).read()
+    m = re.search(r"#define SIRD_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == core.STATIC_SCRATCH_BYTES
+    lib = L.lib()
+    d = torch.zeros(8, dtype=torch.float64).data_ptr()
+    assert lib.sird_loss_backward_static(None, d, d, 0, None, d, None, 0, None) == L.SIRD_EINVAL
+    # 65536 vectors over 7300 steps need about 180 MiB of workspace
+    big = core.Batch([core.ProblemSpec(365, 20, 14, 13, 3.8e7, n_part=65536)], device="cpu")
+    need = lib.sird_loss_backward_workspace(ctypes.byref(big.c), 0)
+    assert need > core.STATIC_SCRATCH_BYTES
+    assert lib.sird_loss_backward_static(ctypes.byref(big.c), d, d, 0, None, d, None, 0,
+                                         None) == L.SIRD_ENOSPACE
+    assert b"static scratch" in lib.sird_last_error()
+    small = core.Batch([core.ProblemSpec(30, 10, 14, 3, 1e6, n_part=100)], device="cpu")
+    for args, what in (((d, d, 5, None, d, None, 0), b"deceased-count"),
+                       ((d, d, 0, None, None, None, 0), b"grad_theta"),
+                       ((None, d, 0, None, d, None, 0), b"NULL"),
+                       ((d, d, 0, None, d, None, -1), b"ckpt_interval")):
+        assert lib.sird_loss_backward_static(ctypes.byref(small.c), *args, None) == L.SIRD_EINVAL
+        assert what in lib.sird_last_error()
+    small.c.dtype = L.SIRD_F32
+    assert lib.sird_loss_backward_static(ctypes.byref(small.c), d, d, 0, None, d, None, 0,
+                                         None) == L.SIRD_EINVAL
