@@ -338,10 +338,14 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
  *   grad_loss: optional particle-indexed upstream gradient (NULL = 1).
  *   grad_theta: output, theta-shaped: grad_loss[p] * dL/dtheta.
  *   loss_out: optional particle-indexed output of the loss itself.
- *   ckpt_interval: steps between checkpoints, 0 = ceil(sqrt(max_steps))
- *       rounded up to a multiple of 10.  Problems whose steps per day and
- *       interval are both multiples of 10 are reversed 10 steps at a time
- *       with no per-step tests (faster; the same result).
+ *   ckpt_interval: steps between checkpoints.  The reverse sweep replays
+ *       an interval from its checkpoint into the wavefront's LDS slice,
+ *       which holds lc steps (40 KiB per wavefront less the observations
+ *       and the lane's betas; 8 <= lc <= 64), and walks it backwards; a
+ *       longer interval is split into lc-step pieces whose start states go
+ *       to the workspace first.  0 = per problem, the whole days that fit
+ *       lc steps (lc steps when one day is longer), so that every interval
+ *       is replayed once and its checkpoints fall on day starts.
  *   from_forward: 0 = run the forward pass here (contents of the workspace
  *       on entry are ignored); 1 = the workspace holds the forward pass of
  *       a sird_loss call with a workspace on the same batch, theta, obs,
@@ -365,9 +369,9 @@ int sird_loss_backward(const sird_batch *batch, const double *theta, const doubl
 /* Workspace bytes needed by sird_loss_backward (0 on a bad batch). */
 size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval);
 
-/* Bytes of the device scratch behind sird_loss_backward_static (32 MiB per
+/* Bytes of the device scratch behind sird_loss_backward_static (64 MiB per
  * GPU the library runs on, held until the process ends). */
-#define SIRD_STATIC_SCRATCH_BYTES (32u << 20)
+#define SIRD_STATIC_SCRATCH_BYTES (64u << 20)
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

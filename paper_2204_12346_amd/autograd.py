@@ -9,36 +9,22 @@ import torch
 
 from .core import Batch, sird_loss, sird_loss_backward, sird_loss_backward_workspace
 
-# Checkpoint interval of the autograd path when its workspace fits the
-# budget: 10 steps is one replay chunk of the reverse sweep, so no interval
-# has to be replayed before it is reversed.
-SHORT_INTERVAL = 10
-WORKSPACE_BUDGET = 4 << 30
-
-
-def autograd_interval(batch: Batch, budget_bytes=WORKSPACE_BUDGET) -> int:
-    """10 when the workspace of 10-step checkpoints fits budget_bytes, else
-    0 (ceil(sqrt(T)) rounded up to a multiple of 10)."""
-    if sird_loss_backward_workspace(batch, SHORT_INTERVAL) <= budget_bytes:
-        return SHORT_INTERVAL
-    return 0
-
-
 class SirdLoss(torch.autograd.Function):
     """loss = SirdLoss.apply(theta, batch, obs, kind, ckpt_interval)
 
     theta: theta-shaped float64 device tensor of the batch (requires_grad).
     Returns the particle-indexed losses.  backward() gives
     grad_theta = upstream_grad[p] * dL_p/dtheta in the theta layout.
-    ckpt_interval None picks autograd_interval(batch).  The workspace holding
-    the forward pass lives until the graph is freed.
+    ckpt_interval None (or 0) takes the library's default: per problem the
+    whole days whose states fit the reverse sweep's LDS slice.  The workspace
+    holding the forward pass lives until the graph is freed.
     """
 
     @staticmethod
     def forward(ctx, theta, batch: Batch, obs, kind="ssre", ckpt_interval=None):
         if theta.dtype != torch.float64:
             raise TypeError(f"SirdLoss: theta must be float64, got {theta.dtype}")
-        ci = autograd_interval(batch) if ckpt_interval is None else int(ckpt_interval)
+        ci = 0 if ckpt_interval is None else int(ckpt_interval)
         theta_c = theta.detach().contiguous()
         ws = torch.empty(max(sird_loss_backward_workspace(batch, ci), 8), dtype=torch.uint8,
                          device=batch.device)

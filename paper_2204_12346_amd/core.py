@@ -397,7 +397,7 @@ def sird_loss_backward(batch: Batch, theta, obs, kind="ssre", grad_loss=None,
 
 
 # Bytes of the static device scratch behind sird_loss_backward_static.
-STATIC_SCRATCH_BYTES = 32 << 20
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def sird_loss_backward_static(batch: Batch, theta, obs, kind="ssre", grad_loss=None,

@@ -1,36 +1,44 @@
 // Gradient of the deceased-count cost with respect to theta by the discrete
 // adjoint of the RK4 scheme (reverse mode through every stage of every step).
 //
-// Per particle (one lane, one tile per wavefront):
-//   1. forward pass: RK4 over the window, the cost, Dhat_i of every day and
-//      the state (S, I, and the stages' scaled susceptible) every s steps
-//      (checkpoints) -> workspace;
+// One particle per lane, one tile (64 particles of one problem) per
+// wavefront, one wavefront per block:
+//   1. forward pass: the loss kernel's integration (state s = b S, I, D; S
+//      formed where beta changes), the cost, Dhat of every day, the
+//      susceptible at every segment start and the state (s, I, S) every
+//      `s` steps (checkpoints) -> workspace;
 //   2. reverse sweep over the checkpoint intervals, last to first: replay
-//      the interval from its checkpoint, keeping the state before every 8th
-//      step in the workspace; then, chunk by chunk from the end, replay 8
-//      steps into registers and walk them backwards.  For step n with stages
-//      Y1 = y, Y2 = y + h/2 k1, Y3 = y + h/2 k2, Y4 = y + h k3 and adjoint
-//      abar of y_{n+1}:
-//        kbar4 = h/6 abar,           Ybar4 = J(Y4)^T kbar4
-//        kbar3 = h/3 abar + h Ybar4,   Ybar3 = J(Y3)^T kbar3
-//        kbar2 = h/3 abar + h/2 Ybar3, Ybar2 = J(Y2)^T kbar2
-//        kbar1 = h/6 abar + h/2 Ybar2, Ybar1 = J(y)^T kbar1
-//        a_n = abar + Ybar1 + Ybar2 + Ybar3 + Ybar4
-//        thetabar += sum_s (df/dtheta)(Y_s)^T kbar_s
-//      and the cost's dl/dDhat_i is added to a_D at n = i * spd.
+//      the interval from its checkpoint with exactly the forward pass's
+//      operations, writing the state (s, I) before every step to the
+//      wavefront's LDS slice, then walk the steps backwards, recomputing each
+//      step's stages from its LDS state.  An interval longer than the LDS
+//      slice holds is split into sub-intervals whose start states a first
+//      replay stores in the workspace.
+// For step n with stages Y1 = y, Y2 = y + h/2 k1, Y3 = y + h/2 k2,
+// Y4 = y + h k3 and adjoint abar of y_{n+1}:
+//   kbar4 = h/6 abar,             Ybar4 = J(Y4)^T kbar4
+//   kbar3 = h/3 abar + h Ybar4,   Ybar3 = J(Y3)^T kbar3
+//   kbar2 = h/3 abar + h/2 Ybar3, Ybar2 = J(Y2)^T kbar2
+//   kbar1 = h/6 abar + h/2 Ybar2, Ybar1 = J(y)^T kbar1
+//   a_n = abar + Ybar1 + Ybar2 + Ybar3 + Ybar4
+//   thetabar += sum_s (df/dtheta)(Y_s)^T kbar_s
+// and the cost's dl/dDhat_i is added to a_D at n = i * spd.
 // State (S, I, D) (R never feeds back and no cost reads it): with
 // p = b S I, b = beta/N, f = (-p, p - lam I, mu I) and u = kI - kS,
 //   J^T k = (b I u,  b S u - lam kI + mu kD,  0),
 //   df/dbeta . k = (S I / N) u,  df/dgamma . k = -I kI,  df/dmu . k = I (kD - kI).
-// D never feeds back, so its adjoint is piecewise constant between samples
-// and kbar_s.D = w_s h a_D with the RK4 weights w = (1/6, 1/3, 1/3, 1/6).
+// The stages are recomputed in the forward's scaled form, s_s = b S_s, which
+// is the b S of J^T k; the beta sum is carried as sum s_s I_s u and divided
+// by b at the segment's end (with beta = 0, s = 0 and S stays at its value
+// S_k at the segment's start: there the sum is S_k sum I_s u).
+// D never feeds back, so its adjoint is piecewise constant between samples:
+// kbar_s.D = w_s h a_D with the RK4 weights w = (1/6, 1/3, 1/3, 1/6), and
+// the D part of the mu sum is h/6 a_D (I1 + 2 I2 + 2 I3 + I4) per step.
 // The initial state depends on I0 through S0 = N - I0 - R0 - D0 and I = I0.
 //
-// The forward pass here carries S next to s = b S (the form whose stages the
-// reverse sweep recomputes); it agrees with the loss kernel, which carries
-// s alone, to rounding.  Recomputation is deterministic (same operations
-// from the same stored state), so the gradient is bitwise independent of
-// the checkpoint interval.
+// Every replay repeats the forward pass's operations from a stored state,
+// so the gradient is bitwise independent of the checkpoint interval and of
+// the sub-interval length.
 //
 // The kernel runs in one of three modes: both passes (sird_loss_backward on
 // its own), the forward pass alone (sird_loss given a workspace: the loss,
@@ -40,10 +48,11 @@
 // the first mode, so the gradient is bitwise the same either way.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <mutex>
 #include <string>
-#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -59,17 +68,32 @@ struct BwdArgs {
     double *grad;
     double *loss_out;
     double *ws;
-    int64_t P;  // slot stride of the workspace (total particles)
+    int64_t P;       // slot stride of the workspace (total particles)
     int n_tiles;
     int obs_series;  // 1 or 3; the deceased counts are the last series
-    int s;          // checkpoint interval in steps
-    int n_ck_max;   // checkpoints per particle
-    int max_days;   // max W over problems (Dhat slots per particle - 1)
-    int lds_stride;
+    int s;           // checkpoint interval in steps; 0: per problem, the whole
+                     // days that fit an LDS sub-interval (lc steps; lc when
+                     // a day is longer)
+    int lc;          // steps of one LDS sub-interval
+    int n_ck_max;    // checkpoints per particle (3 slots each)
+    int n_sub_max;   // stored sub-interval starts per particle (3 slots each)
+    int max_days;    // max W over problems (Dhat slots per particle - 1)
+    int max_seg;     // max K over problems (segment-start slots)
+    int lds_wave;    // doubles of LDS per wavefront
 };
 
 // Modes of k_backward.
 enum BwdMode { kBoth = 0, kFwdOnly = 1, kRevOnly = 2 };
+
+// LDS a wavefront of k_backward may take so that four fit on a compute unit
+// (one per SIMD: 160 KiB of LDS per CU on gfx950).
+constexpr int kBwdLdsBudget = 40 * 1024;
+// Word 3 of a raw buffer resource on gfx9-family chips (gfx950 included):
+// untyped 32-bit data, no swizzle; the workspace loads use it.
+constexpr int kBufferWord3 = 0x00020000;
+// Bounds of the steps per LDS sub-interval.
+constexpr int kLcMin = 8;
+constexpr int kLcMax = 64;
 
 // dl/dDhat_i of the cost; imax is the day MXSE takes its maximum on.
 __device__ __forceinline__ double cost_grad(int kind, int i, int W, double D, double y,
@@ -88,86 +112,80 @@ __device__ __forceinline__ double cost_grad(int kind, int i, int W, double D, do
     }
 }
 
-struct Grad {
-    double beta;   // of the current segment, times N: sum of S_s I_s u over its stages
-    double gamma;
-    double mu;
+// Sums of the reverse sweep.
+struct RevSums {
+    double Gsv;   // sum over the current segment's stages of s_s I_s u
+    double Gv;    // sum over the current segment's stages of I_s u
+    double tI;    // sum over all stages of I_s kbar_s.I
+    double Jsum;  // sum of I1 + 2 I2 + 2 I3 + I4 since a_D last changed
 };
 
-// One stage of the reverse step: Ybar = J(Y_s)^T kbar and the parameter
-// contributions; mkD = mu * kbar_s.D.  Ybar.S = b v with v = I_s u is
-// returned as v: the next stage's kbar.S and the final sum take b in their
-// constants.
-__device__ __forceinline__ void stage_adjoint(double Ss, double Is, double bs, double kS,
-                                              double kI, double mkD, double lam, double &v,
-                                              double &YI, Grad &g, double &tI)
+// One stage of the reverse step: Ybar = J(Y_s)^T kbar; Ybar.S = b v with
+// v = I_s u is returned as v (the next stage's kbar.S and the final sum
+// take b in their constants); mkD = mu kbar_s.D.
+__device__ __forceinline__ void stage_adjoint(double ss, double Is, double kS, double kI,
+                                              double mkD, double lam, double &v, double &YI,
+                                              RevSums &g)
 {
     const double u = kI - kS;
     v = Is * u;
-    YI = fma(bs, u, fma(-lam, kI, mkD));
-    g.beta = fma(Ss, v, g.beta);
-    tI = fma(Is, kI, tI);
+    YI = fma(ss, u, fma(-lam, kI, mkD));
+    g.Gsv = fma(ss, v, g.Gsv);
+    g.tI = fma(Is, kI, g.tI);
 }
 
-// One reverse step: (aS, aI) <- a_n from a_{n+1}; aD unchanged.
-__device__ __forceinline__ void rk4_adjoint_step(double S, double I, double &aS, double &aI,
-                                                 double aD, const StepConst<double> &k,
-                                                 double mu, double h3, Grad &g)
-{
-    // recompute the stages
-    const double bs1 = k.b * S;
-    const double p1 = bs1 * I;
-    const double q1 = fma(-k.lam, I, p1);
-    const double S2 = fma(-k.h2, p1, S);
-    const double I2 = fma(k.h2, q1, I);
-    const double bs2 = k.b * S2;
-    const double p2 = bs2 * I2;
-    const double q2 = fma(-k.lam, I2, p2);
-    const double S3 = fma(-k.h2, p2, S);
-    const double I3 = fma(k.h2, q2, I);
-    const double bs3 = k.b * S3;
-    const double p3 = bs3 * I3;
-    const double q3 = fma(-k.lam, I3, p3);
-    const double S4 = fma(-k.h, p3, S);
-    const double I4 = fma(k.h, q3, I);
-    const double bs4 = k.b * S4;
+// The stages of one step from its start state (s, I), formed as the forward
+// step forms them.
+struct Stages {
+    double s, I, s2, I2, s3, I3, s4, I4;
+};
 
-    const double muaD = mu * aD;
-    const double m6 = k.h6 * muaD;  // mu kbar_s.D for s = 1, 4
-    const double m3 = h3 * muaD;    // mu kbar_s.D for s = 2, 3
-    double tI = 0.0;                 // sum_s I_s kbar_s.I
-    double v4, v3, v2, v1, Y4I, Y3I, Y2I, Y1I;
+__device__ __forceinline__ void stages(Stages &z, const StepConst<double> &k)
+{
+    const double p1 = z.s * z.I;
+    const double c1 = fma(-k.h2lam, z.I, z.I);
+    z.s2 = fma(-k.h2b, p1, z.s);
+    z.I2 = fma(k.h2, p1, c1);
+    const double p2 = z.s2 * z.I2;
+    const double c2 = fma(-k.h2lam, z.I2, z.I);
+    z.s3 = fma(-k.h2b, p2, z.s);
+    z.I3 = fma(k.h2, p2, c2);
+    const double p3 = z.s3 * z.I3;
+    const double c3 = fma(-k.hlam, z.I3, z.I);
+    z.s4 = fma(-k.hb, p3, z.s);
+    z.I4 = fma(k.h, p3, c3);
+}
+
+// One reverse step: (aS, aI) <- a_n from a_{n+1} through the step's stages;
+// a_D is constant here (m6 = h/6 mu a_D, m3 = h/3 mu a_D).
+__device__ __forceinline__ void rev_step(const Stages &z, double &aS, double &aI,
+                                         const StepConst<double> &k, double h3, double m6,
+                                         double m3, RevSums &g)
+{
+    double v4, v3, v2, v1, Y4, Y3, Y2, Y1;
     // stage 4: kbar4 = h/6 abar
     const double k4S = k.h6 * aS, k4I = k.h6 * aI;
-    stage_adjoint(S4, I4, bs4, k4S, k4I, m6, k.lam, v4, Y4I, g, tI);
+    stage_adjoint(z.s4, z.I4, k4S, k4I, m6, k.lam, v4, Y4, g);
     // stage 3: kbar3 = h/3 abar + h Ybar4
     const double h3S = h3 * aS, h3I = h3 * aI;
-    stage_adjoint(S3, I3, bs3, fma(k.hb, v4, h3S), fma(k.h, Y4I, h3I), m3, k.lam, v3, Y3I, g,
-                  tI);
+    stage_adjoint(z.s3, z.I3, fma(k.hb, v4, h3S), fma(k.h, Y4, h3I), m3, k.lam, v3, Y3, g);
     // stage 2: kbar2 = h/3 abar + h/2 Ybar3
-    stage_adjoint(S2, I2, bs2, fma(k.h2b, v3, h3S), fma(k.h2, Y3I, h3I), m3, k.lam, v2, Y2I, g,
-                  tI);
+    stage_adjoint(z.s2, z.I2, fma(k.h2b, v3, h3S), fma(k.h2, Y3, h3I), m3, k.lam, v2, Y2, g);
     // stage 1: kbar1 = h/6 abar + h/2 Ybar2
-    stage_adjoint(S, I, bs1, fma(k.h2b, v2, k4S), fma(k.h2, Y2I, k4I), m6, k.lam, v1, Y1I, g,
-                  tI);
+    stage_adjoint(z.s, z.I, fma(k.h2b, v2, k4S), fma(k.h2, Y2, k4I), m6, k.lam, v1, Y1, g);
 
-    // gamma: -sum I_s kbar_s.I;  mu: sum I_s (kbar_s.D - kbar_s.I)
-    const double J = fma(2.0, I2 + I3, I + I4);
-    g.gamma -= tI;
-    g.mu = fma(k.h6 * aD, J, g.mu - tI);
-    aS = fma(k.b, (v1 + v2) + (v3 + v4), aS);
-    aI = aI + ((Y1I + Y2I) + (Y3I + Y4I));
+    const double V = (v1 + v2) + (v3 + v4);
+    g.Gv += V;
+    aS = fma(k.b, V, aS);
+    aI = aI + ((Y1 + Y2) + (Y3 + Y4));
+    g.Jsum += fma(2.0, z.I2 + z.I3, z.I + z.I4);
 }
 
-// Steps replayed into registers at a time in the reverse sweep.
-constexpr int kChunk = 8;
-// Chunk length of the aligned sweep: when it divides both the steps per day
-// and the checkpoint interval, every day start, segment start and interval
-// start falls on a chunk start, so a chunk's steps are replayed and
-// reversed with no test between them.
-constexpr int kAlign = 10;
-// Threads per block of k_backward (four wavefronts).
-constexpr int kBwdBlock = 256;
+// dL/dbeta_k (before the upstream factor) from the segment's sums.
+__device__ __forceinline__ double beta_grad(const RevSums &g, double b, double Sk, double invN)
+{
+    return b != 0.0 ? (g.Gsv / b) * invN : (Sk * g.Gv) * invN;
+}
 
 __device__ __forceinline__ int seg_of(int n, int SS, int K)
 {
@@ -175,16 +193,64 @@ __device__ __forceinline__ int seg_of(int n, int SS, int K)
     return k > K - 1 ? K - 1 : k;
 }
 
+// First step of the segment after k, or INT_MAX when there is none inside
+// the window.
+__device__ __forceinline__ int next_seg_start(int k, int SS, int K, int T)
+{
+    const long n = (long)(k + 1) * SS;
+    return (k + 1 < K && n < T) ? (int)n : INT_MAX;
+}
+
+// A segment change before step st, as the loss kernel makes it: S = s/b
+// with the old beta (kept when beta = 0), the new beta, s = b S.
+__device__ __forceinline__ void change_segment(SirdState<double> &y, StepConst<double> &sf,
+                                               int &kf, int &next, const double *lb, int lane,
+                                               double invN, int SS, int K, int T)
+{
+    unscale(y, sf);
+    ++kf;
+    set_beta(sf, lb[kf * kWave + lane], invN);
+    rescale(y, sf);
+    next = next_seg_start(kf, SS, K, T);
+}
+
+// The forward pass's integration from step st to step end (segment changes
+// included), calling at() before the steps mark, mark + period, ... (it may
+// store the state); the steps between calls run with no per-step test.
+template <typename At>
+__device__ __forceinline__ void advance_marked(SirdState<double> &y, StepConst<double> &sf,
+                                               int &kf, int &next, int &st, int end, int &mark,
+                                               int period, const double *lb, int lane,
+                                               double invN, int SS, int K, int T, At at)
+{
+    while (st < end) {
+        if (st == next) change_segment(y, sf, kf, next, lb, lane, invN, SS, K, T);
+        if (st == mark) {
+            at();
+            mark += period;
+        }
+        const int stop = min(min(end, next), mark);
+#pragma unroll 2
+        for (; st < stop; ++st) rk4_step<double, false, false>(y, sf);
+    }
+}
+
 template <int KIND, int MODE>
-__global__ void __launch_bounds__(kBwdBlock) k_backward(BwdArgs a)
+__global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
 {
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
     const int t = wave_tile_index();
     if (t >= a.n_tiles) return;
-    double *ly = lds + (size_t)wave * a.lds_stride;
-    double *lw = ly + a.lds_stride / 2;
+    // LDS of the wavefront: the observations and weights, the lane's betas,
+    // and the states before the steps of one sub-interval
+    double *const ly = lds + (size_t)(threadIdx.x / kWave) * a.lds_wave;
+    double *const lw = ly + (a.max_days + 1);
+    double *const lb = lw + (a.max_days + 1);              // [max_seg][64]
+    // [2 + lc][2][64]: (s, I) of the lane before each step of a
+    // sub-interval, from row 2 on (rows 0 and 1 are slack that the walk's
+    // read-ahead may touch and never uses)
+    double *const lst = lb + (size_t)a.max_seg * kWave + 4 * kWave + lane;
 
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
@@ -199,13 +265,29 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(BwdArgs a)
     const size_t ld = (size_t)n;
     const double *th = a.theta + P.theta_off + pc;
     const size_t PS = (size_t)a.P;
-    // workspace of this particle: slot k at base[k * PS]
-    double *const ck_ws = a.ws + (size_t)(P.p_off + pc);    // checkpoint m: 3m .. 3m+2 (S, I, s)
-    double *const in_ws = ck_ws + (size_t)(3 * a.n_ck_max) * PS;  // chunk c: 3c .. 3c+2
-    double *const day_ws = in_ws + (size_t)(3 * ((a.s + kChunk - 1) / kChunk)) * PS;  // Dhat_i
-    // the forward pass's results the reverse sweep needs besides the
-    // checkpoints and Dhat: the day MXSE peaks on, and the loss
-    double *const tail_ws = day_ws + (size_t)(a.max_days + 1) * PS;
+    // Workspace: slot q of this lane's particle at wsb[q * PS] plus the
+    // lane's byte offset (a uniform base and an offset register that never
+    // changes, so a load in flight never holds an address register the
+    // next instructions want); idle lanes address their stand-in column.
+    //   checkpoint m: slots 3m..3m+2 (s, I, S); stored sub-interval start j:
+    //   q_sub + 3j..; Dhat_i: q_day + i; S at segment k's start: q_seg + k;
+    //   MXSE's day and the loss: q_tail, q_tail + 1
+    double *const wsb = a.ws + (size_t)(P.p_off + tl.p0);
+    const uint32_t loff = (uint32_t)(pc - tl.p0) * (uint32_t)sizeof(double);
+    auto slot = [&](size_t q) -> double & {
+        return *(double *)((char *)(wsb + q * PS) + loff);
+    };
+    // loads through a buffer resource on the slot's (uniform) base: the
+    // load's only address register is the lane offset
+    auto load = [&](size_t q) -> double {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(wsb + q * PS), (short)0, kWave * (int)sizeof(double), kBufferWord3);
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, loff, 0, 0));
+    };
+    const size_t q_sub = 3 * (size_t)a.n_ck_max;
+    const size_t q_day = q_sub + 3 * (size_t)a.n_sub_max;
+    const size_t q_seg = q_day + (size_t)(a.max_days + 1);
+    const size_t q_tail = q_seg + (size_t)a.max_seg;
 
     {
         // deceased counts: the last of the obs_series blocks of W+1 values
@@ -215,8 +297,15 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(BwdArgs a)
             ly[i] = yi;
             lw[i] = 1.0 / fmax(yi, 1.0);
         }
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) lb[k * kWave + lane] = th[(size_t)k * ld];
         wave_sync();
     }
+
+    // this problem's checkpoint interval; a whole number of days when days
+    // are the unit (the default, with a day no longer than lc steps)
+    const int dpc = (a.s == 0 && spd <= a.lc) ? a.lc / spd : 0;  // days per interval
+    const int sp = a.s > 0 ? a.s : (dpc > 0 ? dpc * spd : a.lc);
 
     const double gamma = th[(size_t)K * ld];
     const double mu = th[(size_t)(K + 1) * ld];
@@ -227,69 +316,78 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(BwdArgs a)
     StepConst<double> sc = step_const<double>(gamma, mu, spd);
 
     // ---------------------------------------------------- forward pass
-    // The S-carrying form of the forward kernel's step, day by day: a
-    // segment change and the rescale s = b S at the start of a day, the
-    // checkpoint (S, I, s) before every s-th step, the cost and Dhat at the
-    // end of a day.
     int imax = 0;
     if constexpr (MODE == kRevOnly) {
-        imax = active ? (int)tail_ws[0] : 0;
-        if (active && a.loss_out) a.loss_out[P.p_off + pl] = tail_ws[PS];
+        imax = (int)load(q_tail);
+        if (active && a.loss_out) a.loss_out[P.p_off + pl] = load(q_tail + 1);
     } else {
-    SirdState<double> y;
-    y.S = N - I0 - P.R0 - P.D0;
-    y.I = I0;
-    y.Rr = P.R0;
-    y.D = P.D0;
-    y.s = 0.0;
-    y.eS = y.eI = y.eR = y.eD = 0.0;
-    double acc = 0.0;
-    cost_accum(KIND, acc, y.D, ly[0], lw[0], 0);
-    if (active) day_ws[0] = y.D;
-    {
-        int kseg = 0;
-        set_beta(sc, th[0], invN);
+        SirdState<double> y;
+        y.S = N - I0 - P.R0 - P.D0;
+        y.I = I0;
+        y.Rr = P.R0;
+        y.D = P.D0;
+        y.s = 0.0;
+        y.eS = y.eI = y.eR = y.eD = 0.0;
+        double acc = 0.0;
+        cost_accum(KIND, acc, y.D, ly[0], lw[0], 0);
+        if (active) slot(q_day) = y.D;
+        int kf = 0;
+        set_beta(sc, lb[lane], invN);
+        rescale(y, sc);
+        if (active) slot(q_seg) = y.S;
+        int next = next_seg_start(0, SS, K, T);
         int st = 0, next_ck = 0;
-        double *cp = ck_ws;
-        double *dp = day_ws;
+        size_t cq = 0;
+        int kseen = 0;
         for (int day = 0; day < W; ++day) {
-            if (kseg < K - 1 && st == (kseg + 1) * SS) {
-                ++kseg;
-                set_beta(sc, th[(size_t)kseg * ld], invN);
-            }
-            rescale(y, sc);
-            for (int sd = 0; sd < spd;) {
+            // the day's observation, read before its steps
+            const double yo = ly[day + 1], wo = lw[day + 1];
+            if (dpc > 0) {
+                // checkpoints at day starts: the loss kernel's day loop
+                if (st == next) change_segment(y, sc, kf, next, lb, lane, invN, SS, K, T);
                 if (st == next_ck) {
                     if (active) {
-                        cp[0] = y.S;
-                        cp[PS] = y.I;
-                        cp[2 * PS] = y.s;
+                        slot(cq) = y.s;
+                        slot(cq + 1) = y.I;
+                        slot(cq + 2) = y.S;
                     }
-                    cp += 3 * PS;
-                    next_ck += a.s;
+                    cq += 3;
+                    next_ck += sp;
                 }
-                const int run = min(spd - sd, next_ck - st);
-#pragma unroll 2
-                for (int i = 0; i < run; ++i) rk4_step<double, false>(y, sc);
-                sd += run;
-                st += run;
+#pragma unroll 4
+                for (int i = 0; i < spd; ++i) rk4_step<double, false, false>(y, sc);
+                st += spd;
+            } else {
+                advance_marked(y, sc, kf, next, st, st + spd, next_ck, sp, lb, lane, invN, SS,
+                               K, T, [&]() {
+                                   if (active) {
+                                       slot(cq) = y.s;
+                                       slot(cq + 1) = y.I;
+                                       slot(cq + 2) = y.S;
+                                   }
+                                   cq += 3;
+                               });
+            }
+            if (kf != kseen) {
+                // a segment began with this day; S stays as the segment
+                // change formed it (the integration carries s alone)
+                if (active) slot(q_seg + kf) = y.S;
+                kseen = kf;
             }
             const double prev = acc;
-            cost_accum(KIND, acc, y.D, ly[day + 1], lw[day + 1], day + 1);
+            cost_accum(KIND, acc, y.D, yo, wo, day + 1);
             if (KIND == SIRD_LOSS_MXSE && !(acc == prev)) imax = day + 1;
-            dp += PS;
-            if (active) *dp = y.D;
+            if (active) slot(q_day + day + 1) = y.D;
         }
-    }
-    const double L = cost_finish(KIND, acc, W);
-    if (active && a.loss_out) a.loss_out[P.p_off + pl] = L;
-    if constexpr (MODE == kFwdOnly) {
-        if (active) {
-            tail_ws[0] = (double)imax;
-            tail_ws[PS] = L;
+        const double L = cost_finish(KIND, acc, W);
+        if (active && a.loss_out) a.loss_out[P.p_off + pl] = L;
+        if constexpr (MODE == kFwdOnly) {
+            if (active) {
+                slot(q_tail) = (double)imax;
+                slot(q_tail + 1) = L;
+            }
+            return;
         }
-        return;
-    }
     }
 
     // ---------------------------------------------------- reverse sweep
@@ -300,360 +398,220 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(BwdArgs a)
         if (active) gout[(size_t)k * ld] = 0.0;  // segments past the window end
 
     double aS = 0.0, aI = 0.0;
-    const double DW = active ? day_ws[(size_t)W * PS] : 0.0;
-    double aD = cost_grad(KIND, W, W, DW, ly[W], lw[W], imax);
-    Grad g{0.0, 0.0, 0.0};
+    double aD = cost_grad(KIND, W, W, load(q_day + W), ly[W], lw[W], imax);
+    double m6 = sc.h6 * (mu * aD), m3 = h3 * (mu * aD);
+    double muD = 0.0;  // sum over steps of h/6 a_D (I1 + 2 I2 + 2 I3 + I4)
+    RevSums g{0.0, 0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
-    set_beta(sc, th[(size_t)kr * ld], invN);
+    set_beta(sc, lb[kr * kWave + lane], invN);
     int seg_lo = kr * SS;  // first step of segment kr
+    double Sk = load(q_seg + kr);
+    // the next day start at or below the reverse position
+    int dnext = (T - 1) / spd;
 
-    const int n_ck = (T + a.s - 1) / a.s;
-    const bool aligned = spd % kAlign == 0 && a.s % kAlign == 0;
+    const int n_ck = (T + sp - 1) / sp;
     // the checkpoint of the interval to reverse next, loaded one interval
     // ahead
-    double cS, cI, cs_;
+    double cs_, cI, cS;
     {
-        const double *cp = ck_ws + (size_t)(3 * (n_ck - 1)) * PS;
-        cS = active ? cp[0] : 0.0;
-        cI = active ? cp[PS] : 0.0;
-        cs_ = active ? cp[2 * PS] : 0.0;
+        const size_t q = 3 * (size_t)(n_ck - 1);
+        cs_ = load(q);
+        cI = load(q + 1);
+        cS = load(q + 2);
     }
     for (int m = n_ck - 1; m >= 0; --m) {
-        const int n0 = m * a.s;
-        const int n1 = (n0 + a.s < T) ? n0 + a.s : T;
-        const double ckS = cS, ckI = cI, cks = cs_;
-        if (m > 0) {
-            const double *cp = ck_ws + (size_t)(3 * (m - 1)) * PS;
-            cS = active ? cp[0] : 0.0;
-            cI = active ? cp[PS] : 0.0;
-            cs_ = active ? cp[2 * PS] : 0.0;
-        }
-        if (aligned) {
-            // Aligned sweep: chunks of kAlign steps; the interval and every
-            // chunk are whole (T, s and the day are multiples of kAlign), a
-            // chunk lies in one segment and only its first step can start a
-            // day.  The operations are those of the general sweep below, in
-            // the same order, so the gradient is bitwise the same.
-            const int nc = (n1 - n0) / kAlign;
-            // pass 1: chunk start states 1 .. nc-2 to the workspace; the last
-            // chunk's stays in registers
-            double lastS = ckS, lastI = ckI, lasts = cks;
-            if (nc > 1) {
-                SirdState<double> yr;
-                yr.S = ckS;
-                yr.I = ckI;
-                yr.s = cks;
-                yr.Rr = yr.D = 0.0;
-                yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
-                int kf = seg_of(n0, SS, K);
+        const int n0 = m * sp;
+        const int n1 = (n0 + sp < T) ? n0 + sp : T;
+        SirdState<double> ck;
+        ck.s = cs_;
+        ck.I = cI;
+        ck.S = cS;
+        ck.Rr = ck.D = 0.0;
+        ck.eS = ck.eI = ck.eR = ck.eD = 0.0;
+        // One sub-interval [b0, b1) from its start state y: replayed into
+        // LDS, then walked backwards; prefetch: load the next interval's
+        // checkpoint between the two.
+        auto sub_interval = [&](int b0, int b1, SirdState<double> y, bool prefetch)
+                                __attribute__((always_inline)) {
+            // replay the sub-interval into LDS: (s, I) before every step
+            {
+                int kf = seg_of(b0, SS, K);
                 StepConst<double> sf = sc;
-                set_beta(sf, th[(size_t)kf * ld], invN);
-                double *ip = in_ws + 3 * PS;
-                for (int c = 0; c < nc - 1; ++c) {
-                    const int st = n0 + c * kAlign;
-                    if (st % spd == 0) {
-                        if (kf < K - 1 && st == (kf + 1) * SS) {
-                            ++kf;
-                            set_beta(sf, th[(size_t)kf * ld], invN);
-                        }
-                        rescale(yr, sf);
-                    }
-#pragma unroll
-                    for (int i = 0; i < kAlign; ++i) rk4_step<double, false>(yr, sf);
-                    if (c + 1 < nc - 1) {
-                        if (active) {
-                            ip[0] = yr.S;
-                            ip[PS] = yr.I;
-                            ip[2 * PS] = yr.s;
-                        }
-                        ip += 3 * PS;
+                set_beta(sf, lb[kf * kWave + lane], invN);
+                int next = next_seg_start(kf, SS, K, T);
+                // the first row outside the loop: whatever load the start
+                // state came from has landed before any loop below runs
+                lst[0] = y.s;
+                lst[kWave] = y.I;
+                rk4_step<double, false, false>(y, sf);
+                double *w = lst + 2 * kWave;
+                for (int st = b0 + 1; st < b1;) {
+                    if (st == next) change_segment(y, sf, kf, next, lb, lane, invN, SS, K, T);
+                    const int stop = min(b1, next);
+#pragma unroll 2
+                    for (; st < stop; ++st, w += 2 * kWave) {
+                        w[0] = y.s;
+                        w[kWave] = y.I;
+                        rk4_step<double, false, false>(y, sf);
                     }
                 }
-                lastS = yr.S;
-                lastI = yr.I;
-                lasts = yr.s;
             }
-            // pass 2: chunks last to first, the next one's start state and
-            // day-start Dhat loaded before the current one is walked
-            double nS, nI, ns, nD;
-            auto load_chunk = [&](int c) {
-                if (c == 0) {
-                    nS = ckS;
-                    nI = ckI;
-                    ns = cks;
-                } else if (c == nc - 1) {
-                    nS = lastS;
-                    nI = lastI;
-                    ns = lasts;
-                } else {
-                    const double *sp = in_ws + (size_t)(3 * c) * PS;
-                    nS = active ? sp[0] : 0.0;
-                    nI = active ? sp[PS] : 0.0;
-                    ns = active ? sp[2 * PS] : 0.0;
+            if (prefetch && m > 0) {
+                // the next interval's checkpoint, loaded while this one is
+                // walked (after the replay, whose first step waits for every
+                // load in flight)
+                const size_t q = 3 * (size_t)(m - 1);
+                cs_ = load(q);
+                cI = load(q + 1);
+                cS = load(q + 2);
+            }
+            // walk it backwards; day starts take the cost's gradient, and the
+            // first step of a segment closes that segment's beta sum.  Steps
+            // hi down to lo of one day are reversed with no event between
+            // them; the stages of the next step are formed before the
+            // current step's adjoint (the two chains overlap) and the LDS
+            // state of the step after that is read a step ahead.
+            int st = b1 - 1;
+            while (st >= b0) {
+                const int dstart = dnext * spd;
+                const int lo = dstart > b0 ? dstart : b0;
+                // a run that ends at a day start loads that day's Dhat before
+                // its steps and uses it after them (no load is left in flight
+                // into the next replay, whose first step would wait for it)
+                const double Dd = lo == dstart ? load(q_day + dnext) : 0.0;
+                // rows of steps st, st - 1, ...; the read-ahead of the last
+                // iterations reaches at most two rows below lo (the slack)
+                const double *r = lst + (st - b0) * (2 * kWave);
+                Stages cur;
+                cur.s = r[0];
+                cur.I = r[kWave];
+                double ps = r[-2 * kWave], pI = r[-kWave];
+                stages(cur, sc);
+#pragma unroll 2
+                for (; st > lo; --st) {
+                    Stages nxt;
+                    nxt.s = ps;
+                    nxt.I = pI;
+                    r -= 2 * kWave;
+                    ps = r[-2 * kWave];
+                    pI = r[-kWave];
+                    stages(nxt, sc);
+                    rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                    cur = nxt;
                 }
-                const int cs = n0 + c * kAlign;
-                nD = (active && cs % spd == 0) ? day_ws[(size_t)(cs / spd) * PS] : 0.0;
-            };
-            load_chunk(nc - 1);
-            for (int c = nc - 1; c >= 0; --c) {
-                const int cs = n0 + c * kAlign;
-                SirdState<double> yr;
-                yr.S = nS;
-                yr.I = nI;
-                yr.s = ns;
-                yr.Rr = yr.D = 0.0;
-                yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
-                const double Dd = nD;
-                if (c > 0) load_chunk(c - 1);
-                // the chunk is in the reverse's segment kr
-                const bool day_start = cs % spd == 0;
-                if (day_start) rescale(yr, sc);
-                double Sa[kAlign], Ia[kAlign];
-#pragma unroll
-                for (int j = 0; j < kAlign; ++j) {
-                    Sa[j] = yr.S;
-                    Ia[j] = yr.I;
-                    rk4_step<double, false>(yr, sc);
-                }
-#pragma unroll
-                for (int j = kAlign - 1; j >= 0; --j)
-                    rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, h3, g);
-                if (day_start) {
-                    const int i = cs / spd;
-                    aD += cost_grad(KIND, i, W, Dd, ly[i], lw[i], imax);
-                    if (cs == seg_lo && kr > 0) {
-                        // the chunk's first step opened segment kr
-                        if (active) gout[(size_t)kr * ld] = (g.beta * invN) * gl;
-                        g.beta = 0.0;
+                rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                if (lo == dstart) {
+                    muD = fma(sc.h6 * aD, g.Jsum, muD);
+                    g.Jsum = 0.0;
+                    aD += cost_grad(KIND, dnext, W, Dd, ly[dnext], lw[dnext], imax);
+                    m6 = sc.h6 * (mu * aD);
+                    m3 = h3 * (mu * aD);
+                    if (dstart == seg_lo && kr > 0) {
+                        // the step just reversed opened segment kr
+                        if (active) gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
+                        g.Gsv = 0.0;
+                        g.Gv = 0.0;
                         --kr;
                         seg_lo -= SS;
-                        set_beta(sc, th[(size_t)kr * ld], invN);
+                        set_beta(sc, lb[kr * kWave + lane], invN);
+                        Sk = load(q_seg + kr);
                     }
+                    --dnext;
                 }
-            }
-            continue;
-        }
-        const int n_chunks = (n1 - n0 + kChunk - 1) / kChunk;
-        // pass 1: replay the interval from its checkpoint with exactly the
-        // forward pass's operations up to the start of its last chunk,
-        // storing the state before the first step of every chunk but the
-        // first (the checkpoint) and the last (kept in registers)
-        double lastS = ckS, lastI = ckI, lasts = cks;
-        if (n_chunks > 1) {
-            SirdState<double> yr;
-            yr.S = ckS;
-            yr.I = ckI;
-            yr.s = cks;
-            yr.Rr = yr.D = 0.0;
-            yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
-            int kf = seg_of(n0, SS, K);
-            StepConst<double> sf = sc;
-            set_beta(sf, th[(size_t)kf * ld], invN);
-            const int stop = n0 + (n_chunks - 1) * kChunk;
-            int st = n0, sd = n0 % spd, next_store = n0 + kChunk;
-            double *ip = in_ws + 3 * PS;
-            while (st < stop) {
-                if (sd == 0) {
-                    if (kf < K - 1 && st == (kf + 1) * SS) {
-                        ++kf;
-                        set_beta(sf, th[(size_t)kf * ld], invN);
-                    }
-                    rescale(yr, sf);
-                }
-                const int run = min(spd - sd, next_store - st);
-#pragma unroll 2
-                for (int i = 0; i < run; ++i) rk4_step<double, false>(yr, sf);
-                st += run;
-                sd += run;
-                if (sd == spd) sd = 0;
-                if (st == next_store && st < stop) {
-                    if (active) {
-                        ip[0] = yr.S;
-                        ip[PS] = yr.I;
-                        ip[2 * PS] = yr.s;
-                    }
-                    ip += 3 * PS;
-                    next_store += kChunk;
-                }
-            }
-            lastS = yr.S;
-            lastI = yr.I;
-            lasts = yr.s;
-        }
-        // pass 2: chunks last to first: replay kChunk steps into registers,
-        // then walk them backwards.  The next chunk's start state, its day
-        // starts (a mask) and their Dhat are loaded before the current
-        // chunk is walked, so with one wavefront per SIMD their latency is
-        // hidden.
-        // With at least kChunk steps per day a chunk holds at most one day
-        // start, kept in (nD1, nday1); else every day start j of the chunk
-        // has its own (nD[j], nday[j]).
-        const bool sparse = spd >= kChunk;
-        double nS, nI, ns, nD[kChunk], nD1;
-        int nday[kChunk], nday1;
-        unsigned nmask;
-        // chunk c starts at step cs = n0 + c kChunk = q spd + ph
-        auto load_chunk = [&](int c, int cs, int q, int ph) {
-            if (c == 0) {
-                nS = ckS;
-                nI = ckI;
-                ns = cks;
-            } else if (c == n_chunks - 1) {
-                nS = lastS;
-                nI = lastI;
-                ns = lasts;
-            } else {
-                const double *sp = in_ws + (size_t)(3 * c) * PS;
-                nS = active ? sp[0] : 0.0;
-                nI = active ? sp[PS] : 0.0;
-                ns = active ? sp[2 * PS] : 0.0;
-            }
-            const int len = (n1 - cs < kChunk) ? n1 - cs : kChunk;
-            int jd = ph == 0 ? 0 : spd - ph;  // first day start in the chunk
-            int d = ph == 0 ? q : q + 1;      // its day
-            nmask = 0u;
-            nD1 = 0.0;
-            nday1 = d;
-            if (sparse) {
-                if (jd < len) {
-                    nmask = 1u << jd;
-                    if (active) nD1 = day_ws[(size_t)d * PS];
-                }
-                return;
-            }
-#pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                nD[j] = 0.0;
-                nday[j] = 0;
-                if (j == jd && j < len) {
-                    nmask |= 1u << j;
-                    nday[j] = d;
-                    if (active) nD[j] = day_ws[(size_t)d * PS];
-                    ++d;
-                    jd += spd;
-                }
+                st = lo - 1;
             }
         };
-        int cs = n0 + (n_chunks - 1) * kChunk;
-        int q = cs / spd, ph = cs - q * spd;
-        load_chunk(n_chunks - 1, cs, q, ph);
-        for (int c = n_chunks - 1; c >= 0; --c) {
-            const int len = (n1 - cs < kChunk) ? n1 - cs : kChunk;
-            SirdState<double> yr;
-            yr.S = nS;
-            yr.I = nI;
-            yr.s = ns;
-            yr.Rr = yr.D = 0.0;
-            yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
-            double Dd[kChunk];
-            int day[kChunk];
-            if (!sparse) {
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    Dd[j] = nD[j];
-                    day[j] = nday[j];
-                }
+        const int nsub = (n1 - n0 + a.lc - 1) / a.lc;
+        if (nsub == 1) {
+            // the interval fits the LDS slice (the default interval): its
+            // own code path, where no load is in flight at the replay
+            sub_interval(n0, n1, ck, true);
+            continue;
+        }
+        // with more than one sub-interval: replay up to the last one's start,
+        // storing the starts of the ones between (the first starts at the
+        // checkpoint, the last one's start stays in registers)
+        SirdState<double> last = ck;
+        {
+            int kf = seg_of(n0, SS, K);
+            StepConst<double> sf = sc;
+            set_beta(sf, lb[kf * kWave + lane], invN);
+            int next = next_seg_start(kf, SS, K, T);
+            int st = n0, mark = n0 + a.lc;
+            size_t sq = q_sub;
+            advance_marked(last, sf, kf, next, st, n0 + (nsub - 1) * a.lc, mark, a.lc, lb, lane,
+                           invN, SS, K, T, [&]() {
+                               sq += 3;
+                               if (active) {
+                                   slot(sq) = last.s;
+                                   slot(sq + 1) = last.I;
+                                   slot(sq + 2) = last.S;
+                               }
+                           });
+            // the last sub-interval may open a segment: its start state after
+            // the change, as every stored start holds it
+            if (st == next) change_segment(last, sf, kf, next, lb, lane, invN, SS, K, T);
+        }
+        for (int j = nsub - 1; j >= 0; --j) {
+            const int b0 = n0 + j * a.lc;
+            const int b1 = (b0 + a.lc < n1) ? b0 + a.lc : n1;
+            SirdState<double> y = ck;
+            if (j == nsub - 1) {
+                y = last;
+            } else if (j > 0) {
+                const size_t q = q_sub + 3 * (size_t)j;
+                y.s = load(q);
+                y.I = load(q + 1);
+                y.S = load(q + 2);
             }
-            const double Dd1 = nD1;
-            const int day1 = nday1;
-            const unsigned dmask = nmask;
-            // the previous chunk's position
-            const int pcs = cs - kChunk;
-            int pq = q, pph = ph - kChunk;
-            while (pph < 0) {
-                pph += spd;
-                --pq;
-            }
-            if (c > 0) load_chunk(c - 1, pcs, pq, pph);
-            // segment of the chunk's first step: kr, or an earlier one when
-            // a segment starts inside the chunk
-            int kf = kr, lo = seg_lo;
-            while (cs < lo) {
-                --kf;
-                lo -= SS;
-            }
-            StepConst<double> sf = sc;  // the reverse's segment: no reload
-            if (kf != kr) set_beta(sf, th[(size_t)kf * ld], invN);
-            int next_seg = (kf < K - 1) ? (kf + 1) * SS : T + 1;
-            // replay, then walk back; a full chunk (every chunk but an
-            // interval's last one, when the interval is not a multiple of
-            // kChunk) has no per-step length test
-            auto walk = [&](auto full) {
-                constexpr bool FULL = decltype(full)::value;
-                double Sa[kChunk], Ia[kChunk];
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    Sa[j] = Ia[j] = 0.0;
-                    if (FULL || j < len) {
-                        if (dmask & (1u << j)) {
-                            if (cs + j == next_seg) {
-                                ++kf;
-                                next_seg = (kf < K - 1) ? next_seg + SS : T + 1;
-                                set_beta(sf, th[(size_t)kf * ld], invN);
-                            }
-                            rescale(yr, sf);
-                        }
-                        Sa[j] = yr.S;
-                        Ia[j] = yr.I;
-                        rk4_step<double, false>(yr, sf);
-                    }
-                }
-#pragma unroll
-                for (int j = kChunk - 1; j >= 0; --j) {
-                    if (FULL || j < len) {
-                        rk4_adjoint_step(Sa[j], Ia[j], aS, aI, aD, sc, mu, h3, g);
-                        if (dmask & (1u << j)) {
-                            const int i = sparse ? day1 : day[j];
-                            const double Dj = sparse ? Dd1 : Dd[j];
-                            aD += cost_grad(KIND, i, W, Dj, ly[i], lw[i], imax);
-                            if (cs + j == seg_lo && kr > 0) {
-                                // the step just reversed opened segment kr
-                                if (active) gout[(size_t)kr * ld] = (g.beta * invN) * gl;
-                                g.beta = 0.0;
-                                --kr;
-                                seg_lo -= SS;
-                                set_beta(sc, th[(size_t)kr * ld], invN);
-                            }
-                        }
-                    }
-                }
-            };
-            if (len == kChunk)
-                walk(std::true_type{});
-            else
-                walk(std::false_type{});
-            cs = pcs;
-            q = pq;
-            ph = pph;
+            sub_interval(b0, b1, y, j == nsub - 1);
         }
     }
     if (active) {
-        gout[(size_t)kr * ld] = (g.beta * invN) * gl;
-        gout[(size_t)K * ld] = g.gamma * gl;
-        gout[(size_t)(K + 1) * ld] = g.mu * gl;
+        gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
+        gout[(size_t)K * ld] = -g.tI * gl;
+        gout[(size_t)(K + 1) * ld] = (muD - g.tI) * gl;
         gout[(size_t)(K + 2) * ld] = (aI - aS) * gl;
     }
 }
 
-// The checkpoint interval: as given, else ceil(sqrt(T)) rounded up to a
-// multiple of kAlign (so that problems whose steps per day are a multiple
-// of kAlign take the aligned sweep).
-static int resolve_interval(const sird_batch *b, int ckpt_interval)
+// Steps per LDS sub-interval: as many as fit the wavefront's share of LDS
+// (four wavefronts per compute unit) next to the observations and betas,
+// within [kLcMin, kLcMax].
+static int lds_steps(const sird_batch *b)
 {
-    if (ckpt_interval > 0) return ckpt_interval;
-    const int s = (int)std::ceil(std::sqrt((double)b->max_steps));
-    return (s + kAlign - 1) / kAlign * kAlign;
+    const long fixed = 8L * (2L * (b->max_days + 1) + (long)kWave * (b->max_d - 3 + 4));
+    long lc = (kBwdLdsBudget - fixed) / (2L * kWave * 8);
+    if (lc < kLcMin) lc = kLcMin;
+    if (lc > kLcMax) lc = kLcMax;
+    return (int)lc;
 }
 
-// Workspace slots per particle: 3 per checkpoint (S, I, s), 3 per chunk of
-// one replayed interval (the first and last chunks' slots go unused: the
-// first starts at the checkpoint, the last one's start stays in registers),
-// Dhat of every day, the day MXSE peaks on and the loss.
-static size_t ws_slots(const sird_batch *b, int s)
+// Checkpoints per particle for ckpt_interval.  0: per problem the whole
+// days that fit lc steps (an interval of at least (lc + 1)/2 steps, and at
+// most one checkpoint a day), or lc steps when a day is longer.
+static int64_t checkpoints(const sird_batch *b, int ckpt_interval)
 {
-    const int64_t n_ck = (b->max_steps + s - 1) / s;
-    const int64_t n_chunk = ((int64_t)s + kChunk - 1) / kChunk;
-    return (size_t)(3 * n_ck + 3 * n_chunk + b->max_days + 1 + 2);
+    const int lc = lds_steps(b);
+    if (ckpt_interval > 0) return (b->max_steps + ckpt_interval - 1) / ckpt_interval;
+    const int64_t per_lc = (b->max_steps + lc - 1) / lc;
+    int64_t aligned = (2 * b->max_steps + lc) / (lc + 1);
+    if (aligned > b->max_days) aligned = b->max_days;
+    return per_lc > aligned ? per_lc : aligned;
+}
+
+// Workspace slots per particle: 3 per checkpoint (s, I, S), 3 per LDS
+// sub-interval of an interval longer than one (the first and last
+// sub-intervals' slots go unused: the first starts at the checkpoint, the
+// last one's start stays in registers), Dhat of every day, S at every
+// segment start, the day MXSE peaks on and the loss.
+static size_t ws_slots(const sird_batch *b, int ckpt_interval)
+{
+    const int lc = lds_steps(b);
+    const int64_t n_ck = checkpoints(b, ckpt_interval);
+    const int64_t n_sub =
+        ckpt_interval > lc ? ((int64_t)ckpt_interval + lc - 1) / lc : 0;
+    return (size_t)(3 * n_ck + 3 * n_sub + b->max_days + 1 + (b->max_d - 3) + 2);
 }
 
 template <int MODE>
@@ -682,7 +640,7 @@ static void launch_backward(int kind, int grid, int block, size_t lds, hipStream
 
 size_t adjoint_workspace_bytes(const sird_batch *b, int ckpt_interval)
 {
-    return ws_slots(b, resolve_interval(b, ckpt_interval)) * (size_t)b->total_particles *
+    return ws_slots(b, ckpt_interval) * (size_t)b->total_particles *
            sizeof(double);
 }
 
@@ -707,7 +665,6 @@ static int adjoint_prepare(const sird_batch *batch, const double *theta, const d
         return fail(SIRD_EINVAL, w + ": the adjoint supports the RK4 segment model only");
     if (ckpt_interval < 0) return fail(SIRD_EINVAL, w + ": ckpt_interval < 0");
     if (batch->obs_len < 1) return fail(SIRD_EINVAL, w + ": batch planned without obs");
-    const int s = resolve_interval(batch, ckpt_interval);
     *a = BwdArgs{};
     a->probs = batch->probs;
     a->tiles = batch->tiles;
@@ -719,26 +676,53 @@ static int adjoint_prepare(const sird_batch *batch, const double *theta, const d
     a->P = batch->total_particles;
     a->n_tiles = batch->n_tiles;
     a->obs_series = batch->obs_series;
-    a->s = s;
-    a->n_ck_max = (int)((batch->max_steps + s - 1) / s);
+    a->s = ckpt_interval;
+    a->lc = lds_steps(batch);
+    a->n_ck_max = (int)checkpoints(batch, ckpt_interval);
+    a->n_sub_max = ckpt_interval > a->lc ? (ckpt_interval + a->lc - 1) / a->lc : 0;
     a->max_days = batch->max_days;
-    a->lds_stride = 2 * (batch->max_days + 1);
-    *lds = (size_t)(kBwdBlock / kWave) * a->lds_stride * sizeof(double);
+    a->max_seg = batch->max_d - 3;
+    a->lds_wave = 2 * (batch->max_days + 1) + kWave * (a->max_seg + 2 * (2 + a->lc));
+    *lds = sizeof(double) * (size_t)a->lds_wave;
     if (*lds > 65536) return fail(SIRD_EINVAL, w + ": window too long for LDS");
-    *grid = tile_blocks(batch->n_tiles);
+    *grid = batch->n_tiles;
     return SIRD_OK;
 }
 
+// Wavefronts per block of k_backward: four (one per SIMD of the compute unit
+// a block lands on) when the device lets a block take four wavefronts' LDS,
+// else one.
+static int bwd_waves_per_block(size_t lds_per_wave)
+{
+    static std::atomic<int> per_block[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1;
+    int lim = per_block[dev].load(std::memory_order_relaxed);
+    if (lim <= 0) {
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess ||
+            lim <= 0)
+            return 1;
+        per_block[dev].store(lim, std::memory_order_relaxed);
+    }
+    return 4 * lds_per_wave <= (size_t)lim ? 4 : 1;
+}
+
+// grid: tiles (one wavefront each); lds: bytes per wavefront.
 static int adjoint_launch(int mode, int loss_kind, int grid, size_t lds, hipStream_t stream,
                           const BwdArgs &a, const char *who)
 {
     if (grid == 0) return SIRD_OK;
+    const int wpb = bwd_waves_per_block(lds);
+    const int blocks = (grid + wpb - 1) / wpb;
+    const int block = wpb * kWave;
+    const size_t bytes = (size_t)wpb * lds;
     if (mode == kFwdOnly)
-        launch_backward<kFwdOnly>(loss_kind, grid, kBwdBlock, lds, stream, a);
+        launch_backward<kFwdOnly>(loss_kind, blocks, block, bytes, stream, a);
     else if (mode == kRevOnly)
-        launch_backward<kRevOnly>(loss_kind, grid, kBwdBlock, lds, stream, a);
+        launch_backward<kRevOnly>(loss_kind, blocks, block, bytes, stream, a);
     else
-        launch_backward<kBoth>(loss_kind, grid, kBwdBlock, lds, stream, a);
+        launch_backward<kBoth>(loss_kind, blocks, block, bytes, stream, a);
     return hip_status(hipGetLastError(), who);
 }
 

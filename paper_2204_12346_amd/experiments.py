@@ -125,7 +125,7 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
             "ms_self_contained_backward": ms_full,
             "gradients_per_s_self_contained": n / (ms_full / 1e3),
             "ms_forward": ms_f, "reverse_over_forward": ms_rev / ms_f,
-            "ckpt_interval": ckpt_interval or "ceil(sqrt(T)) rounded up to 10",
+            "ckpt_interval": ckpt_interval or "default: whole days per LDS slice (one day here)",
             "particle_steps": b.particle_steps, "workspace_bytes": int(ws.numel())}
 
 
@@ -245,7 +245,7 @@ def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=2
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
     loss = rb.empty_particles()
-    ci = fit.refine_interval(rb)
+    ci = 0  # the library's default checkpoint interval
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
                      device=b.device)
     best = curve[-1][1]
@@ -272,7 +272,7 @@ def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10)
     rb = Batch(specs, device=b.device, obs_series=b.obs_series)
     theta = sird_gather(b, sw.pbest_x, params.lo, rb, idx, k)
     st = LbfgsState(rb, theta)
-    ci = fit.refine_interval(rb)
+    ci = 0  # the library's default checkpoint interval
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
                      device=b.device)
     sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f,

@@ -19,21 +19,6 @@ from .core import (Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm, pso_
                    sird_loss_backward_workspace, sird_pso_iterate)
 
 
-# Checkpoint interval of the adjoint that the refinement drivers use when
-# the workspace allows: the reverse sweep replays 8 steps at a time into
-# registers, so an interval of 8 leaves nothing else to replay.
-SHORT_INTERVAL = 10
-
-
-def refine_interval(batch: Batch, budget_bytes=1 << 28) -> int:
-    """ckpt_interval for sird_loss_backward on this batch: 10 when its
-    workspace fits budget_bytes, else 0 (ceil(sqrt(T)) rounded up to a
-    multiple of 10)."""
-    if sird_loss_backward_workspace(batch, SHORT_INTERVAL) <= budget_bytes:
-        return SHORT_INTERVAL
-    return 0
-
-
 def run_swarm(batch: Batch, params: PsoParams, obs, kind="ssre", iters=100, hist=True,
               graph_chunk=0, swarm: Optional[Swarm] = None, init=True) -> Swarm:
     """iters swarm iterations from pso_init.  graph_chunk > 0 replays a HIP
@@ -75,7 +60,7 @@ def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre",
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
     if ckpt_interval is None:
-        ckpt_interval = refine_interval(rb)
+        ckpt_interval = 0  # the library's default (whole days per LDS slice)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
@@ -107,7 +92,7 @@ def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre",
     loss and gradient at st.theta.  callback(round) every check_every rounds
     may return True to stop."""
     if ckpt_interval is None:
-        ckpt_interval = refine_interval(rb)
+        ckpt_interval = 0  # the library's default (whole days per LDS slice)
     ws = workspace
     if ws is None:
         ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8),
@@ -135,7 +120,7 @@ def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre"
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
     if ckpt_interval is None:
-        ckpt_interval = refine_interval(rb)
+        ckpt_interval = 0  # the library's default (whole days per LDS slice)
     st = LbfgsState(rb, theta, m=m)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
                      device=batch.device)

@@ -31,7 +31,7 @@ def _both(b, theta, obs, kind, interval, grad_loss=None):
 
 
 def test_static_scratch_gradient_equals_workspace_gradient():
-    # call 1: one fit of 8192 particles over 1800 steps (about 20 MiB of
+    # call 1: one fit of 8192 particles over 1800 steps (about 36 MiB of
     # workspace)
     f = synth.c2().fits[0]
     assert S.sird_loss_backward_workspace(make_batch([f]), 0) <= S.core.STATIC_SCRATCH_BYTES
