@@ -247,10 +247,12 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     double *const ly = lds + (size_t)(threadIdx.x / kWave) * a.lds_wave;
     double *const lw = ly + (a.max_days + 1);
     double *const lb = lw + (a.max_days + 1);              // [max_seg][64]
-    // [2 + lc][2][64]: (s, I) of the lane before each step of a
-    // sub-interval, from row 2 on (rows 0 and 1 are slack that the walk's
-    // read-ahead may touch and never uses)
-    double *const lst = lb + (size_t)a.max_seg * kWave + 4 * kWave + lane;
+    // [3][64]: a prefetched checkpoint (s, I, S), parked until its replay
+    double *const lck = lb + (size_t)a.max_seg * kWave + lane;
+    // [2 + lc + 2][2][64]: (s, I) of the lane before each step of a
+    // sub-interval, from row 2 on (two rows of slack at either end, which
+    // the walk's read-ahead may touch and never uses)
+    double *const lst = lb + (size_t)a.max_seg * kWave + 3 * kWave + 4 * kWave + lane;
 
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
@@ -409,7 +411,163 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     // the next day start at or below the reverse position
     int dnext = (T - 1) / spd;
 
+    // The step just reversed began day dnext (its Dhat is Dd): fold the mu
+    // sum's D part with the old a_D, add the cost's gradient, and close
+    // segment kr if the step opened it.
+    auto day_start = [&](int dstart, double Dd) __attribute__((always_inline)) {
+        muD = fma(sc.h6 * aD, g.Jsum, muD);
+        g.Jsum = 0.0;
+        aD += cost_grad(KIND, dnext, W, Dd, ly[dnext], lw[dnext], imax);
+        m6 = sc.h6 * (mu * aD);
+        m3 = h3 * (mu * aD);
+        if (dstart == seg_lo && kr > 0) {
+            if (active) gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
+            g.Gsv = 0.0;
+            g.Gv = 0.0;
+            --kr;
+            seg_lo -= SS;
+            set_beta(sc, lb[kr * kWave + lane], invN);
+            Sk = load(q_seg + kr);
+        }
+        --dnext;
+    };
+
     const int n_ck = (T + sp - 1) / sp;
+    if (dpc > 0) {
+        // Day-aligned intervals of L = sp steps (the last one may be shorter,
+        // a whole number of days too): interval m is walked backwards while
+        // interval m - 1 is replayed forwards, step for step, so the walk's
+        // dependent chains and the replay's overlap.  One LDS slice holds
+        // both: consecutive intervals are stored in opposite row orders
+        // (interval m in ascending rows when n_ck - 1 - m is even), so the
+        // replay writes each row right after the walk has read it; the
+        // walk's read-ahead reaches two slack rows past either end.
+        const int L = sp;
+        const int R = 2 * kWave;  // doubles per row
+        auto row_of = [&](bool asc, int i) { return lst + (asc ? i : L - 1 - i) * R; };
+        // replay state of the interval before the walked one
+        SirdState<double> yr;
+        StepConst<double> sf = sc;
+        int kf = 0, rnext = INT_MAX;
+        auto replay_start = [&](int n0r, double s0, double I0r, double S0) {
+            yr.s = s0;
+            yr.I = I0r;
+            yr.S = S0;
+            yr.Rr = yr.D = 0.0;
+            yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
+            kf = seg_of(n0r, SS, K);
+            set_beta(sf, lb[kf * kWave + lane], invN);
+            rnext = next_seg_start(kf, SS, K, T);
+        };
+        // one replayed day: spd steps from step rst into rows w, w + dw, ...
+        auto replay_step = [&](double *&w, int dw) __attribute__((always_inline)) {
+            w[0] = yr.s;
+            w[kWave] = yr.I;
+            w += dw;
+            rk4_step<double, false, false>(yr, sf);
+        };
+        // Checkpoints reach the replay through LDS: loaded one interval
+        // ahead and parked after the first day walked, so no load the replay
+        // waits for is ever issued shortly before it (waits on loads cover
+        // every load issued before).
+        double ps_ = 0.0, pI_ = 0.0, pS_ = 0.0;
+        auto prefetch = [&](int mm) {
+            if (mm >= 0) {
+                const size_t q = 3 * (size_t)mm;
+                ps_ = load(q);
+                pI_ = load(q + 1);
+                pS_ = load(q + 2);
+            }
+        };
+        auto park = [&]() {
+            lck[0] = ps_;
+            lck[kWave] = pI_;
+            lck[2 * kWave] = pS_;
+        };
+        {
+            // the last interval alone, ascending
+            const int n0 = (n_ck - 1) * L;
+            const size_t q = 3 * (size_t)(n_ck - 1);
+            replay_start(n0, load(q), load(q + 1), load(q + 2));
+            prefetch(n_ck - 2);
+            double *w = lst;
+            for (int rst = n0; rst < T; rst += spd) {
+                if (rst == rnext) change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
+                for (int i = 0; i < spd; ++i) replay_step(w, R);
+            }
+            park();
+        }
+        for (int m = n_ck - 1; m >= 0; --m) {
+            const int n0 = m * L;
+            const int n1 = (n0 + L < T) ? n0 + L : T;
+            const bool asc = ((n_ck - 1 - m) & 1) == 0;
+            // walk: row of step n1 - 1, then one row per step towards n0
+            double *r = asc ? lst + (n1 - 1 - n0) * R : lst + (L - 1 - (n1 - 1 - n0)) * R;
+            const int dr = asc ? -R : R;
+            // replay of interval m - 1 in the other order
+            const bool rep = m > 0;
+            double *w = row_of(!asc, 0);
+            const int dw = asc ? -R : R;
+            int rst = (m - 1) * L;
+            if (rep) {
+                replay_start(rst, lck[0], lck[kWave], lck[2 * kWave]);
+                prefetch(m - 2);
+            }
+            for (int hi = n1 - 1; hi >= n0; hi -= spd) {
+                const int lo = hi - spd + 1;  // a day start
+                const double Dd = load(q_day + dnext);
+                Stages cur;
+                cur.s = r[0];
+                cur.I = r[kWave];
+                double ps = r[dr], pI = r[dr + kWave];
+                stages(cur, sc);
+                if (rep && rst == rnext)
+                    change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
+                if (rep) {
+#pragma unroll 2
+                    for (int st = hi; st > lo; --st) {
+                        replay_step(w, dw);
+                        Stages nxt;
+                        nxt.s = ps;
+                        nxt.I = pI;
+                        r += dr;
+                        ps = r[dr];
+                        pI = r[dr + kWave];
+                        stages(nxt, sc);
+                        rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                        cur = nxt;
+                    }
+                    replay_step(w, dw);
+                    rst += spd;
+                } else {
+#pragma unroll 2
+                    for (int st = hi; st > lo; --st) {
+                        Stages nxt;
+                        nxt.s = ps;
+                        nxt.I = pI;
+                        r += dr;
+                        ps = r[dr];
+                        pI = r[dr + kWave];
+                        stages(nxt, sc);
+                        rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                        cur = nxt;
+                    }
+                }
+                rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                r += dr;
+                day_start(lo, Dd);
+                if (hi == n1 - 1 && m >= 2) park();
+            }
+            // the replayed interval is longer than the walked one (only
+            // after the last interval): its remaining days alone
+            if (rep) {
+                for (; rst < n0; rst += spd) {
+                    if (rst == rnext) change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
+                    for (int i = 0; i < spd; ++i) replay_step(w, dw);
+                }
+            }
+        }
+    } else {
     // the checkpoint of the interval to reverse next, loaded one interval
     // ahead
     double cs_, cI, cS;
@@ -500,24 +658,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     cur = nxt;
                 }
                 rev_step(cur, aS, aI, sc, h3, m6, m3, g);
-                if (lo == dstart) {
-                    muD = fma(sc.h6 * aD, g.Jsum, muD);
-                    g.Jsum = 0.0;
-                    aD += cost_grad(KIND, dnext, W, Dd, ly[dnext], lw[dnext], imax);
-                    m6 = sc.h6 * (mu * aD);
-                    m3 = h3 * (mu * aD);
-                    if (dstart == seg_lo && kr > 0) {
-                        // the step just reversed opened segment kr
-                        if (active) gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
-                        g.Gsv = 0.0;
-                        g.Gv = 0.0;
-                        --kr;
-                        seg_lo -= SS;
-                        set_beta(sc, lb[kr * kWave + lane], invN);
-                        Sk = load(q_seg + kr);
-                    }
-                    --dnext;
-                }
+                if (lo == dstart) day_start(dstart, Dd);
                 st = lo - 1;
             }
         };
@@ -567,6 +708,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             sub_interval(b0, b1, y, j == nsub - 1);
         }
     }
+    }
     if (active) {
         gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
         gout[(size_t)K * ld] = -g.tI * gl;
@@ -580,7 +722,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
 // within [kLcMin, kLcMax].
 static int lds_steps(const sird_batch *b)
 {
-    const long fixed = 8L * (2L * (b->max_days + 1) + (long)kWave * (b->max_d - 3 + 4));
+    const long fixed = 8L * (2L * (b->max_days + 1) + (long)kWave * (b->max_d - 3 + 3 + 8));
     long lc = (kBwdLdsBudget - fixed) / (2L * kWave * 8);
     if (lc < kLcMin) lc = kLcMin;
     if (lc > kLcMax) lc = kLcMax;
@@ -682,7 +824,7 @@ static int adjoint_prepare(const sird_batch *batch, const double *theta, const d
     a->n_sub_max = ckpt_interval > a->lc ? (ckpt_interval + a->lc - 1) / a->lc : 0;
     a->max_days = batch->max_days;
     a->max_seg = batch->max_d - 3;
-    a->lds_wave = 2 * (batch->max_days + 1) + kWave * (a->max_seg + 2 * (2 + a->lc));
+    a->lds_wave = 2 * (batch->max_days + 1) + kWave * (a->max_seg + 3 + 2 * (4 + a->lc));
     *lds = sizeof(double) * (size_t)a->lds_wave;
     if (*lds > 65536) return fail(SIRD_EINVAL, w + ": window too long for LDS");
     *grid = batch->n_tiles;
