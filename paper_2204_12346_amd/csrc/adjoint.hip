@@ -33,7 +33,9 @@
 // S_k at the segment's start: there the sum is S_k sum I_s u).
 // D never feeds back, so its adjoint is piecewise constant between samples:
 // kbar_s.D = w_s h a_D with the RK4 weights w = (1/6, 1/3, 1/3, 1/6), and
-// the D part of the mu sum is h/6 a_D (I1 + 2 I2 + 2 I3 + I4) per step.
+// the D part of the mu sum is h/6 a_D (I1 + 2 I2 + 2 I3 + I4) per step,
+// added a day at a time from the day's sum of J = I1 + 2 I2 + 2 I3 + I4,
+// which the forward pass saves.
 // The initial state depends on I0 through S0 = N - I0 - R0 - D0 and I = I0.
 //
 // Every replay repeats the forward pass's operations from a stored state,
@@ -117,7 +119,6 @@ struct RevSums {
     double Gsv;   // sum over the current segment's stages of s_s I_s u
     double Gv;    // sum over the current segment's stages of I_s u
     double tI;    // sum over all stages of I_s kbar_s.I
-    double Jsum;  // sum of I1 + 2 I2 + 2 I3 + I4 since a_D last changed
 };
 
 // One stage of the reverse step: Ybar = J(Y_s)^T kbar; Ybar.S = b v with
@@ -178,7 +179,6 @@ __device__ __forceinline__ void rev_step(const Stages &z, double &aS, double &aI
     g.Gv += V;
     aS = fma(k.b, V, aS);
     aI = aI + ((Y1 + Y2) + (Y3 + Y4));
-    g.Jsum += fma(2.0, z.I2 + z.I3, z.I + z.I4);
 }
 
 // dL/dbeta_k (before the upstream factor) from the segment's sums.
@@ -217,11 +217,13 @@ __device__ __forceinline__ void change_segment(SirdState<double> &y, StepConst<d
 // The forward pass's integration from step st to step end (segment changes
 // included), calling at() before the steps mark, mark + period, ... (it may
 // store the state); the steps between calls run with no per-step test.
+// jsum accumulates the steps' J.
 template <typename At>
 __device__ __forceinline__ void advance_marked(SirdState<double> &y, StepConst<double> &sf,
                                                int &kf, int &next, int &st, int end, int &mark,
                                                int period, const double *lb, int lane,
-                                               double invN, int SS, int K, int T, At at)
+                                               double invN, int SS, int K, int T, double &jsum,
+                                               At at)
 {
     while (st < end) {
         if (st == next) change_segment(y, sf, kf, next, lb, lane, invN, SS, K, T);
@@ -231,7 +233,7 @@ __device__ __forceinline__ void advance_marked(SirdState<double> &y, StepConst<d
         }
         const int stop = min(min(end, next), mark);
 #pragma unroll 2
-        for (; st < stop; ++st) rk4_step<double, false, false>(y, sf);
+        for (; st < stop; ++st) jsum += rk4_step<double, false, false>(y, sf);
     }
 }
 
@@ -273,7 +275,8 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     // next instructions want); idle lanes address their stand-in column.
     //   checkpoint m: slots 3m..3m+2 (s, I, S); stored sub-interval start j:
     //   q_sub + 3j..; Dhat_i: q_day + i; S at segment k's start: q_seg + k;
-    //   MXSE's day and the loss: q_tail, q_tail + 1
+    //   the sum of J over day i's steps: q_jd + i; MXSE's day and the loss:
+    //   q_tail, q_tail + 1
     double *const wsb = a.ws + (size_t)(P.p_off + tl.p0);
     const uint32_t loff = (uint32_t)(pc - tl.p0) * (uint32_t)sizeof(double);
     auto slot = [&](size_t q) -> double & {
@@ -289,7 +292,8 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     const size_t q_sub = 3 * (size_t)a.n_ck_max;
     const size_t q_day = q_sub + 3 * (size_t)a.n_sub_max;
     const size_t q_seg = q_day + (size_t)(a.max_days + 1);
-    const size_t q_tail = q_seg + (size_t)a.max_seg;
+    const size_t q_jd = q_seg + (size_t)a.max_seg;
+    const size_t q_tail = q_jd + (size_t)a.max_days;
 
     {
         // deceased counts: the last of the obs_series blocks of W+1 values
@@ -344,6 +348,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
         for (int day = 0; day < W; ++day) {
             // the day's observation, read before its steps
             const double yo = ly[day + 1], wo = lw[day + 1];
+            double jd = 0.0;  // the day's sum of J
             if (dpc > 0) {
                 // checkpoints at day starts: the loss kernel's day loop
                 if (st == next) change_segment(y, sc, kf, next, lb, lane, invN, SS, K, T);
@@ -357,11 +362,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     next_ck += sp;
                 }
 #pragma unroll 4
-                for (int i = 0; i < spd; ++i) rk4_step<double, false, false>(y, sc);
+                for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
                 st += spd;
             } else {
                 advance_marked(y, sc, kf, next, st, st + spd, next_ck, sp, lb, lane, invN, SS,
-                               K, T, [&]() {
+                               K, T, jd, [&]() {
                                    if (active) {
                                        slot(cq) = y.s;
                                        slot(cq + 1) = y.I;
@@ -379,7 +384,10 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             const double prev = acc;
             cost_accum(KIND, acc, y.D, yo, wo, day + 1);
             if (KIND == SIRD_LOSS_MXSE && !(acc == prev)) imax = day + 1;
-            if (active) slot(q_day + day + 1) = y.D;
+            if (active) {
+                slot(q_day + day + 1) = y.D;
+                slot(q_jd + day) = jd;
+            }
         }
         const double L = cost_finish(KIND, acc, W);
         if (active && a.loss_out) a.loss_out[P.p_off + pl] = L;
@@ -403,7 +411,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     double aD = cost_grad(KIND, W, W, load(q_day + W), ly[W], lw[W], imax);
     double m6 = sc.h6 * (mu * aD), m3 = h3 * (mu * aD);
     double muD = 0.0;  // sum over steps of h/6 a_D (I1 + 2 I2 + 2 I3 + I4)
-    RevSums g{0.0, 0.0, 0.0, 0.0};
+    RevSums g{0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
     set_beta(sc, lb[kr * kWave + lane], invN);
     int seg_lo = kr * SS;  // first step of segment kr
@@ -411,12 +419,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     // the next day start at or below the reverse position
     int dnext = (T - 1) / spd;
 
-    // The step just reversed began day dnext (its Dhat is Dd): fold the mu
-    // sum's D part with the old a_D, add the cost's gradient, and close
-    // segment kr if the step opened it.
-    auto day_start = [&](int dstart, double Dd) __attribute__((always_inline)) {
-        muD = fma(sc.h6 * aD, g.Jsum, muD);
-        g.Jsum = 0.0;
+    // The step just reversed began day dnext (its Dhat is Dd, the day's sum
+    // of J is Jd): add the mu sum's D part of the day with the day's a_D, add
+    // the cost's gradient, and close segment kr if the step opened it.
+    auto day_start = [&](int dstart, double Dd, double Jd) __attribute__((always_inline)) {
+        muD = fma(sc.h6 * aD, Jd, muD);
         aD += cost_grad(KIND, dnext, W, Dd, ly[dnext], lw[dnext], imax);
         m6 = sc.h6 * (mu * aD);
         m3 = h3 * (mu * aD);
@@ -516,6 +523,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             for (int hi = n1 - 1; hi >= n0; hi -= spd) {
                 const int lo = hi - spd + 1;  // a day start
                 const double Dd = load(q_day + dnext);
+                const double Jd = load(q_jd + dnext);
                 Stages cur;
                 cur.s = r[0];
                 cur.I = r[kWave];
@@ -555,7 +563,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                 }
                 rev_step(cur, aS, aI, sc, h3, m6, m3, g);
                 r += dr;
-                day_start(lo, Dd);
+                day_start(lo, Dd, Jd);
                 if (hi == n1 - 1 && m >= 2) park();
             }
             // the replayed interval is longer than the walked one (only
@@ -637,6 +645,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                 // its steps and uses it after them (no load is left in flight
                 // into the next replay, whose first step would wait for it)
                 const double Dd = lo == dstart ? load(q_day + dnext) : 0.0;
+                const double Jd = lo == dstart ? load(q_jd + dnext) : 0.0;
                 // rows of steps st, st - 1, ...; the read-ahead of the last
                 // iterations reaches at most two rows below lo (the slack)
                 const double *r = lst + (st - b0) * (2 * kWave);
@@ -658,7 +667,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     cur = nxt;
                 }
                 rev_step(cur, aS, aI, sc, h3, m6, m3, g);
-                if (lo == dstart) day_start(dstart, Dd);
+                if (lo == dstart) day_start(dstart, Dd, Jd);
                 st = lo - 1;
             }
         };
@@ -680,8 +689,9 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             int next = next_seg_start(kf, SS, K, T);
             int st = n0, mark = n0 + a.lc;
             size_t sq = q_sub;
+            double jdummy = 0.0;
             advance_marked(last, sf, kf, next, st, n0 + (nsub - 1) * a.lc, mark, a.lc, lb, lane,
-                           invN, SS, K, T, [&]() {
+                           invN, SS, K, T, jdummy, [&]() {
                                sq += 3;
                                if (active) {
                                    slot(sq) = last.s;
@@ -746,14 +756,14 @@ static int64_t checkpoints(const sird_batch *b, int ckpt_interval)
 // sub-interval of an interval longer than one (the first and last
 // sub-intervals' slots go unused: the first starts at the checkpoint, the
 // last one's start stays in registers), Dhat of every day, S at every
-// segment start, the day MXSE peaks on and the loss.
+// segment start, every day's sum of J, the day MXSE peaks on and the loss.
 static size_t ws_slots(const sird_batch *b, int ckpt_interval)
 {
     const int lc = lds_steps(b);
     const int64_t n_ck = checkpoints(b, ckpt_interval);
     const int64_t n_sub =
         ckpt_interval > lc ? ((int64_t)ckpt_interval + lc - 1) / lc : 0;
-    return (size_t)(3 * n_ck + 3 * n_sub + b->max_days + 1 + (b->max_d - 3) + 2);
+    return (size_t)(3 * n_ck + 3 * n_sub + b->max_days + 1 + (b->max_d - 3) + b->max_days + 2);
 }
 
 template <int MODE>

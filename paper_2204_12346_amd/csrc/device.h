@@ -105,8 +105,10 @@ __device__ __forceinline__ void unscale(SirdState<R> &y, const StepConst<R> &k)
     if (k.b != R(0)) y.S = y.s / k.b;
 }
 
+// Returns J = I1 + 2 I2 + 2 I3 + I4 (D+ - D = h/6 mu J), which callers that
+// only integrate ignore.
 template <typename R, bool WITH_R, bool WITH_S = true>
-__device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
+__device__ __forceinline__ R rk4_step(SirdState<R> &y, const StepConst<R> &k)
 {
     // Stage I_{k+1} = I + c h (p_k - lam I_k) is formed as
     // fma(c h, p_k, I - c h lam I_k): the second term does not wait for
@@ -142,6 +144,7 @@ __device__ __forceinline__ void rk4_step(SirdState<R> &y, const StepConst<R> &k)
         if (WITH_R) kahan_add(y.Rr, y.eR, k.h6g * J);
         kahan_add(y.D, y.eD, k.h6mu * J);
     }
+    return J;
 }
 
 template <typename R>

@@ -71,12 +71,14 @@ def swarm_throughput(wl, dtype="f64", iters=200, warmup=10, graph_chunk=10,
             "particles": b.total_particles, "graph_chunk": graph_chunk}
 
 
-def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
+def gradients_per_s(wl, thetas, reps=10, ckpt_interval=0, warm_pairs=5) -> Dict:
     """Loss + gradient of every parameter vector, as the autograd path runs
     it: sird_loss saving the adjoint's checkpoints, then the reverse sweep
     alone (sird_loss_backward from_forward).  Also timed: the self-contained
     sird_loss_backward (both passes in one launch, as the refinement uses
-    it) and the plain loss kernel."""
+    it) and the plain loss kernel.  warm_pairs loss + gradient pairs run
+    first: the engine clock takes a few milliseconds of this load to settle
+    (the first pairs of a cold start run up to 20 % slower)."""
     f = wl.fits[0]
     b = Batch([ProblemSpec.from_fit(f, len(thetas))])
     theta = b.pack_theta([thetas])
@@ -112,6 +114,8 @@ def gradients_per_s(wl, thetas, reps=3, ckpt_interval=0) -> Dict:
         sird_loss_backward(b, theta, obs, wl.loss, grad_theta=grad, loss_out=loss,
                            ckpt_interval=ckpt_interval, workspace=ws)
 
+    for _ in range(warm_pairs):
+        pair()
     ms_pair = timed(pair)
     ms_fc = timed(fwd_ckpt)
     fwd_ckpt()

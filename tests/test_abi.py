@@ -210,20 +210,21 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     b.c.waves_per_simd = 0
     ws = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 0)
     # steps of the LDS sub-interval: what fits 40 KiB next to the observations
-    # (2 x 46 doubles), 64 lanes' betas (4 segments) and two slack rows of
-    # (s, I); the default interval
-    lc = (40960 - 8 * (2 * 46 + 64 * (4 + 4))) // (2 * 64 * 8)
-    assert lc == 35
+    # (2 x 46 doubles), 64 lanes' betas (4 segments), a parked checkpoint
+    # (3 x 64) and two slack rows of (s, I) at either end
+    lc = (40960 - 8 * (2 * 46 + 64 * (4 + 3 + 8))) // (2 * 64 * 8)
+    assert lc == 31
     # the default interval is a whole number of days per problem that fits lc
     # steps: at least (lc + 1)/2 steps, at most one checkpoint a day; 3 slots
-    # per checkpoint (s, I, S), one per day, one per segment start, the day
-    # MXSE peaks on and the loss
+    # per checkpoint (s, I, S), Dhat of days 0..45, S at the start of each of
+    # 4 segments, the sum of J of days 0..44, the day MXSE peaks on and the
+    # loss
     n_ck = max(int(np.ceil(300 / lc)), min(45, (2 * 300 + lc) // (lc + 1)))
-    assert n_ck == 17
-    assert ws == (3 * n_ck + 46 + 4 + 2) * 165 * 8
+    assert n_ck == 19
+    assert ws == (3 * n_ck + 46 + 4 + 45 + 2) * 165 * 8
     # an interval longer than the sub-interval adds 3 slots per sub-interval
     ws100 = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 100)
-    assert ws100 == (3 * 3 + 3 * int(np.ceil(100 / lc)) + 46 + 4 + 2) * 165 * 8
+    assert ws100 == (3 * 3 + 3 * int(np.ceil(100 / lc)) + 46 + 4 + 45 + 2) * 165 * 8
     # too small a workspace is reported before anything is enqueued
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
                                 dummy.data_ptr(), None, 0, 0, ctypes.c_void_p(4096), 16, None)
