@@ -160,6 +160,17 @@ typedef struct sird_batch {
                                 LDS so that no more blocks fit on a compute
                                 unit; SIRD_EINVAL when the reservation would
                                 exceed 64 KiB per block)                     */
+    int32_t ppl;             /* particles per lane of the loss and swarm
+                                integration: 0 or 1, or 2: a wavefront takes
+                                two consecutive tiles of one problem (the
+                                pairs of pair_tiles), each lane two particles,
+                                with the same results bitwise; applies to
+                                batches of the RK4 model with a
+                                deceased-count cost and persistent = 0, the
+                                others run with one                         */
+    int32_t n_pairs;         /* entries of pair_tiles                        */
+    const int32_t *pair_tiles; /* device, from sird_plan_pairs: the first tile
+                                of every tile pair; read only when ppl = 2    */
 } sird_batch;
 
 /* Coefficients of the swarm, Sec. 3.3 (inertia, cognitive, social), the
@@ -226,10 +237,19 @@ int sird_problem_validate(const sird_problem *probs, int n_prob, int64_t total_p
 int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile *tiles_out,
                     int max_tiles);
 
+/* Pair the tiles of a tile table (as sird_plan_tiles orders them) for
+ * two particles per lane: a problem's tiles 0 and 1, 2 and 3, ... form a
+ * pair, an odd last tile stands alone; writes the first tile of each pair,
+ * in table order (longest first stays longest first), to pairs_out (host)
+ * and returns the pair count, or SIRD_ENOSPACE if max_pairs is too small,
+ * SIRD_EINVAL for a bad table.  Pure host code. */
+int sird_plan_pairs(const sird_tile *tiles, int n_tiles, int32_t *pairs_out, int max_pairs);
+
 /* Fill the scalar fields of *batch from a host problem table (validated as
  * in sird_problem_validate) and the given device pointers.  traj_len may be
- * 0 if sird_integrate is not used.  block/persistent/waves_per_simd/dtype
- * are left as the caller set them.  Pure host code. */
+ * 0 if sird_integrate is not used.  block, persistent, waves_per_simd,
+ * dtype, ppl, n_pairs and pair_tiles are left as the caller set them.  Pure
+ * host code. */
 int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,
                     int64_t total_particles, int64_t theta_len, int64_t obs_len,
                     int64_t traj_len, int64_t box_len, int obs_series, int n_tiles,

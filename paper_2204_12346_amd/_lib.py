@@ -55,7 +55,8 @@ class sird_batch(ctypes.Structure):
         ("dtype", ctypes.c_int32), ("block", ctypes.c_int32),
         ("persistent", ctypes.c_int32), ("obs_series", ctypes.c_int32),
         ("models", ctypes.c_int32), ("max_part", ctypes.c_int32),
-        ("waves_per_simd", ctypes.c_int32),
+        ("waves_per_simd", ctypes.c_int32), ("ppl", ctypes.c_int32),
+        ("n_pairs", ctypes.c_int32), ("pair_tiles", ctypes.c_void_p),
     ]
 
 
@@ -108,6 +109,7 @@ SIGNATURES = {
     "pso_complete_move": (_I, [_B, _PP, _PS, _P]),
     "sird_loss_backward": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),
     "sird_loss_backward_workspace": (ctypes.c_size_t, [_B, _I]),
+    "sird_plan_pairs": (_I, [_P, _I, _P, _I]),
     "sird_loss_backward_static": (_I, [_B, _P, _P, _I, _P, _P, _P, _I, _P]),
     "pso_topk": (_I, [_B, _P, _I, _P, _P]),
     "sird_gather": (_I, [_B, _P, _P, _B, _P, _P, _I, _P]),

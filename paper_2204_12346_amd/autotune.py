@@ -1,15 +1,16 @@
 """Autotuner of the integration kernel's launch shape.
 
-Searches threads per block (1, 2, 4 or 8 wavefronts, each on its own
-64-particle tile), the cap on resident wavefronts per SIMD of a launch with
-one wavefront per tile, and the persistent-queue size (0 = one wavefront per
+Searches threads per block (1, 2, 4 or 8 wavefronts), particles per lane
+(1: each wavefront on its own 64-particle tile; 2: on a pair of a
+problem's tiles, each lane integrating two particles), the cap on resident
+wavefronts per SIMD, and the persistent-queue size (0 = one wavefront per
 tile dispatched longest-first; otherwise that many resident wavefronts
 pulling tiles from a device counter), times sird_loss (autotune) or the
-fused swarm
-iteration (autotune_iterate) with HIP events, and checks that every
-candidate returns bitwise the same losses as the first -- the launch shape
-must never change results.  Choices are cached in a JSON file keyed by
-device, precision, workload shape and objective.
+fused swarm iteration (autotune_iterate) with HIP events, and checks that
+every candidate returns bitwise the same losses as the first -- the launch
+shape must never change results.  Choices are cached in a JSON file keyed
+by device, precision, workload shape, cost and objective; a cached shape
+is applied only after one launch of it succeeds.
 """
 from __future__ import annotations
 
@@ -31,23 +32,33 @@ def _cache_path():
                                                    "sird_autotune.json"))
 
 
-def shape_key(batch: Batch) -> str:
+def shape_key(batch: Batch, kind: str) -> str:
     dev = torch.cuda.get_device_name(batch.device)
     steps = [s.T for s in batch.specs]
     return (f"{dev}|{'f32' if batch.c.dtype else 'f64'}|probs={batch.n_prob}|"
-            f"particles={batch.total_particles}|maxT={max(steps)}|sumT={sum(steps)}")
+            f"particles={batch.total_particles}|maxT={max(steps)}|sumT={sum(steps)}|"
+            f"maxW={batch.c.max_days}|series={batch.obs_series}|models={batch.c.models}|"
+            f"kind={kind}")
 
 
-def candidates(n_cu: int) -> List[Dict[str, int]]:
+def candidates(n_cu: int, pairs: bool = True) -> List[Dict[str, int]]:
+    """pairs: include two particles per lane (only batches of the RK4 model
+    with a deceased-count cost run it; for the others it would repeat a
+    one-particle shape)."""
     out = []
     for block in (64, 128, 256, 512):
-        out.append(dict(block=block, persistent=0, waves_per_simd=0))
+        out.append(dict(block=block, persistent=0, waves_per_simd=0, ppl=1))
     for block, caps in ((256, (2, 3, 4, 5)), (64, (3, 4, 5))):
         for w in caps:
-            out.append(dict(block=block, persistent=0, waves_per_simd=w))
+            out.append(dict(block=block, persistent=0, waves_per_simd=w, ppl=1))
     for wpc in (4, 6, 8, 10, 12, 16):  # resident wavefronts per CU
-        out.append(dict(block=64, persistent=n_cu * wpc, waves_per_simd=0))
-    out.append(dict(block=256, persistent=n_cu * 8, waves_per_simd=0))
+        out.append(dict(block=64, persistent=n_cu * wpc, waves_per_simd=0, ppl=1))
+    out.append(dict(block=256, persistent=n_cu * 8, waves_per_simd=0, ppl=1))
+    if pairs:
+        for block in (64, 256):
+            out.append(dict(block=block, persistent=0, waves_per_simd=0, ppl=2))
+        for w in (1, 2, 3, 4):
+            out.append(dict(block=256, persistent=0, waves_per_simd=w, ppl=2))
     return out
 
 
@@ -85,7 +96,7 @@ def _store_cache(path, cache):
 
 
 def _search(batch: Batch, key: str, run, use_cache: bool, verbose: bool,
-            rounds: int = 3, warm: int = 20) -> Dict[str, int]:
+            rounds: int = 3, warm: int = 20, kind: str = "ssre") -> Dict[str, int]:
     """run() -> (ms, result tensor) times one candidate launch shape.  Every
     candidate's result must agree bitwise with the first's; the clock is
     warmed first and the candidates are timed in interleaved rounds (median
@@ -96,10 +107,19 @@ def _search(batch: Batch, key: str, run, use_cache: bool, verbose: bool,
     if use_cache and key in cache:
         best = cache[key]["launch"]
         batch.configure(**best)
-        return best
+        try:
+            run()  # the cached shape must still launch on this batch
+            return best
+        except SirdError as e:
+            if e.status != SIRD_EINVAL:
+                raise
     n_cu = torch.cuda.get_device_properties(batch.device).multi_processor_count
-    cands = [c for c in candidates(n_cu)
-             if (c["block"] // 64) * 2 * (batch.c.max_days + 1) * 8 <= 65536]
+    pairs = batch.c.models == 1 and not kind.startswith("ird")
+    # the integration kernels stage 2 (deceased counts) or 6 (F_IRD) doubles
+    # per day and wavefront in at most 64 KiB of LDS per block
+    per_day = 2 * (3 if kind.startswith("ird") else 1)
+    cands = [c for c in candidates(n_cu, pairs)
+             if (c["block"] // 64) * per_day * (batch.c.max_days + 1) * 8 <= 65536]
     ref = None
     times = {i: [] for i in range(len(cands))}
     for r in range(rounds):
@@ -141,8 +161,9 @@ def autotune(batch: Batch, theta, obs, kind="ssre", reps=5, use_cache=True,
              verbose=False) -> Dict[str, int]:
     """Pick and apply the fastest launch shape of the loss kernel (sird_loss)
     for this batch; returns it."""
-    return _search(batch, shape_key(batch),
-                   lambda: time_config(batch, theta, obs, kind, reps), use_cache, verbose)
+    return _search(batch, shape_key(batch, kind),
+                   lambda: time_config(batch, theta, obs, kind, reps), use_cache, verbose,
+                   kind=kind)
 
 
 def autotune_iterate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="ssre", reps=5,
@@ -173,7 +194,8 @@ def autotune_iterate(batch: Batch, params: PsoParams, swarm: Swarm, obs, kind="s
         return e0.elapsed_time(e1) / reps, first
 
     try:
-        return _search(batch, shape_key(batch) + "|iterate", run, use_cache, verbose)
+        return _search(batch, shape_key(batch, kind) + "|iterate", run, use_cache, verbose,
+                       kind=kind)
     finally:
         restore()
         torch.cuda.synchronize()

@@ -112,7 +112,7 @@ class Batch:
     lays out I, R and D observations per problem (the F_IRD costs)."""
 
     def __init__(self, specs: Sequence[ProblemSpec], dtype="f64", block=0, persistent=0,
-                 with_traj=False, device="cuda", obs_series=1, waves_per_simd=0):
+                 with_traj=False, device="cuda", obs_series=1, waves_per_simd=0, ppl=1):
         specs = list(specs)
         n = len(specs)
         self.obs_series = int(obs_series)
@@ -146,21 +146,33 @@ class Batch:
         self.device = dev
         self.probs_dev = torch.from_numpy(tab.view(np.uint8).copy()).to(self.device)
         self.tiles_dev = torch.from_numpy(tiles.view(np.uint8).copy()).to(self.device)
+        pairs = np.zeros(max(nt, 1), dtype=np.int32)
+        npairs = lib().sird_plan_pairs(tiles.ctypes.data, nt, pairs.ctypes.data, len(pairs))
+        check(npairs if npairs < 0 else 0, "sird_plan_pairs")
+        self.n_pairs = npairs
+        self.pairs_host = pairs[:npairs]
+        self.pairs_dev = torch.from_numpy(pairs.copy()).to(self.device)
         self.sched_dev = torch.zeros(2, dtype=torch.int32, device=self.device)
         b = _lib.sird_batch()
         b.dtype = SIRD_F32 if dtype in ("f32", SIRD_F32) else SIRD_F64
         b.block = int(block)
         b.persistent = int(persistent)
         b.waves_per_simd = int(waves_per_simd)
+        b.ppl = int(ppl)
         check(lib().sird_batch_plan(ctypes.byref(b), tab.ctypes.data, n, p_off, theta_off,
                                     obs_off, traj_off, box_off, self.obs_series, nt,
                                     ptr(self.probs_dev),
                                     ptr(self.tiles_dev), ptr(self.sched_dev)),
               "sird_batch_plan")
+        b.n_pairs = npairs
+        b.pair_tiles = ptr(self.pairs_dev)
         self.c = b
 
     # ------------------------------------------------------------ config
-    def configure(self, block=None, persistent=None, dtype=None, waves_per_simd=None):
+    def configure(self, block=None, persistent=None, dtype=None, waves_per_simd=None,
+                  ppl=None):
+        if ppl is not None:
+            self.c.ppl = int(ppl)
         if block is not None:
             self.c.block = int(block)
         if persistent is not None:

@@ -34,6 +34,8 @@ struct FwdArgs {
     const double *obs;
     double *loss;
     double *traj;
+    const int32_t *pairs;  // first tile of each wavefront's tile pair (two particles per lane)
+    int n_pairs;
     int n_tiles;
     int n_waves;     // resident wavefronts of a persistent launch, else 0
     int obs_series;  // 1 (D) or 3 (I, R, D)
@@ -324,6 +326,139 @@ __global__ void __launch_bounds__(1024) k_forward(FwdArgs a)
     }
 }
 
+// Two particles per lane: the wavefront integrates the tile pair starting
+// at tile pairs[w] (two consecutive 64-particle tiles of one problem, or a
+// problem's last tile alone), lane l taking local particles p0 + l and
+// p0 + 64 + l.  Only for the RK4 model with a deceased-count cost.  Each
+// particle goes through exactly the operations fwd_tile applies to it (the
+// two particles' steps are interleaved, which gives the scheduler two
+// independent dependency chains), so the results are bitwise those of one
+// particle per lane; the observations are staged and read once per pair.
+template <typename R, bool FUSED, int ACC>
+__device__ __forceinline__ void fwd_pair(const FwdArgs &a, int w, int lane, double *ly)
+{
+    constexpr int PPL = 2;
+    const int t = a.pairs[w];
+    const sird_tile tl = a.tiles[t];
+    const sird_problem P = a.probs[tl.prob];
+    if (P.model != SIRD_MODEL_RK4_SEGMENTS) return;
+    const bool two = t + 1 < a.n_tiles && a.tiles[t + 1].prob == tl.prob &&
+                     a.tiles[t + 1].p0 == tl.p0 + kWave;
+    const int W = P.n_days, spd = P.steps_per_day, K = P.n_seg;
+    const int n = P.n_part;
+    const size_t ld = (size_t)n;
+    int pl[PPL];
+    bool active[PPL];
+    const double *th[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        pl[j] = tl.p0 + j * kWave + lane;
+        active[j] = pl[j] < n && (j == 0 || two);
+        th[j] = a.theta + P.theta_off + (active[j] ? pl[j] : n - 1);
+    }
+
+    stage_d(a, P, lane, ly);
+    wave_sync();
+
+    const bool lazy = FUSED && a.do_move;
+    const uint64_t it = FUSED && a.do_move ? a.iter[0] - 1 : 0;
+    double mv0[PPL][4];
+    bool from_move[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mv0[j][u] = 0.0;
+        from_move[j] = lazy && active[j];
+        if (from_move[j]) pso_move_block_seq(a.mv, P, pl[j], it, 0, mv0[j]);
+    }
+    constexpr bool WITH_S = sizeof(R) != 8;
+    const double N = P.N;
+    const double invN = 1.0 / N;
+    SirdState<R> y[PPL];
+    StepConst<R> sc[PPL];
+    double acc[PPL];
+    double beta_next[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const double gamma = from_move[j] ? mv0[j][0] : th[j][(size_t)K * ld];
+        const double mu = from_move[j] ? mv0[j][1] : th[j][(size_t)(K + 1) * ld];
+        const double I0 = from_move[j] ? mv0[j][2] : th[j][(size_t)(K + 2) * ld];
+        y[j].S = (R)(N - I0 - P.R0 - P.D0);
+        y[j].I = (R)I0;
+        y[j].Rr = (R)P.R0;
+        y[j].D = (R)P.D0;
+        y[j].s = R(0);
+        y[j].eS = y[j].eI = y[j].eR = y[j].eD = R(0);
+        sc[j] = step_const<R>(gamma, mu, spd);
+        acc[j] = acc_init<ACC>();
+        // SSRE leaves out day 0
+        const double e0 = (ly[0] - state_value(y[j].D, y[j].eD)) * ly[1];
+        acc_day<ACC>(acc[j], a.cost.skip0 ? 0.0 : e0);
+        beta_next[j] = from_move[j] ? mv0[j][3] : th[j][0];
+    }
+    const int seg = P.seg_days;
+    int day = 0;
+    for (int k = 0; k < K; ++k) {
+        double beta_k[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            beta_k[j] = beta_next[j];
+            if (k + 1 < K) {
+                if (lazy && (k & 3) == 0) {
+                    double xn[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (active[j]) pso_move_block_seq(a.mv, P, pl[j], it, k / 4 + 1, xn);
+                    beta_next[j] = active[j] ? xn[0] : th[j][(size_t)(k + 1) * ld];
+                } else {
+                    beta_next[j] = th[j][(size_t)(k + 1) * ld];  // prefetch
+                }
+            }
+        }
+        const int dend = (k == K - 1) ? W : (int)min((long)W, (long)(k + 1) * seg);
+        if (day >= dend) continue;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            if (!WITH_S && day > 0) unscale(y[j], sc[j]);
+            set_beta(sc[j], beta_k[j], invN);
+            if (!WITH_S) rescale(y[j], sc[j]);
+        }
+        for (; day < dend; ++day) {
+            if (WITH_S) {
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) rescale(y[j], sc[j]);
+            }
+            const double yo = ly[2 * (day + 1)], wo = ly[2 * (day + 1) + 1];
+#pragma unroll 4
+            for (int st = 0; st < spd; ++st) {
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) rk4_step<R, false, WITH_S>(y[j], sc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < PPL; ++j)
+                acc_day<ACC>(acc[j], (yo - state_value(y[j].D, y[j].eD)) * wo);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        if (active[j]) {
+            const double L = cost_value(a.cost, acc[j], W);
+            a.loss[P.p_off + pl[j]] = L;
+            if (FUSED) pso_pbest_particle(L, P, pl[j], a.pbest_f, a.pbest_x, a.mv.x);
+        }
+    }
+    wave_sync();  // LDS slice reads done before it is restaged
+}
+
+template <typename R, bool FUSED, int ACC>
+__global__ void __launch_bounds__(1024) k_forward_pairs(FwdArgs a)
+{
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double *ly = lds + (size_t)wave * a.lds_stride;
+    const int w = wave_tile_index();
+    if (w < a.n_pairs) fwd_pair<R, FUSED, ACC>(a, w, lane, ly);
+}
+
 // The constants of each cost kind (Sec. 3.1).
 static CostPlan cost_plan(int kind)
 {
@@ -382,6 +517,20 @@ static int launch_forward(const sird_batch *b, FwdArgs a, hipStream_t s, const c
             return fail(SIRD_EINVAL, std::string(who) +
                                          ": waves_per_simd too small for the block size");
         if (lds < cap) lds = cap;
+    }
+    if constexpr (!TRAJ && NS == 1) {
+        // two particles per lane: the tile pairs of the batch, one per
+        // wavefront (RK4-only batches without the persistent queue)
+        if (b->ppl == 2 && b->persistent == 0 && b->models == 1 << SIRD_MODEL_RK4_SEGMENTS) {
+            a.pairs = b->pair_tiles;
+            a.n_pairs = b->n_pairs;
+            a.n_waves = 0;
+            const int pgrid = (b->n_pairs + wpb - 1) / wpb;
+            if (pgrid == 0) return SIRD_OK;
+            hipLaunchKernelGGL((k_forward_pairs<R, FUSED, ACC>), dim3(pgrid), dim3(block), lds,
+                               s, a);
+            return hip_status(hipGetLastError(), who);
+        }
     }
     int grid;
     if (b->persistent > 0) {

@@ -52,6 +52,10 @@ int check_batch(const sird_batch *b, const char *who)
         return fail(SIRD_EINVAL, w + ": obs_series must be 1 or 3");
     if (b->models < 1 || b->models > 3)
         return fail(SIRD_EINVAL, w + ": models must be a non-empty mask of SIRD_MODEL_*");
+    if (b->ppl < 0 || b->ppl > 2) return fail(SIRD_EINVAL, w + ": ppl must be 0, 1 or 2");
+    if (b->ppl == 2 && b->n_tiles > 0 && (!b->pair_tiles || b->n_pairs < 1 ||
+                                          b->n_pairs > b->n_tiles))
+        return fail(SIRD_EINVAL, w + ": ppl = 2 needs the pair table (sird_plan_pairs)");
     return SIRD_OK;
 }
 
@@ -150,6 +154,22 @@ extern "C" int sird_plan_tiles(const sird_problem *probs, int n_prob, sird_tile 
     });
     for (size_t i = 0; i < t.size(); ++i) tiles_out[i] = t[i];
     return (int)t.size();
+}
+
+extern "C" int sird_plan_pairs(const sird_tile *tiles, int n_tiles, int32_t *pairs_out,
+                               int max_pairs)
+{
+    if (n_tiles < 0 || (n_tiles > 0 && (!tiles || !pairs_out)))
+        return fail(SIRD_EINVAL, "sird_plan_pairs: bad tile table");
+    int np = 0;
+    for (int t = 0; t < n_tiles;) {
+        if (np >= max_pairs) return fail(SIRD_ENOSPACE, "sird_plan_pairs: pairs_out too small");
+        pairs_out[np++] = t;
+        const bool two = t + 1 < n_tiles && tiles[t + 1].prob == tiles[t].prob &&
+                         tiles[t + 1].p0 == tiles[t].p0 + kTileParticles;
+        t += two ? 2 : 1;
+    }
+    return np;
 }
 
 extern "C" int sird_batch_plan(sird_batch *batch, const sird_problem *probs_host, int n_prob,

@@ -33,7 +33,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("sird_integrate", "sird_loss", "pso_step", "sird_loss_backward"):
         assert required in names
-    assert len(names) == 24, names
+    assert len(names) == 25, names
 
 
 def test_library_exports_every_declared_symbol(L):
@@ -55,6 +55,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", offsetof(sird_problem, N), offsetof(sird_problem, p_off),
          offsetof(sird_problem, stream), offsetof(sird_batch, probs), offsetof(sird_batch, dtype));
   printf("%zu %zu\n", offsetof(pso_state, f), offsetof(pso_state, hist_len));
+  printf("%zu %zu %zu\n", offsetof(sird_batch, ppl), offsetof(sird_batch, n_pairs),
+         offsetof(sird_batch, pair_tiles));
   return 0;
 }
 ''')
@@ -73,6 +75,9 @@ int main(void) {
     assert vals[8] == L.PROBLEM_DTYPE.fields["stream"][1]
     assert vals[9] == L.sird_batch.probs.offset
     assert vals[10] == L.sird_batch.dtype.offset
+    assert vals[13:16] == [L.sird_batch.ppl.offset, L.sird_batch.n_pairs.offset,
+                           L.sird_batch.pair_tiles.offset]
+    assert vals[2] == 136
     assert vals[11] == L.pso_state.f.offset
     assert vals[12] == L.pso_state.hist_len.offset
 
@@ -324,3 +329,30 @@ def test_static_gradient_entry_checks_on_host(L):
     small.c.dtype = L.SIRD_F32
     assert lib.sird_loss_backward_static(ctypes.byref(small.c), d, d, 0, None, d, None, 0,
                                          None) == L.SIRD_EINVAL
+
+
+def test_tile_pairs_on_host(L):
+    """sird_plan_pairs: a problem's tiles 0-1, 2-3, ... pair up, an odd last
+    tile stands alone, table order kept; ppl = 2 without the table is
+    refused before any HIP call."""
+    import torch
+    from paper_2204_12346_amd import core
+    specs = [core.ProblemSpec(30, 10, 14, 3, 1e6, n_part=300, stream=0),   # 5 tiles
+             core.ProblemSpec(60, 10, 14, 5, 1e6, n_part=128, stream=1),   # 2 tiles
+             core.ProblemSpec(12, 5, 7, 2, 1e5, n_part=0, stream=2),
+             core.ProblemSpec(45, 2, 14, 4, 1e7, n_part=65, stream=3)]     # 2 tiles
+    b = core.Batch(specs, device="cpu", ppl=2)
+    tiles = b.tiles_host
+    # longest window first: problem 1 (600 steps), then 0 (300), then 3 (90)
+    assert [int(t["prob"]) for t in tiles] == [1, 1, 0, 0, 0, 0, 0, 3, 3]
+    assert list(b.pairs_host) == [0, 2, 4, 6, 7]
+    assert b.c.ppl == 2 and b.c.n_pairs == 5
+    lib = L.lib()
+    out = np.zeros(2, dtype=np.int32)
+    assert lib.sird_plan_pairs(tiles.ctypes.data, len(tiles), out.ctypes.data, 2) == L.SIRD_ENOSPACE
+    d = torch.zeros(8, dtype=torch.float64).data_ptr()
+    b.c.pair_tiles = None
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, 0, None, 0, None) == L.SIRD_EINVAL
+    assert b"pair table" in lib.sird_last_error()
+    b.c.ppl = 3
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, 0, None, 0, None) == L.SIRD_EINVAL

@@ -175,3 +175,36 @@ def test_full_size_batched_workload_sampled():
             ref = oracle.loss_batch(prob, ths[r][p:p + 1], f.y, "ssre")
             kap = [kappa("ssre", oracle.integrate(prob, ths[r][p])[3], f.y)]
             assert_loss_close(per[r][p:p + 1], ref, kap, TOL64, f"region {r} particle {p}")
+
+
+@pytest.mark.parametrize("dtype,launch", [("f64", dict(block=256)),
+                                          ("f64", dict(block=64, waves_per_simd=4)),
+                                          ("f32", dict(block=128))])
+def test_two_particles_per_lane_bitwise(dtype, launch):
+    """Two particles per lane (tile pairs) gives bitwise the losses of one
+    particle per lane, for every deceased-count cost, on an uneven batch
+    whose problems have odd and even tile counts (a lone last tile, a
+    problem with one particle, one with none)."""
+    wl = synth.c3(regions=list(range(7)))
+    n_parts = [300, 1, 128, 0, 200, 64, 65]
+    ths = [random_theta(f, n, seed=60 + r) for r, (f, n) in enumerate(zip(wl.fits, n_parts))]
+    obs_list = [f.y for f in wl.fits]
+    out = {}
+    for ppl in (1, 2):
+        b = make_batch(wl.fits, n_parts, dtype=dtype, ppl=ppl, **launch)
+        theta, obs = b.pack_theta(ths), b.pack_obs(obs_list)
+        for kind in KINDS:
+            print(f"case ppl={ppl} {dtype} {launch} {kind}", flush=True)
+            out[(ppl, kind)] = S.sird_loss(b, theta, obs, kind).cpu().numpy()
+    for kind in KINDS:
+        assert np.array_equal(out[(1, kind)], out[(2, kind)], equal_nan=True), kind
+    # and the oracle on the lone-tile and one-particle problems
+    b = make_batch(wl.fits, n_parts, dtype=dtype, ppl=2, **launch)
+    per = b.split_particles(S.sird_loss(b, b.pack_theta(ths), b.pack_obs(obs_list), "ssre"))
+    eps = TOL64 if dtype == "f64" else TOL32
+    for r in (1, 6):
+        f = wl.fits[r]
+        prob = oracle_problem(f)
+        ref = oracle.loss_batch(prob, ths[r], f.y, "ssre")
+        kap = [kappa("ssre", oracle.integrate(prob, t)[3], f.y) for t in ths[r]]
+        assert_loss_close(per[r], ref, kap, eps, f"region {r}")

@@ -339,3 +339,30 @@ def test_fused_move_every_block_layout(launch):
                         sw.gbest_idx, sw.iter, sw.hist_f, sw.hist_idx, sw.f)])
     for a, c in zip(*states):
         assert np.array_equal(a, c, equal_nan=True)
+
+
+@pytest.mark.parametrize("dtype,launch", [("f64", dict(block=256, waves_per_simd=4)),
+                                          ("f64", dict(block=64)),
+                                          ("f32", dict(block=256))])
+def test_two_particles_per_lane_swarm_bitwise(dtype, launch):
+    """The fused swarm iteration with two particles per lane leaves bitwise
+    the swarm state of one particle per lane (moves, losses, bests,
+    history), on an uneven batch with lone last tiles."""
+    wl = synth.c3(regions=list(range(6)))
+    n_parts = [100, 64, 1, 150, 33, 257]
+    states = []
+    for ppl in (1, 2):
+        print(f"case swarm ppl={ppl} {dtype} {launch}", flush=True)
+        b = make_batch(wl.fits, n_parts, dtype=dtype, ppl=ppl, **launch)
+        params = S.PsoParams(b, [f.lo for f in wl.fits], [f.hi for f in wl.fits], wl.w, wl.c1,
+                             wl.c2, wl.seed)
+        sw = S.Swarm(b, hist_len=8)
+        obs = b.pack_obs([f.y for f in wl.fits])
+        S.pso_init(b, params, sw)
+        S.sird_pso_iterate(b, params, sw, obs, "ssre", 8)
+        torch.cuda.synchronize()
+        states.append([t.cpu().numpy().copy() for t in
+                       (sw.x, sw.v, sw.pbest_x, sw.pbest_f, sw.gbest_x, sw.gbest_f,
+                        sw.gbest_idx, sw.iter, sw.hist_f, sw.hist_idx, sw.f)])
+    for a, c in zip(*states):
+        assert np.array_equal(a, c, equal_nan=True)

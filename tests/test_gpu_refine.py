@@ -162,6 +162,19 @@ def test_autotuner_candidates_agree_bitwise(tmp_path, monkeypatch):
     # a second call is served from the cache
     again = autotune.autotune(b, theta, obs, "ssre")
     assert again == best
+    # the key separates costs; a cached shape the library refuses for this
+    # batch is searched again instead of applied
+    assert autotune.shape_key(b, "ssre") != autotune.shape_key(b, "mse")
+    import json
+    path = tmp_path / "cache.json"
+    cache = json.loads(path.read_text())
+    bad = dict(block=1024, persistent=0, waves_per_simd=1, ppl=1)
+    cache[autotune.shape_key(b, "ssre")]["launch"] = bad
+    path.write_text(json.dumps(cache))
+    redo = autotune.autotune(b, theta, obs, "ssre", reps=2)
+    assert redo != bad and redo in autotune.candidates(
+        torch.cuda.get_device_properties(0).multi_processor_count)
+    assert np.array_equal(S.sird_loss(b, theta, obs, "ssre").cpu().numpy(), ref)
 
 
 def test_autotuner_of_the_fused_iteration_restores_the_swarm(tmp_path, monkeypatch):
