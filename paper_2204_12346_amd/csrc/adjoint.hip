@@ -284,11 +284,12 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     };
     // loads through a buffer resource on the slot's (uniform) base: the
     // load's only address register is the lane offset
-    auto load = [&](size_t q) -> double {
+    auto load_at = [&](const double *base) -> double {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(wsb + q * PS), (short)0, kWave * (int)sizeof(double), kBufferWord3);
+            (void *)base, (short)0, kWave * (int)sizeof(double), kBufferWord3);
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, loff, 0, 0));
     };
+    auto load = [&](size_t q) -> double { return load_at(wsb + q * PS); };
     const size_t q_sub = 3 * (size_t)a.n_ck_max;
     const size_t q_day = q_sub + 3 * (size_t)a.n_sub_max;
     const size_t q_seg = q_day + (size_t)(a.max_days + 1);
@@ -416,8 +417,12 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     set_beta(sc, lb[kr * kWave + lane], invN);
     int seg_lo = kr * SS;  // first step of segment kr
     double Sk = load(q_seg + kr);
-    // the next day start at or below the reverse position
+    // the next day start at or below the reverse position, and the slots of
+    // its Dhat and sum of J (uniform addresses stepped down a day at a time,
+    // so a day's loads take no address arithmetic)
     int dnext = (T - 1) / spd;
+    const double *pday = wsb + (q_day + (size_t)dnext) * PS;
+    const double *pjd = wsb + (q_jd + (size_t)dnext) * PS;
 
     // The step just reversed began day dnext (its Dhat is Dd, the day's sum
     // of J is Jd): add the mu sum's D part of the day with the day's a_D, add
@@ -437,6 +442,8 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             Sk = load(q_seg + kr);
         }
         --dnext;
+        pday -= PS;
+        pjd -= PS;
     };
 
     const int n_ck = (T + sp - 1) / sp;
@@ -452,19 +459,32 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
         const int L = sp;
         const int R = 2 * kWave;  // doubles per row
         auto row_of = [&](bool asc, int i) { return lst + (asc ? i : L - 1 - i) * R; };
-        // replay state of the interval before the walked one
+        // replay state of the interval before the walked one (kf: the
+        // segment whose beta sf holds, -1 before the first replay)
         SirdState<double> yr;
         StepConst<double> sf = sc;
-        int kf = 0, rnext = INT_MAX;
+        int kf = -1, rnext = INT_MAX;
+        // the segment of the latest replay start and its first step: replay
+        // starts only move down, an interval at a time, from below T
+        int k0 = k_last;
+        int k0_lo = k_last * SS;
         auto replay_start = [&](int n0r, double s0, double I0r, double S0) {
             yr.s = s0;
             yr.I = I0r;
             yr.S = S0;
             yr.Rr = yr.D = 0.0;
             yr.eS = yr.eI = yr.eR = yr.eD = 0.0;
-            kf = seg_of(n0r, SS, K);
-            set_beta(sf, lb[kf * kWave + lane], invN);
-            rnext = next_seg_start(kf, SS, K, T);
+            while (n0r < k0_lo) {
+                --k0;
+                k0_lo -= SS;
+            }
+            // the previous replay may have ended in this segment: then sf
+            // and rnext already belong to it
+            if (k0 != kf) {
+                kf = k0;
+                set_beta(sf, lb[kf * kWave + lane], invN);
+                rnext = next_seg_start(kf, SS, K, T);
+            }
         };
         // one replayed day: spd steps from step rst into rows w, w + dw, ...
         auto replay_step = [&](double *&w, int dw) __attribute__((always_inline)) {
@@ -477,14 +497,19 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
         // ahead and parked after the first day walked, so no load the replay
         // waits for is ever issued shortly before it (waits on loads cover
         // every load issued before).
+        // mck: the checkpoint the next prefetch loads (one lower each time),
+        // at slot address pck
         double ps_ = 0.0, pI_ = 0.0, pS_ = 0.0;
-        auto prefetch = [&](int mm) {
-            if (mm >= 0) {
-                const size_t q = 3 * (size_t)mm;
-                ps_ = load(q);
-                pI_ = load(q + 1);
-                pS_ = load(q + 2);
+        int mck = n_ck - 2;
+        const double *pck = wsb + 3 * (size_t)(mck > 0 ? mck : 0) * PS;
+        auto prefetch = [&]() {
+            if (mck >= 0) {
+                ps_ = load_at(pck);
+                pI_ = load_at(pck + PS);
+                pS_ = load_at(pck + 2 * PS);
+                if (mck > 0) pck -= 3 * PS;
             }
+            --mck;
         };
         auto park = [&]() {
             lck[0] = ps_;
@@ -496,7 +521,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             const int n0 = (n_ck - 1) * L;
             const size_t q = 3 * (size_t)(n_ck - 1);
             replay_start(n0, load(q), load(q + 1), load(q + 2));
-            prefetch(n_ck - 2);
+            prefetch();
             double *w = lst;
             for (int rst = n0; rst < T; rst += spd) {
                 if (rst == rnext) change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
@@ -518,16 +543,20 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             int rst = (m - 1) * L;
             if (rep) {
                 replay_start(rst, lck[0], lck[kWave], lck[2 * kWave]);
-                prefetch(m - 2);
+                prefetch();
             }
             for (int hi = n1 - 1; hi >= n0; hi -= spd) {
                 const int lo = hi - spd + 1;  // a day start
-                const double Dd = load(q_day + dnext);
-                const double Jd = load(q_jd + dnext);
+                const double Dd = load_at(pday);
+                const double Jd = load_at(pjd);
                 Stages cur;
                 cur.s = r[0];
                 cur.I = r[kWave];
+                // the rows of the next two steps, read ahead: a row is read
+                // two steps before its stages are formed, so the read's
+                // latency hides behind a whole step
                 double ps = r[dr], pI = r[dr + kWave];
+                double qs = r[2 * dr], qI = r[2 * dr + kWave];
                 stages(cur, sc);
                 if (rep && rst == rnext)
                     change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
@@ -538,9 +567,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                         Stages nxt;
                         nxt.s = ps;
                         nxt.I = pI;
+                        ps = qs;
+                        pI = qI;
                         r += dr;
-                        ps = r[dr];
-                        pI = r[dr + kWave];
+                        qs = r[2 * dr];
+                        qI = r[2 * dr + kWave];
                         stages(nxt, sc);
                         rev_step(cur, aS, aI, sc, h3, m6, m3, g);
                         cur = nxt;
@@ -553,9 +584,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                         Stages nxt;
                         nxt.s = ps;
                         nxt.I = pI;
+                        ps = qs;
+                        pI = qI;
                         r += dr;
-                        ps = r[dr];
-                        pI = r[dr + kWave];
+                        qs = r[2 * dr];
+                        qI = r[2 * dr + kWave];
                         stages(nxt, sc);
                         rev_step(cur, aS, aI, sc, h3, m6, m3, g);
                         cur = nxt;
@@ -644,24 +677,27 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                 // a run that ends at a day start loads that day's Dhat before
                 // its steps and uses it after them (no load is left in flight
                 // into the next replay, whose first step would wait for it)
-                const double Dd = lo == dstart ? load(q_day + dnext) : 0.0;
-                const double Jd = lo == dstart ? load(q_jd + dnext) : 0.0;
-                // rows of steps st, st - 1, ...; the read-ahead of the last
-                // iterations reaches at most two rows below lo (the slack)
+                const double Dd = lo == dstart ? load_at(pday) : 0.0;
+                const double Jd = lo == dstart ? load_at(pjd) : 0.0;
+                // rows of steps st, st - 1, ...; two rows are read ahead,
+                // which below lo reaches the two slack rows under row 0
                 const double *r = lst + (st - b0) * (2 * kWave);
                 Stages cur;
                 cur.s = r[0];
                 cur.I = r[kWave];
                 double ps = r[-2 * kWave], pI = r[-kWave];
+                double qs = r[-4 * kWave], qI = r[-3 * kWave];
                 stages(cur, sc);
 #pragma unroll 2
                 for (; st > lo; --st) {
                     Stages nxt;
                     nxt.s = ps;
                     nxt.I = pI;
+                    ps = qs;
+                    pI = qI;
                     r -= 2 * kWave;
-                    ps = r[-2 * kWave];
-                    pI = r[-kWave];
+                    qs = r[-4 * kWave];
+                    qI = r[-3 * kWave];
                     stages(nxt, sc);
                     rev_step(cur, aS, aI, sc, h3, m6, m3, g);
                     cur = nxt;
