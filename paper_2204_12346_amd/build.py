@@ -7,6 +7,9 @@ Flags:
                       explicit fma() call
   -Xclang -target-feature -Xclang -packed-fp32-ops
                       keep the compiler from emitting packed FP32 VALU ops
+  -Werror=shadow      a local that shadows another is an error: kernels keep
+                      many same-typed doubles in one scope, where a shadowed
+                      name silently reads the wrong value
 
     python -m paper_2204_12346_amd.build
 """
@@ -28,7 +31,7 @@ FLAGS = [
     "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
     "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-Werror=shadow",
 ]
 
 

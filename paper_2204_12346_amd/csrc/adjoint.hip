@@ -114,25 +114,30 @@ __device__ __forceinline__ double cost_grad(int kind, int i, int W, double D, do
     }
 }
 
-// Sums of the reverse sweep.
+// Sums of the reverse sweep.  The sums over stages 2 and 3 are kept apart
+// from those over stages 1 and 4: the reverse step carries half the stage
+// adjoints of stages 2 and 3 (see rev_step), whose terms count twice.
 struct RevSums {
-    double Gsv;   // sum over the current segment's stages of s_s I_s u
-    double Gv;    // sum over the current segment's stages of I_s u
-    double tI;    // sum over all stages of I_s kbar_s.I
+    double G14;   // over the segment's stages 1 and 4: s_s I_s u
+    double G23;   // over the segment's stages 2 and 3: s_s I_s u / 2
+    double Gv;    // over the segment's stages: I_s u
+    double T14;   // over all stages 1 and 4: I_s kbar_s.I
+    double T23;   // over all stages 2 and 3: I_s kbar_s.I / 2
 };
 
 // One stage of the reverse step: Ybar = J(Y_s)^T kbar; Ybar.S = b v with
 // v = I_s u is returned as v (the next stage's kbar.S and the final sum
-// take b in their constants); mkD = mu kbar_s.D.
+// take b in their constants); mkD = mu kbar_s.D.  G and T are the stage's
+// pair of sums.
 __device__ __forceinline__ void stage_adjoint(double ss, double Is, double kS, double kI,
                                               double mkD, double lam, double &v, double &YI,
-                                              RevSums &g)
+                                              double &G, double &T)
 {
     const double u = kI - kS;
     v = Is * u;
     YI = fma(ss, u, fma(-lam, kI, mkD));
-    g.Gsv = fma(ss, v, g.Gsv);
-    g.tI = fma(Is, kI, g.tI);
+    G = fma(ss, v, G);
+    T = fma(Is, kI, T);
 }
 
 // The stages of one step from its start state (s, I), formed as the forward
@@ -157,34 +162,42 @@ __device__ __forceinline__ void stages(Stages &z, const StepConst<double> &k)
     z.I4 = fma(k.h, p3, c3);
 }
 
-// One reverse step: (aS, aI) <- a_n from a_{n+1} through the step's stages;
-// a_D is constant here (m6 = h/6 mu a_D, m3 = h/3 mu a_D).
-__device__ __forceinline__ void rev_step(const Stages &z, double &aS, double &aI,
-                                         const StepConst<double> &k, double h3, double m6,
-                                         double m3, RevSums &g)
+// One reverse step on the scaled adjoint (hS, hI) = h/6 a of (S, I): from
+// h/6 a_{n+1} to h/6 a_n through the step's stages; a_D is constant here
+// (m6 = h/6 mu a_D).  With the scaled adjoint, kbar4 = (hS, hI) and
+// kbar1 = (hS, hI) + h/2 Ybar2 take no multiply, and stages 3 and 2 run on
+// half their adjoints, kbar3/2 = (hS, hI) + h/2 Ybar4 and
+// kbar2/2 = (hS, hI) + h/2 (Ybar3/2) (h/3 = 2 h/6; the stage adjoint is
+// linear in kbar, and mu kbar.D / 2 = m6 for both): four multiplies fewer
+// than forming h/6 a and h/3 a.  Ybar2/2 and Ybar3/2 count twice in the sums.
+__device__ __forceinline__ void rev_step(const Stages &z, double &hS, double &hI,
+                                         const StepConst<double> &k, double m6, RevSums &g)
 {
     double v4, v3, v2, v1, Y4, Y3, Y2, Y1;
-    // stage 4: kbar4 = h/6 abar
-    const double k4S = k.h6 * aS, k4I = k.h6 * aI;
-    stage_adjoint(z.s4, z.I4, k4S, k4I, m6, k.lam, v4, Y4, g);
-    // stage 3: kbar3 = h/3 abar + h Ybar4
-    const double h3S = h3 * aS, h3I = h3 * aI;
-    stage_adjoint(z.s3, z.I3, fma(k.hb, v4, h3S), fma(k.h, Y4, h3I), m3, k.lam, v3, Y3, g);
-    // stage 2: kbar2 = h/3 abar + h/2 Ybar3
-    stage_adjoint(z.s2, z.I2, fma(k.h2b, v3, h3S), fma(k.h2, Y3, h3I), m3, k.lam, v2, Y2, g);
-    // stage 1: kbar1 = h/6 abar + h/2 Ybar2
-    stage_adjoint(z.s, z.I, fma(k.h2b, v2, k4S), fma(k.h2, Y2, k4I), m6, k.lam, v1, Y1, g);
+    // stage 4: kbar4 = h/6 a
+    stage_adjoint(z.s4, z.I4, hS, hI, m6, k.lam, v4, Y4, g.G14, g.T14);
+    // stage 3: kbar3 / 2 = h/6 a + h/2 Ybar4
+    stage_adjoint(z.s3, z.I3, fma(k.h2b, v4, hS), fma(k.h2, Y4, hI), m6, k.lam, v3, Y3, g.G23,
+                  g.T23);
+    // stage 2: kbar2 / 2 = h/6 a + h/2 (Ybar3 / 2)
+    stage_adjoint(z.s2, z.I2, fma(k.h2b, v3, hS), fma(k.h2, Y3, hI), m6, k.lam, v2, Y2, g.G23,
+                  g.T23);
+    // stage 1: kbar1 = h/6 a + h (Ybar2 / 2)
+    stage_adjoint(z.s, z.I, fma(k.hb, v2, hS), fma(k.h, Y2, hI), m6, k.lam, v1, Y1, g.G14,
+                  g.T14);
 
-    const double V = (v1 + v2) + (v3 + v4);
+    // a_n = a + the four Ybar: h/6 a_n = h/6 a + h/6 (Y1 + 2 (Y2 + Y3) + Y4)
+    // with the halved Y2, Y3; the S part is b V
+    const double V = fma(2.0, v2 + v3, v1 + v4);
     g.Gv += V;
-    aS = fma(k.b, V, aS);
-    aI = aI + ((Y1 + Y2) + (Y3 + Y4));
+    hS = fma(k.h6b, V, hS);
+    hI = fma(k.h6, fma(2.0, Y2 + Y3, Y1 + Y4), hI);
 }
 
 // dL/dbeta_k (before the upstream factor) from the segment's sums.
 __device__ __forceinline__ double beta_grad(const RevSums &g, double b, double Sk, double invN)
 {
-    return b != 0.0 ? (g.Gsv / b) * invN : (Sk * g.Gv) * invN;
+    return b != 0.0 ? (fma(2.0, g.G23, g.G14) / b) * invN : (Sk * g.Gv) * invN;
 }
 
 __device__ __forceinline__ int seg_of(int n, int SS, int K)
@@ -319,7 +332,6 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     const double I0 = th[(size_t)(K + 2) * ld];
     const double N = P.N;
     const double invN = 1.0 / N;
-    const double h3 = (1.0 / (double)spd) / 3.0;
     StepConst<double> sc = step_const<double>(gamma, mu, spd);
 
     // ---------------------------------------------------- forward pass
@@ -408,11 +420,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     for (int k = k_last + 1; k < K; ++k)
         if (active) gout[(size_t)k * ld] = 0.0;  // segments past the window end
 
-    double aS = 0.0, aI = 0.0;
+    double hS = 0.0, hI = 0.0;  // h/6 times the adjoint of (S, I)
     double aD = cost_grad(KIND, W, W, load(q_day + W), ly[W], lw[W], imax);
-    double m6 = sc.h6 * (mu * aD), m3 = h3 * (mu * aD);
+    double m6 = sc.h6 * (mu * aD);
     double muD = 0.0;  // sum over steps of h/6 a_D (I1 + 2 I2 + 2 I3 + I4)
-    RevSums g{0.0, 0.0, 0.0};
+    RevSums g{0.0, 0.0, 0.0, 0.0, 0.0};
     int kr = k_last;  // segment of the reverse position
     set_beta(sc, lb[kr * kWave + lane], invN);
     int seg_lo = kr * SS;  // first step of segment kr
@@ -431,10 +443,10 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
         muD = fma(sc.h6 * aD, Jd, muD);
         aD += cost_grad(KIND, dnext, W, Dd, ly[dnext], lw[dnext], imax);
         m6 = sc.h6 * (mu * aD);
-        m3 = h3 * (mu * aD);
         if (dstart == seg_lo && kr > 0) {
             if (active) gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
-            g.Gsv = 0.0;
+            g.G14 = 0.0;
+            g.G23 = 0.0;
             g.Gv = 0.0;
             --kr;
             seg_lo -= SS;
@@ -561,7 +573,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                 if (rep && rst == rnext)
                     change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
                 if (rep) {
-#pragma unroll 2
+#pragma unroll 4
                     for (int st = hi; st > lo; --st) {
                         replay_step(w, dw);
                         Stages nxt;
@@ -573,7 +585,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                         qs = r[2 * dr];
                         qI = r[2 * dr + kWave];
                         stages(nxt, sc);
-                        rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                        rev_step(cur, hS, hI, sc, m6, g);
                         cur = nxt;
                     }
                     replay_step(w, dw);
@@ -590,11 +602,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                         qs = r[2 * dr];
                         qI = r[2 * dr + kWave];
                         stages(nxt, sc);
-                        rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                        rev_step(cur, hS, hI, sc, m6, g);
                         cur = nxt;
                     }
                 }
-                rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                rev_step(cur, hS, hI, sc, m6, g);
                 r += dr;
                 day_start(lo, Dd, Jd);
                 if (hi == n1 - 1 && m >= 2) park();
@@ -699,10 +711,10 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     qs = r[-4 * kWave];
                     qI = r[-3 * kWave];
                     stages(nxt, sc);
-                    rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                    rev_step(cur, hS, hI, sc, m6, g);
                     cur = nxt;
                 }
-                rev_step(cur, aS, aI, sc, h3, m6, m3, g);
+                rev_step(cur, hS, hI, sc, m6, g);
                 if (lo == dstart) day_start(dstart, Dd, Jd);
                 st = lo - 1;
             }
@@ -756,10 +768,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     }
     }
     if (active) {
+        const double tI = fma(2.0, g.T23, g.T14);  // sum over stages of I_s kbar_s.I
         gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
-        gout[(size_t)K * ld] = -g.tI * gl;
-        gout[(size_t)(K + 1) * ld] = (muD - g.tI) * gl;
-        gout[(size_t)(K + 2) * ld] = (aI - aS) * gl;
+        gout[(size_t)K * ld] = -tI * gl;
+        gout[(size_t)(K + 1) * ld] = (muD - tI) * gl;
+        gout[(size_t)(K + 2) * ld] = ((hI - hS) / sc.h6) * gl;
     }
 }
 
