@@ -90,6 +90,8 @@ enum BwdMode { kBoth = 0, kFwdOnly = 1, kRevOnly = 2 };
 // LDS a wavefront of k_backward may take so that four fit on a compute unit
 // (one per SIMD: 160 KiB of LDS per CU on gfx950).
 constexpr int kBwdLdsBudget = 40 * 1024;
+// The 64-bit operand of the raw buffer load and store builtins.
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
 // Word 3 of a raw buffer resource on gfx9-family chips (gfx950 included):
 // untyped 32-bit data, no swizzle; the workspace loads use it.
 constexpr int kBufferWord3 = 0x00020000;
@@ -303,6 +305,12 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, loff, 0, 0));
     };
     auto load = [&](size_t q) -> double { return load_at(wsb + q * PS); };
+    // a store through a buffer resource on a uniform slot address
+    auto store_at = [&](double *base, double v) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)base, (short)0, kWave * (int)sizeof(double), kBufferWord3);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, loff, 0, 0);
+    };
     const size_t q_sub = 3 * (size_t)a.n_ck_max;
     const size_t q_day = q_sub + 3 * (size_t)a.n_sub_max;
     const size_t q_seg = q_day + (size_t)(a.max_days + 1);
@@ -356,28 +364,57 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
         if (active) slot(q_seg) = y.S;
         int next = next_seg_start(0, SS, K, T);
         int st = 0, next_ck = 0;
-        size_t cq = 0;
         int kseen = 0;
-        for (int day = 0; day < W; ++day) {
-            // the day's observation, read before its steps
-            const double yo = ly[day + 1], wo = lw[day + 1];
-            double jd = 0.0;  // the day's sum of J
-            if (dpc > 0) {
-                // checkpoints at day starts: the loss kernel's day loop
+        // the end of day `day` (the state after its steps, jd the sum of its
+        // steps' J): S if a segment began with the day (it stays as the
+        // segment change formed it: the integration carries s alone), the
+        // cost, Dhat and the sum of J; the day slots are stepped a day at a
+        // time, so their stores take no address arithmetic
+        double *wday = wsb + (q_day + 1) * PS;
+        double *wjd = wsb + q_jd * PS;
+        auto end_of_day = [&](int day, double yo, double wo, double jd)
+                              __attribute__((always_inline)) {
+            if (kf != kseen) {
+                if (active) slot(q_seg + kf) = y.S;
+                kseen = kf;
+            }
+            const double prev = acc;
+            cost_accum(KIND, acc, y.D, yo, wo, day + 1);
+            if (KIND == SIRD_LOSS_MXSE && !(acc == prev)) imax = day + 1;
+            if (active) {
+                store_at(wday, y.D);
+                store_at(wjd, jd);
+            }
+            wday += PS;
+            wjd += PS;
+        };
+        if (dpc > 0) {
+            // checkpoints at day starts: the loss kernel's day loop
+            double *wck = wsb;
+            for (int day = 0; day < W; ++day) {
+                // the day's observation, read before its steps
+                const double yo = ly[day + 1], wo = lw[day + 1];
                 if (st == next) change_segment(y, sc, kf, next, lb, lane, invN, SS, K, T);
                 if (st == next_ck) {
                     if (active) {
-                        slot(cq) = y.s;
-                        slot(cq + 1) = y.I;
-                        slot(cq + 2) = y.S;
+                        store_at(wck, y.s);
+                        store_at(wck + PS, y.I);
+                        store_at(wck + 2 * PS, y.S);
                     }
-                    cq += 3;
+                    wck += 3 * PS;
                     next_ck += sp;
                 }
+                double jd = 0.0;
 #pragma unroll 4
                 for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
                 st += spd;
-            } else {
+                end_of_day(day, yo, wo, jd);
+            }
+        } else {
+            size_t cq = 0;
+            for (int day = 0; day < W; ++day) {
+                const double yo = ly[day + 1], wo = lw[day + 1];
+                double jd = 0.0;
                 advance_marked(y, sc, kf, next, st, st + spd, next_ck, sp, lb, lane, invN, SS,
                                K, T, jd, [&]() {
                                    if (active) {
@@ -387,19 +424,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                                    }
                                    cq += 3;
                                });
-            }
-            if (kf != kseen) {
-                // a segment began with this day; S stays as the segment
-                // change formed it (the integration carries s alone)
-                if (active) slot(q_seg + kf) = y.S;
-                kseen = kf;
-            }
-            const double prev = acc;
-            cost_accum(KIND, acc, y.D, yo, wo, day + 1);
-            if (KIND == SIRD_LOSS_MXSE && !(acc == prev)) imax = day + 1;
-            if (active) {
-                slot(q_day + day + 1) = y.D;
-                slot(q_jd + day) = jd;
+                end_of_day(day, yo, wo, jd);
             }
         }
         const double L = cost_finish(KIND, acc, W);
