@@ -462,11 +462,13 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     const double *pjd = wsb + (q_jd + (size_t)dnext) * PS;
 
     // The step just reversed began day dnext (its Dhat is Dd, the day's sum
-    // of J is Jd): add the mu sum's D part of the day with the day's a_D, add
-    // the cost's gradient, and close segment kr if the step opened it.
-    auto day_start = [&](int dstart, double Dd, double Jd) __attribute__((always_inline)) {
+    // of J is Jd, its observation and weight yd, wd, all read before the
+    // day's steps): add the mu sum's D part of the day with the day's a_D,
+    // add the cost's gradient, and close segment kr if the step opened it.
+    auto day_start = [&](int dstart, double Dd, double Jd, double yd, double wd)
+                         __attribute__((always_inline)) {
         muD = fma(sc.h6 * aD, Jd, muD);
-        aD += cost_grad(KIND, dnext, W, Dd, ly[dnext], lw[dnext], imax);
+        aD += cost_grad(KIND, dnext, W, Dd, yd, wd, imax);
         m6 = sc.h6 * (mu * aD);
         if (dstart == seg_lo && kr > 0) {
             if (active) gout[(size_t)kr * ld] = beta_grad(g, sc.b, Sk, invN) * gl;
@@ -582,18 +584,22 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                 replay_start(rst, lck[0], lck[kWave], lck[2 * kWave]);
                 prefetch();
             }
+            double ps = r[0], pI = r[kWave];
+            double qs = r[dr], qI = r[dr + kWave];
+            r -= dr;
             for (int hi = n1 - 1; hi >= n0; hi -= spd) {
                 const int lo = hi - spd + 1;  // a day start
                 const double Dd = load_at(pday);
                 const double Jd = load_at(pjd);
+                const double yd = ly[dnext], wd = lw[dnext];
+                r += dr;
                 Stages cur;
-                cur.s = r[0];
-                cur.I = r[kWave];
-                // the rows of the next two steps, read ahead: a row is read
-                // two steps before its stages are formed, so the read's
-                // latency hides behind a whole step
-                double ps = r[dr], pI = r[dr + kWave];
-                double qs = r[2 * dr], qI = r[2 * dr + kWave];
+                cur.s = ps;
+                cur.I = pI;
+                ps = qs;
+                pI = qI;
+                qs = r[2 * dr];
+                qI = r[2 * dr + kWave];
                 stages(cur, sc);
                 if (rep && rst == rnext)
                     change_segment(yr, sf, kf, rnext, lb, lane, invN, SS, K, T);
@@ -632,8 +638,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     }
                 }
                 rev_step(cur, hS, hI, sc, m6, g);
-                r += dr;
-                day_start(lo, Dd, Jd);
+                day_start(lo, Dd, Jd, yd, wd);
                 if (hi == n1 - 1 && m >= 2) park();
             }
             // the replayed interval is longer than the walked one (only
@@ -716,6 +721,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                 // into the next replay, whose first step would wait for it)
                 const double Dd = lo == dstart ? load_at(pday) : 0.0;
                 const double Jd = lo == dstart ? load_at(pjd) : 0.0;
+                const double yd = ly[dnext], wd = lw[dnext];
                 // rows of steps st, st - 1, ...; two rows are read ahead,
                 // which below lo reaches the two slack rows under row 0
                 const double *r = lst + (st - b0) * (2 * kWave);
@@ -740,7 +746,7 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     cur = nxt;
                 }
                 rev_step(cur, hS, hI, sc, m6, g);
-                if (lo == dstart) day_start(dstart, Dd, Jd);
+                if (lo == dstart) day_start(dstart, Dd, Jd, yd, wd);
                 st = lo - 1;
             }
         };

@@ -260,111 +260,141 @@ __device__ __forceinline__ double grad_u(const Coord &c, double th, double g)
     return c.lg ? g * th * c.w : g * c.w;
 }
 
-// One lane per parameter vector.  The recursion vector r lives in the lane's
-// column of theta_t until theta_t receives the trial point.
+// Lane j's value of x, read by every lane.
+__device__ __forceinline__ double lane_value(double x, int j)
+{
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, j);
+    const unsigned hi32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), j);
+    return __builtin_bit_cast(double, ((unsigned long long)hi32 << 32) | lo32);
+}
+
+// x_0 + x_1 + ... + x_{d-1} over lanes 0..d-1, added in that order (the
+// rounding of a loop over the dimensions).
+__device__ __forceinline__ double ordered_sum(double x, int d)
+{
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) s = s + lane_value(x, j);
+    return s;
+}
+
+// One wavefront per parameter vector, lane j for dimension j (d <= 64).  All
+// stored pairs are loaded at once, and every dot product is summed across the
+// lanes in the order of the dimensions, so the proposal is the one a loop over
+// the dimensions computes, without a memory round trip per pair.
 __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int t = wave_tile_index();
+    const int j = threadIdx.x & (kWave - 1);
+    const int v = wave_tile_index();  // the vector: tile v / 64, its lane v % 64
+    const int t = v / kWave;
     if (t >= a.n_tiles) return;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
-    const int pl = tl.p0 + lane;
+    const int pl = tl.p0 + v % kWave;
     if (pl >= P.n_part) return;
     const int d = P.n_seg + 3;
+    const bool on = j < d;
     const int m = a.st.m;
     const size_t n = (size_t)P.n_part;
-    const size_t col = (size_t)P.theta_off + pl;
+    const size_t cj = (size_t)P.theta_off + (size_t)(on ? j : 0) * n + pl;
     const size_t pidx = (size_t)P.p_off + pl;
-    const double *lo = a.lo + P.box_off;
-    const double *hi = a.hi + P.box_off;
-    const double *th = a.st.theta + col;
-    const double *g = a.st.grad + col;
-    double *r = a.st.theta_t + col;
+    const int lgl = a.st.log_last;
+    const Coord c = coord_of(a.lo + P.box_off, a.hi + P.box_off, on ? j : 0, d, lgl);
+    const double th = a.st.theta[cj];
+    const double gu = grad_u(c, th, a.st.grad[cj]);
     int cnt = a.st.count[pidx];
     const int head = a.st.head[pidx];
-    const int lgl = a.st.log_last;
-    for (int j = 0; j < d; ++j) r[j * n] = grad_u(coord_of(lo, hi, j, d, lgl), th[j * n], g[j * n]);
+    // the stored pairs, newest first
+    double Sk[kLbfgsMaxM], Yk[kLbfgsMaxM], rho[kLbfgsMaxM];
+#pragma unroll
+    for (int k = 0; k < kLbfgsMaxM; ++k) {
+        Sk[k] = Yk[k] = rho[k] = 0.0;
+        if (k < cnt) {
+            const int slot = ((head - 1 - k) % m + m) % m;
+            Sk[k] = a.st.S[(size_t)slot * a.theta_len + cj];
+            Yk[k] = a.st.Y[(size_t)slot * a.theta_len + cj];
+            rho[k] = a.st.rho[(size_t)slot * a.total_particles + pidx];
+        }
+    }
+    double r = gu;
     double coef[kLbfgsMaxM];
 #pragma unroll
     for (int k = 0; k < kLbfgsMaxM; ++k) {  // newest to oldest
         coef[k] = 0.0;
         if (k < cnt) {
-            const int slot = ((head - 1 - k) % m + m) % m;
-            const double *S = a.st.S + (size_t)slot * a.theta_len + col;
-            const double *Y = a.st.Y + (size_t)slot * a.theta_len + col;
-            double sr = 0.0;
-            for (int j = 0; j < d; ++j) sr = sr + S[j * n] * r[j * n];
-            coef[k] = a.st.rho[(size_t)slot * a.total_particles + pidx] * sr;
-            for (int j = 0; j < d; ++j) r[j * n] = r[j * n] - coef[k] * Y[j * n];
+            coef[k] = rho[k] * ordered_sum(Sk[k] * r, d);
+            r = r - coef[k] * Yk[k];
         }
     }
     double h0 = 1.0;
     if (cnt > 0) {
-        const int slot = ((head - 1) % m + m) % m;
-        const double *S = a.st.S + (size_t)slot * a.theta_len + col;
-        const double *Y = a.st.Y + (size_t)slot * a.theta_len + col;
-        double sy = 0.0, yy = 0.0;
-        for (int j = 0; j < d; ++j) {
-            sy = sy + S[j * n] * Y[j * n];
-            yy = yy + Y[j * n] * Y[j * n];
-        }
+        const double sy = ordered_sum(Sk[0] * Yk[0], d);
+        const double yy = ordered_sum(Yk[0] * Yk[0], d);
         if (yy > 0.0) h0 = sy / yy;
     }
-    for (int j = 0; j < d; ++j) r[j * n] = h0 * r[j * n];
+    r = h0 * r;
 #pragma unroll
     for (int k = kLbfgsMaxM - 1; k >= 0; --k) {  // oldest to newest
         if (k < cnt) {
-            const int slot = ((head - 1 - k) % m + m) % m;
-            const double *S = a.st.S + (size_t)slot * a.theta_len + col;
-            const double *Y = a.st.Y + (size_t)slot * a.theta_len + col;
-            double yr = 0.0;
-            for (int j = 0; j < d; ++j) yr = yr + Y[j * n] * r[j * n];
-            const double b = a.st.rho[(size_t)slot * a.total_particles + pidx] * yr;
-            for (int j = 0; j < d; ++j) r[j * n] = r[j * n] + S[j * n] * (coef[k] - b);
+            const double b = rho[k] * ordered_sum(Yk[k] * r, d);
+            r = r + Sk[k] * (coef[k] - b);
         }
     }
-    // direction p = -r, projected; r[j] <- p[j]
-    double gp = 0.0, pmax = 0.0;
-    for (int j = 0; j < d; ++j) {
-        const Coord c = coord_of(lo, hi, j, d, lgl);
-        const double u = to_u(c, th[j * n]);
-        double pj = -r[j * n];
-        if (c.w == 0.0 || (u <= 0.0 && pj < 0.0) || (u >= 1.0 && pj > 0.0)) pj = 0.0;
-        r[j * n] = pj;
-        gp = gp + grad_u(c, th[j * n], g[j * n]) * pj;
-    }
+    // direction p = -r, projected
+    const double u = to_u(c, th);
+    double p = -r;
+    if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
+    double gp = ordered_sum(gu * p, d);
     if (!(gp < 0.0)) {  // not a descent direction: steepest descent
         cnt = 0;
-        gp = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const Coord c = coord_of(lo, hi, j, d, lgl);
-            const double u = to_u(c, th[j * n]);
-            const double gu = grad_u(c, th[j * n], g[j * n]);
-            double pj = -gu;
-            if (c.w == 0.0 || (u <= 0.0 && pj < 0.0) || (u >= 1.0 && pj > 0.0)) pj = 0.0;
-            r[j * n] = pj;
-            gp = gp + gu * pj;
-        }
+        p = -gu;
+        if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
+        gp = ordered_sum(gu * p, d);
     }
-    a.st.count[pidx] = cnt;
     double alpha = a.st.alpha[pidx];
     if (cnt == 0) {
-        for (int j = 0; j < d; ++j) pmax = fmax(pmax, fabs(r[j * n]));
+        double pmax = 0.0;
+        for (int i = 0; i < d; ++i) pmax = fmax(pmax, fabs(lane_value(p, i)));
         if (pmax > 0.0 && alpha * pmax > 0.01) alpha = 0.01 / pmax;
-        a.st.alpha[pidx] = alpha;
     }
-    a.st.gp[pidx] = gp;
-    for (int j = 0; j < d; ++j) {
-        const Coord c = coord_of(lo, hi, j, d, lgl);
-        if (c.w == 0.0) {
-            r[j * n] = th[j * n];
-            continue;
+    if (j == 0) {
+        a.st.count[pidx] = cnt;
+        a.st.alpha[pidx] = alpha;
+        a.st.gp[pidx] = gp;
+    }
+    if (on) {
+        double tt = th;
+        if (c.w != 0.0) {
+            double ut = u + alpha * p;
+            if (ut < 0.0) ut = 0.0;
+            if (ut > 1.0) ut = 1.0;
+            tt = from_u(c, ut);
         }
-        double ut = to_u(c, th[j * n]) + alpha * r[j * n];
-        if (ut < 0.0) ut = 0.0;
-        if (ut > 1.0) ut = 1.0;
-        r[j * n] = from_u(c, ut);
+        a.st.theta_t[cj] = tt;
+    }
+}
+
+// The accepted step's arrays of one lane (column stride n).  The arrays are
+// distinct buffers; the restrict-qualified parameters let the compiler issue
+// the loads of a loop ahead of its stores instead of one element at a time.
+__device__ __forceinline__ void lbfgs_take(size_t n, int d, const double *lo, const double *hi,
+                                           int lgl, double *__restrict__ th,
+                                           double *__restrict__ g,
+                                           const double *__restrict__ tt,
+                                           const double *__restrict__ gt,
+                                           double *__restrict__ S, double *__restrict__ Y,
+                                           bool keep)
+{
+    if (keep) {
+        for (int j = 0; j < d; ++j) {
+            const Coord c = coord_of(lo, hi, j, d, lgl);
+            S[j * n] = to_u(c, tt[j * n]) - to_u(c, th[j * n]);
+            Y[j * n] = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
+        }
+    }
+    for (int j = 0; j < d; ++j) {
+        th[j * n] = tt[j * n];
+        g[j * n] = gt[j * n];
     }
 }
 
@@ -400,22 +430,13 @@ __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
             const double yj = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
             sy = sy + sj * yj;
         }
+        const int head = a.st.head[pidx];
+        lbfgs_take(n, d, lo, hi, lgl, th, g, tt, gt, a.st.S + (size_t)head * a.theta_len + col,
+                   a.st.Y + (size_t)head * a.theta_len + col, sy > 0.0);
         if (sy > 0.0) {
-            const int head = a.st.head[pidx];
-            double *S = a.st.S + (size_t)head * a.theta_len + col;
-            double *Y = a.st.Y + (size_t)head * a.theta_len + col;
-            for (int j = 0; j < d; ++j) {
-                const Coord c = coord_of(lo, hi, j, d, lgl);
-                S[j * n] = to_u(c, tt[j * n]) - to_u(c, th[j * n]);
-                Y[j * n] = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
-            }
             a.st.rho[(size_t)head * a.total_particles + pidx] = 1.0 / sy;
             a.st.head[pidx] = (head + 1) % m;
             if (a.st.count[pidx] < m) a.st.count[pidx] = a.st.count[pidx] + 1;
-        }
-        for (int j = 0; j < d; ++j) {
-            th[j * n] = tt[j * n];
-            g[j * n] = gt[j * n];
         }
         a.st.f[pidx] = ft;
         a.st.alpha[pidx] = 1.0;
@@ -472,10 +493,11 @@ extern "C" int sird_lbfgs_propose(const sird_batch *batch, const lbfgs_state *st
 {
     int st = check_lbfgs(batch, state, lo, hi, "sird_lbfgs_propose");
     if (st) return st;
-    const int grid = tile_blocks(batch->n_tiles);
-    if (grid == 0) return SIRD_OK;
-    hipLaunchKernelGGL(k_lbfgs_propose, dim3(grid), dim3(256), 0, (hipStream_t)stream,
-                       lbfgs_args(batch, state, lo, hi, 0.0));
+    // a wavefront per parameter vector: 64 per tile, four per block
+    if (batch->n_tiles == 0) return SIRD_OK;
+    const int64_t waves = (int64_t)batch->n_tiles * kWave;
+    hipLaunchKernelGGL(k_lbfgs_propose, dim3((unsigned)((waves + 3) / 4)), dim3(4 * kWave), 0,
+                       (hipStream_t)stream, lbfgs_args(batch, state, lo, hi, 0.0));
     return hip_status(hipGetLastError(), "sird_lbfgs_propose");
 }
 
