@@ -350,11 +350,24 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
                      const pso_state *state, const double *obs, int loss_kind,
                      int n_iters, void *stream);
 
+/* ckpt_interval of the segment-parallel reverse sweep (sird_loss,
+ * sird_loss_backward, sird_loss_backward_workspace,
+ * sird_loss_backward_static).  The forward pass checkpoints every day start;
+ * the reverse sweep then runs every beta segment of every parameter vector
+ * at once (one wavefront per tile and segment) as an affine map of the
+ * adjoint of (S, I) at the segment's end, three adjoints walked through the
+ * segment's steps, and chains the segments' maps per vector.  Three times the
+ * reverse work of the sequential sweep, in K times as many wavefronts: for
+ * batches too small to fill the GPU (a refinement on a few thousand vectors),
+ * where it shortens the call's latency.  The gradient equals the sequential
+ * sweep's up to rounding (not bitwise); the losses are the same. */
+#define SIRD_CKPT_SEGMENTS (-1)
+
 /* Gradient of the cost with respect to theta by the discrete adjoint of the
  * RK4 scheme (reverse mode through every stage).  The forward pass stores
  * the state every ckpt_interval steps in the workspace; the reverse sweep
  * recomputes each interval from its checkpoint.  The result does not depend
- * on ckpt_interval (bitwise).
+ * on ckpt_interval >= 0 (bitwise).
  *   grad_loss: optional particle-indexed upstream gradient (NULL = 1).
  *   grad_theta: output, theta-shaped: grad_loss[p] * dL/dtheta.
  *   loss_out: optional particle-indexed output of the loss itself.
@@ -366,6 +379,7 @@ int sird_pso_iterate(const sird_batch *batch, const pso_params *params,
  *       to the workspace first.  0 = per problem, the whole days that fit
  *       lc steps (lc steps when one day is longer), so that every interval
  *       is replayed once and its checkpoints fall on day starts.
+ *       SIRD_CKPT_SEGMENTS: the segment-parallel reverse sweep above.
  *   from_forward: 0 = run the forward pass here (contents of the workspace
  *       on entry are ignored); 1 = the workspace holds the forward pass of
  *       a sird_loss call with a workspace on the same batch, theta, obs,

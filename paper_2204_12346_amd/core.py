@@ -378,6 +378,12 @@ def pso_complete_move(batch: Batch, params: PsoParams, swarm: Swarm, stream=None
           "pso_complete_move")
 
 
+# ckpt_interval of the segment-parallel reverse sweep (SIRD_CKPT_SEGMENTS):
+# every beta segment of every vector at once, for batches too small to fill
+# the GPU; the gradient equals the sequential sweep's up to rounding.
+CKPT_SEGMENTS = -1
+
+
 def sird_loss_backward_workspace(batch: Batch, ckpt_interval=0):
     return int(lib().sird_loss_backward_workspace(ctypes.byref(batch.c), int(ckpt_interval)))
 

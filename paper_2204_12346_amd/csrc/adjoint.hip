@@ -82,6 +82,9 @@ struct BwdArgs {
     int max_days;    // max W over problems (Dhat slots per particle - 1)
     int max_seg;     // max K over problems (segment-start slots)
     int lds_wave;    // doubles of LDS per wavefront
+    int seg;         // 1: the segment-parallel sweep (checkpoints at every
+                     // day start, then k_seg_transfer and k_seg_combine)
+    int seg_rows;    // steps a wavefront of k_seg_transfer holds in LDS
 };
 
 // Modes of k_backward.
@@ -331,9 +334,11 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     }
 
     // this problem's checkpoint interval; a whole number of days when days
-    // are the unit (the default, with a day no longer than lc steps)
-    const int dpc = (a.s == 0 && spd <= a.lc) ? a.lc / spd : 0;  // days per interval
-    const int sp = a.s > 0 ? a.s : (dpc > 0 ? dpc * spd : a.lc);
+    // are the unit (the default, with a day no longer than lc steps, and the
+    // segment-parallel sweep's forward pass, one day per interval); dpc: the
+    // days per interval, 0 when steps are the unit
+    const int dpc = a.seg ? 1 : ((a.s == 0 && spd <= a.lc) ? a.lc / spd : 0);
+    const int sp = a.seg ? spd : (a.s > 0 ? a.s : (dpc > 0 ? dpc * spd : a.lc));
 
     const double gamma = th[(size_t)K * ld];
     const double mu = th[(size_t)(K + 1) * ld];
@@ -807,6 +812,266 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
     }
 }
 
+// ------------------------------------------------ segment-parallel sweep
+// The reverse sweep is affine in the (scaled) adjoint c = h/6 a of (S, I):
+// a_D never depends on c (D does not feed back), and at any step it is the
+// sum of the cost's dl/dDhat_i over the days after the step, known once the
+// forward pass has saved Dhat.  So the sweep over one beta segment maps the
+// adjoint c_end at the segment's end to c_start = A c_end + b, and the
+// segment's sums (of s_s I_s u, I_s u and I_s kbar.I over its stages) are
+// affine in c_end too.  k_seg_transfer runs every segment of every parameter
+// vector at once (a wavefront per tile and segment, replaying each day from
+// the checkpoint at its start) and walks three adjoints backwards through
+// the segment, with the same reverse step as the sequential sweep: c = (1, 0)
+// and c = (0, 1) without a_D (the columns of A, and the sums' slopes), and
+// c = 0 with a_D (b, and the sums' offsets).  k_seg_combine then chains the
+// segments from the last, one lane per vector.  The gradient is the
+// sequential sweep's up to rounding (its sums are added in another order).
+
+// Workspace slots of one segment's affine map, after the two tail slots:
+// A (c_S, c_I of both unit walks), b, and per walk the sums of s_s I_s u,
+// I_s u and I_s kbar.I, then the segment's part of the mu sum's D part.
+constexpr int kSegSlots = 16;
+
+// The workspace column of one lane: slot q of particle p at ws[q * stride + p],
+// addressed as a uniform base (the tile's first particle) plus the lane's
+// byte offset.
+struct WsLane {
+    double *base;
+    size_t stride;
+    uint32_t off;
+
+    __device__ __forceinline__ double load(size_t q) const
+    {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(base + q * stride), (short)0, kWave * (int)sizeof(double), kBufferWord3);
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    __device__ __forceinline__ void store(size_t q, double v) const
+    {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(base + q * stride), (short)0, kWave * (int)sizeof(double), kBufferWord3);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, 0);
+    }
+};
+
+// Slots of the segment-parallel sweep's workspace (no stored sub-interval
+// starts): checkpoint d at 3d .. 3d + 2 (s, I, S), then Dhat, S at every
+// segment start, the sums of J, the tail (MXSE's day, the loss) and the
+// segments' affine maps.
+struct SegSlots {
+    size_t day, seg, jd, tail, map;
+    __device__ __forceinline__ SegSlots(const BwdArgs &a)
+    {
+        day = 3 * (size_t)a.n_ck_max;
+        seg = day + (size_t)(a.max_days + 1);
+        jd = seg + (size_t)a.max_seg;
+        tail = jd + (size_t)a.max_days;
+        map = tail + 2;
+    }
+};
+
+// One wavefront per (tile, segment), one lane per parameter vector.
+template <int KIND>
+__global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
+{
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = wave_uniform((int)blockIdx.x);
+    const int t = wv / a.max_seg;
+    const int k = wv - t * a.max_seg;
+    if (t >= a.n_tiles) return;
+    const sird_tile tl = a.tiles[t];
+    const sird_problem P = a.probs[tl.prob];
+    const int W = P.n_days, spd = P.steps_per_day, K = P.n_seg, n = P.n_part;
+    const int T = W * spd;
+    const int SS = (int)min((long)P.seg_days * spd, (long)T + 1);
+    const int k_last = seg_of(T - 1, SS, K);
+    if (k > k_last) return;  // no step of the window in this segment
+    const int pl = tl.p0 + lane;
+    const bool active = pl < n;
+    const int pc = active ? pl : n - 1;
+    const size_t ld = (size_t)n;
+    const double *th = a.theta + P.theta_off + pc;
+    const WsLane ws{a.ws + (size_t)(P.p_off + tl.p0), (size_t)a.P,
+                    (uint32_t)(pc - tl.p0) * (uint32_t)sizeof(double)};
+    const SegSlots q(a);
+    // LDS of the wavefront: the deceased counts and their weights, then
+    // [2 slack][seg_rows][2][64], (s, I) of the lane before each step of one
+    // piece of a day (the walk's read-ahead touches the slack rows below
+    // row 0 and never uses them)
+    double *const ly = lds;
+    double *const lw = ly + (a.max_days + 1);
+    double *const lst = lw + (a.max_days + 1) + 4 * kWave + lane;
+    {
+        const double *y = a.obs + P.obs_off + (size_t)(a.obs_series - 1) * (W + 1);
+        for (int i = lane; i <= W; i += kWave) {
+            const double yi = y[i];
+            ly[i] = yi;
+            lw[i] = 1.0 / fmax(yi, 1.0);
+        }
+        wave_sync();
+    }
+    const double gamma = th[(size_t)K * ld];
+    const double mu = th[(size_t)(K + 1) * ld];
+    StepConst<double> sc = step_const<double>(gamma, mu, spd);
+    set_beta(sc, th[(size_t)k * ld], 1.0 / P.N);
+    const int imax = (int)ws.load(q.tail);
+    // the segment's days d0 .. d1 - 1 (segments start at day starts)
+    const int d0 = (k * SS) / spd;
+    const int d1 = k == k_last ? W : ((k + 1) * SS) / spd;
+    // a_D over the segment's last day: the cost's gradient at days W down to
+    // d1, added in the sequential sweep's order; Dhat is loaded sixteen days
+    // at a time (one memory round trip per sixteen days, not per day)
+    double aD = cost_grad(KIND, W, W, ws.load(q.day + W), ly[W], lw[W], imax);
+    for (int i0 = W - 1; i0 >= d1; i0 -= 16) {
+        double Dv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Dv[i] = ws.load(q.day + (size_t)max(i0 - i, d1));
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i0 - i >= d1)
+                aD += cost_grad(KIND, i0 - i, W, Dv[i], ly[i0 - i], lw[i0 - i], imax);
+    }
+    // the three walks: unit c_S, unit c_I (no a_D), and c = 0 with a_D
+    double c1S = 1.0, c1I = 0.0, c2S = 0.0, c2I = 1.0, c3S = 0.0, c3I = 0.0;
+    RevSums g1{0.0, 0.0, 0.0, 0.0, 0.0}, g2 = g1, g3 = g1;
+    double muD = 0.0;
+    const int R = a.seg_rows;
+    const int npieces = (spd + R - 1) / R;
+    // the day's checkpoint, Dhat and sum of J are loaded a day ahead
+    double nDd = ws.load(q.day + d1 - 1), nJd = ws.load(q.jd + d1 - 1);
+    double nck_s = ws.load(3 * (size_t)(d1 - 1)), nck_I = ws.load(3 * (size_t)(d1 - 1) + 1);
+    for (int d = d1 - 1; d >= d0; --d) {
+        const double m6 = sc.h6 * (mu * aD);
+        const double Dd = nDd, Jd = nJd, ck_s = nck_s, ck_I = nck_I;
+        if (d > d0) {
+            nDd = ws.load(q.day + d - 1);
+            nJd = ws.load(q.jd + d - 1);
+            nck_s = ws.load(3 * (size_t)(d - 1));
+            nck_I = ws.load(3 * (size_t)(d - 1) + 1);
+        }
+        // the day's steps in pieces of at most R, the last piece first; a
+        // piece is replayed from the day's checkpoint
+        for (int j = npieces - 1; j >= 0; --j) {
+            const int b0 = j * R;
+            const int b1 = min(spd, b0 + R);
+            SirdState<double> y;
+            y.s = ck_s;
+            y.I = ck_I;
+            y.S = y.Rr = y.D = 0.0;
+            y.eS = y.eI = y.eR = y.eD = 0.0;
+            for (int i = 0; i < b0; ++i) rk4_step<double, false, false>(y, sc);
+            double *w = lst;
+            for (int i = b0; i < b1; ++i, w += 2 * kWave) {
+                w[0] = y.s;
+                w[kWave] = y.I;
+                rk4_step<double, false, false>(y, sc);
+            }
+            const double *r = lst + (size_t)(b1 - b0 - 1) * (2 * kWave);
+            Stages cur;
+            cur.s = r[0];
+            cur.I = r[kWave];
+            double ps = r[-2 * kWave], pI = r[-kWave];
+            stages(cur, sc);
+            for (int i = b1 - 1; i > b0; --i) {
+                Stages nxt;
+                nxt.s = ps;
+                nxt.I = pI;
+                r -= 2 * kWave;
+                ps = r[-2 * kWave];
+                pI = r[-kWave];
+                stages(nxt, sc);
+                rev_step(cur, c1S, c1I, sc, 0.0, g1);
+                rev_step(cur, c2S, c2I, sc, 0.0, g2);
+                rev_step(cur, c3S, c3I, sc, m6, g3);
+                cur = nxt;
+            }
+            rev_step(cur, c1S, c1I, sc, 0.0, g1);
+            rev_step(cur, c2S, c2I, sc, 0.0, g2);
+            rev_step(cur, c3S, c3I, sc, m6, g3);
+        }
+        // the day start, as the sequential sweep takes it
+        muD = fma(sc.h6 * aD, Jd, muD);
+        aD += cost_grad(KIND, d, W, Dd, ly[d], lw[d], imax);
+    }
+    if (active) {
+        const size_t m = q.map + (size_t)kSegSlots * k;
+        const double out[kSegSlots] = {c1S,
+                                       c1I,
+                                       c2S,
+                                       c2I,
+                                       c3S,
+                                       c3I,
+                                       fma(2.0, g1.G23, g1.G14),
+                                       fma(2.0, g2.G23, g2.G14),
+                                       fma(2.0, g3.G23, g3.G14),
+                                       g1.Gv,
+                                       g2.Gv,
+                                       g3.Gv,
+                                       fma(2.0, g1.T23, g1.T14),
+                                       fma(2.0, g2.T23, g2.T14),
+                                       fma(2.0, g3.T23, g3.T14),
+                                       muD};
+#pragma unroll
+        for (int i = 0; i < kSegSlots; ++i) ws.store(m + i, out[i]);
+    }
+}
+
+// One lane per parameter vector: the segments' maps chained from the last
+// segment (where c = 0) to the first, the gradient written.
+__global__ void __launch_bounds__(256) k_seg_combine(BwdArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = wave_tile_index();
+    if (t >= a.n_tiles) return;
+    const sird_tile tl = a.tiles[t];
+    const sird_problem P = a.probs[tl.prob];
+    const int W = P.n_days, spd = P.steps_per_day, K = P.n_seg, n = P.n_part;
+    const int T = W * spd;
+    const int SS = (int)min((long)P.seg_days * spd, (long)T + 1);
+    const int k_last = seg_of(T - 1, SS, K);
+    const int pl = tl.p0 + lane;
+    const bool active = pl < n;
+    const int pc = active ? pl : n - 1;
+    const size_t ld = (size_t)n;
+    const double *th = a.theta + P.theta_off + pc;
+    const WsLane ws{a.ws + (size_t)(P.p_off + tl.p0), (size_t)a.P,
+                    (uint32_t)(pc - tl.p0) * (uint32_t)sizeof(double)};
+    const SegSlots q(a);
+    if (active && a.loss_out) a.loss_out[P.p_off + pl] = ws.load(q.tail + 1);
+    const double gl = a.grad_loss ? a.grad_loss[P.p_off + pc] : 1.0;
+    double *gout = a.grad + P.theta_off + pc;
+    for (int k = k_last + 1; k < K; ++k)
+        if (active) gout[(size_t)k * ld] = 0.0;  // segments past the window end
+    const double invN = 1.0 / P.N;
+    double cS = 0.0, cI = 0.0, tI = 0.0, muD = 0.0;
+    for (int k = k_last; k >= 0; --k) {
+        const size_t m = q.map + (size_t)kSegSlots * k;
+        double v[kSegSlots];
+#pragma unroll
+        for (int i = 0; i < kSegSlots; ++i) v[i] = ws.load(m + i);
+        const double G = fma(v[6], cS, fma(v[7], cI, v[8]));
+        const double Gv = fma(v[9], cS, fma(v[10], cI, v[11]));
+        const double Tk = fma(v[12], cS, fma(v[13], cI, v[14]));
+        const double b = th[(size_t)k * ld] * invN;
+        const double g = b != 0.0 ? (G / b) * invN : (ws.load(q.seg + k) * Gv) * invN;
+        if (active) gout[(size_t)k * ld] = g * gl;
+        tI += Tk;
+        muD += v[15];
+        const double nS = fma(v[0], cS, fma(v[2], cI, v[4]));
+        const double nI = fma(v[1], cS, fma(v[3], cI, v[5]));
+        cS = nS;
+        cI = nI;
+    }
+    if (active) {
+        const double h6 = step_const<double>(0.0, 0.0, spd).h6;
+        gout[(size_t)K * ld] = -tI * gl;
+        gout[(size_t)(K + 1) * ld] = (muD - tI) * gl;
+        gout[(size_t)(K + 2) * ld] = ((cI - cS) / h6) * gl;
+    }
+}
+
 // Steps per LDS sub-interval: as many as fit the wavefront's share of LDS
 // (four wavefronts per compute unit) next to the observations and betas,
 // within [kLcMin, kLcMax].
@@ -839,6 +1104,9 @@ static int64_t checkpoints(const sird_batch *b, int ckpt_interval)
 // segment start, every day's sum of J, the day MXSE peaks on and the loss.
 static size_t ws_slots(const sird_batch *b, int ckpt_interval)
 {
+    if (ckpt_interval == SIRD_CKPT_SEGMENTS)
+        return (size_t)(3 * (int64_t)b->max_days + b->max_days + 1 + (b->max_d - 3) +
+                        b->max_days + 2 + (int64_t)kSegSlots * (b->max_d - 3));
     const int lc = lds_steps(b);
     const int64_t n_ck = checkpoints(b, ckpt_interval);
     const int64_t n_sub =
@@ -895,7 +1163,9 @@ static int adjoint_prepare(const sird_batch *batch, const double *theta, const d
         return fail(SIRD_EINVAL, w + ": the adjoint needs a deceased-count cost (loss_kind 0..4)");
     if (batch->models != 1 << SIRD_MODEL_RK4_SEGMENTS)
         return fail(SIRD_EINVAL, w + ": the adjoint supports the RK4 segment model only");
-    if (ckpt_interval < 0) return fail(SIRD_EINVAL, w + ": ckpt_interval < 0");
+    const bool seg = ckpt_interval == SIRD_CKPT_SEGMENTS;
+    if (ckpt_interval < 0 && !seg)
+        return fail(SIRD_EINVAL, w + ": ckpt_interval < 0 (and not SIRD_CKPT_SEGMENTS)");
     if (batch->obs_len < 1) return fail(SIRD_EINVAL, w + ": batch planned without obs");
     *a = BwdArgs{};
     a->probs = batch->probs;
@@ -908,12 +1178,20 @@ static int adjoint_prepare(const sird_batch *batch, const double *theta, const d
     a->P = batch->total_particles;
     a->n_tiles = batch->n_tiles;
     a->obs_series = batch->obs_series;
-    a->s = ckpt_interval;
+    a->s = seg ? 0 : ckpt_interval;
     a->lc = lds_steps(batch);
-    a->n_ck_max = (int)checkpoints(batch, ckpt_interval);
-    a->n_sub_max = ckpt_interval > a->lc ? (ckpt_interval + a->lc - 1) / a->lc : 0;
+    a->n_ck_max = seg ? batch->max_days : (int)checkpoints(batch, ckpt_interval);
+    a->n_sub_max = !seg && ckpt_interval > a->lc ? (ckpt_interval + a->lc - 1) / a->lc : 0;
     a->max_days = batch->max_days;
     a->max_seg = batch->max_d - 3;
+    a->seg = seg ? 1 : 0;
+    if (seg) {
+        // rows of a k_seg_transfer wavefront: what fits kBwdLdsBudget next to
+        // the observations, their weights and two slack rows
+        const long rows = (kBwdLdsBudget / 8L - 2L * (batch->max_days + 1)) / (2L * kWave) - 2;
+        if (rows < 1) return fail(SIRD_EINVAL, w + ": window too long for LDS");
+        a->seg_rows = (int)(rows < kLcMax ? rows : kLcMax);
+    }
     a->lds_wave = 2 * (batch->max_days + 1) + kWave * (a->max_seg + 3 + 2 * (4 + a->lc));
     *lds = sizeof(double) * (size_t)a->lds_wave;
     if (*lds > 65536) return fail(SIRD_EINVAL, w + ": window too long for LDS");
@@ -940,11 +1218,56 @@ static int bwd_waves_per_block(size_t lds_per_wave)
     return 4 * lds_per_wave <= (size_t)lim ? 4 : 1;
 }
 
+static void launch_seg_transfer(int kind, int grid, size_t lds, hipStream_t s,
+                                const BwdArgs &a)
+{
+    switch (kind) {
+    case SIRD_LOSS_SSRE:
+        hipLaunchKernelGGL(k_seg_transfer<SIRD_LOSS_SSRE>, dim3(grid), dim3(kWave), lds, s, a);
+        break;
+    case SIRD_LOSS_MSE:
+        hipLaunchKernelGGL(k_seg_transfer<SIRD_LOSS_MSE>, dim3(grid), dim3(kWave), lds, s, a);
+        break;
+    case SIRD_LOSS_MXSE:
+        hipLaunchKernelGGL(k_seg_transfer<SIRD_LOSS_MXSE>, dim3(grid), dim3(kWave), lds, s, a);
+        break;
+    case SIRD_LOSS_MAE:
+        hipLaunchKernelGGL(k_seg_transfer<SIRD_LOSS_MAE>, dim3(grid), dim3(kWave), lds, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_seg_transfer<SIRD_LOSS_MAPE>, dim3(grid), dim3(kWave), lds, s, a);
+        break;
+    }
+}
+
+// The reverse sweep of the segment-parallel form: the segments' maps, then
+// their chain (grid: tiles).
+static int seg_reverse(int loss_kind, int grid, hipStream_t stream, const BwdArgs &a,
+                       const char *who)
+{
+    const size_t lds = sizeof(double) * (2 * (size_t)(a.max_days + 1) +
+                                         (size_t)kWave * 2 * (size_t)(a.seg_rows + 2));
+    launch_seg_transfer(loss_kind, grid * a.max_seg, lds, stream, a);
+    int st = hip_status(hipGetLastError(), who);
+    if (st) return st;
+    hipLaunchKernelGGL(k_seg_combine, dim3(tile_blocks(grid)), dim3(256), 0, stream, a);
+    return hip_status(hipGetLastError(), who);
+}
+
 // grid: tiles (one wavefront each); lds: bytes per wavefront.
 static int adjoint_launch(int mode, int loss_kind, int grid, size_t lds, hipStream_t stream,
                           const BwdArgs &a, const char *who)
 {
     if (grid == 0) return SIRD_OK;
+    if (a.seg && mode != kFwdOnly) {
+        // the forward pass (checkpoints at every day start) unless it is
+        // saved, then the segments' maps and their chain
+        if (mode == kBoth) {
+            const int st = adjoint_launch(kFwdOnly, loss_kind, grid, lds, stream, a, who);
+            if (st) return st;
+        }
+        return seg_reverse(loss_kind, grid, stream, a, who);
+    }
     const int wpb = bwd_waves_per_block(lds);
     const int blocks = (grid + wpb - 1) / wpb;
     const int block = wpb * kWave;
@@ -986,7 +1309,7 @@ using namespace sird;
 extern "C" size_t sird_loss_backward_workspace(const sird_batch *batch, int ckpt_interval)
 {
     if (check_batch(batch, "sird_loss_backward_workspace")) return 0;
-    if (ckpt_interval < 0) return 0;
+    if (ckpt_interval < 0 && ckpt_interval != SIRD_CKPT_SEGMENTS) return 0;
     return adjoint_workspace_bytes(batch, ckpt_interval);
 }
 

@@ -230,6 +230,18 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     # an interval longer than the sub-interval adds 3 slots per sub-interval
     ws100 = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 100)
     assert ws100 == (3 * 3 + 3 * int(np.ceil(100 / lc)) + 46 + 4 + 45 + 2) * 165 * 8
+    # the segment-parallel sweep: a checkpoint per day (3 x 45), Dhat, S at
+    # every segment start, the sums of J, the tail and 16 slots per segment
+    text = open(HEADER).read()
+    m = re.search(r"#define SIRD_CKPT_SEGMENTS \((-?\d+)\)", text)
+    assert m and int(m.group(1)) == core.CKPT_SEGMENTS
+    wseg = lib.sird_loss_backward_workspace(ctypes.byref(b.c), core.CKPT_SEGMENTS)
+    assert wseg == (3 * 45 + 46 + 4 + 45 + 2 + 16 * 4) * 165 * 8
+    assert lib.sird_loss_backward_workspace(ctypes.byref(b.c), -2) == 0
+    st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
+                                dummy.data_ptr(), None, -2, 0, ctypes.c_void_p(4096), 1 << 30,
+                                None)
+    assert st == L.SIRD_EINVAL and b"SIRD_CKPT_SEGMENTS" in lib.sird_last_error()
     # too small a workspace is reported before anything is enqueued
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
                                 dummy.data_ptr(), None, 0, 0, ctypes.c_void_p(4096), 16, None)
@@ -286,7 +298,7 @@ def test_loss_with_checkpoint_workspace_checks_on_host(L):
     need = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 10)
     assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, 10, big, need - 1, None) == L.SIRD_ENOSPACE
     assert b"workspace too small" in lib.sird_last_error()
-    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, -1, big, 1 << 40, None) == L.SIRD_EINVAL
+    assert lib.sird_loss(ctypes.byref(b.c), d, d, 0, d, -2, big, 1 << 40, None) == L.SIRD_EINVAL
     assert lib.sird_loss(ctypes.byref(b.c), d, d, 5, d, 10, big, 1 << 40, None) == L.SIRD_EINVAL
     assert lib.sird_loss(ctypes.byref(b.c), d, d, 1, d, 10, ctypes.c_void_p(4096 + 8), 1 << 40,
                          None) == L.SIRD_EINVAL
@@ -323,7 +335,7 @@ def test_static_gradient_entry_checks_on_host(L):
     for args, what in (((d, d, 5, None, d, None, 0), b"deceased-count"),
                        ((d, d, 0, None, None, None, 0), b"grad_theta"),
                        ((None, d, 0, None, d, None, 0), b"NULL"),
-                       ((d, d, 0, None, d, None, -1), b"ckpt_interval")):
+                       ((d, d, 0, None, d, None, -2), b"ckpt_interval")):
         assert lib.sird_loss_backward_static(ctypes.byref(small.c), *args, None) == L.SIRD_EINVAL
         assert what in lib.sird_last_error()
     small.c.dtype = L.SIRD_F32

@@ -260,3 +260,108 @@ def test_mixed_sweeps_in_one_batch_equal_single_launches():
         for p in (0, n_parts[r] - 1):
             assert_grad_close(G[r][p], *oracle_grad(prob, ths[r][p], f.y, "ssre"),
                               f"problem {r} particle {p}")
+
+
+# ------------------------------------------------ segment-parallel sweep
+SEG = S.CKPT_SEGMENTS
+
+
+@pytest.mark.parametrize("shape", ["c1", "c2"])
+@pytest.mark.parametrize("kind", ["ssre", "mse", "mxse", "mae", "mape"])
+def test_segment_parallel_sweep_matches_forward_mode(shape, kind):
+    """The segment-parallel reverse sweep against the oracle's forward-mode
+    gradient (the same per-component bar as the sequential sweep), its
+    losses bitwise the sequential call's, and its gradient the sequential
+    sweep's to rounding."""
+    f = (synth.c1() if shape == "c1" else synth.c2()).fits[0]
+    P = 70
+    th = random_theta(f, P, seed=3)
+    th[:, :f.K] *= 0.5
+    th[P - 10:] = near_truth(f, 10, seed=30)
+    b = make_batch([f], [P])
+    theta, obs = b.pack_theta([th]), b.pack_obs([f.y])
+    print(f"case segment sweep {shape}/{kind}", flush=True)
+    g, L = S.sird_loss_backward(b, theta, obs, kind, loss_out=b.empty_particles(),
+                                ckpt_interval=SEG)
+    g0, L0 = S.sird_loss_backward(b, theta, obs, kind, loss_out=b.empty_particles())
+    assert torch.equal(L, L0)
+    gg, g0g = b.unpack_theta(g)[0], b.unpack_theta(g0)[0]
+    prob = oracle_problem(f)
+    worst, worst0 = [], []
+    for p in list(range(0, P - 10, 3)) + list(range(P - 10, P)):
+        gr, sc = oracle_grad(prob, th[p], f.y, kind)
+        assert_grad_close(gg[p], gr, sc, f"{shape}/{kind}/particle {p}", worst)
+        # against the sequential sweep: both are the discrete adjoint, summed
+        # in different orders
+        assert_grad_close(gg[p], g0g[p], sc, f"{shape}/{kind}/particle {p} vs sequential",
+                          worst0)
+    print(f"{shape}/{kind}: worst per-component relative error {max(worst):.2e} "
+          f"(oracle), {max(worst0):.2e} (sequential sweep)")
+
+
+@pytest.mark.parametrize("spd", [1, 3, 10, 20, 40])
+def test_segment_parallel_sweep_edge_cases(spd):
+    """One to forty steps per day (forty: more than a transfer wavefront's
+    LDS rows, so a day is walked in pieces), two-step and one-day segments,
+    a segment with beta = 0, segments past the window end; against the
+    oracle."""
+    f = synth.c2().fits[0]
+    f.spd = spd
+    f.W = 40 if spd == 40 else f.W
+    f.seg_days = 2 if spd == 1 else (1 if spd == 20 else f.seg_days)
+    f.K = min(f.K, (f.W + f.seg_days - 1) // f.seg_days + 2)  # two segments past the end
+    f.lo, f.hi = np.concatenate([f.lo[:f.K], f.lo[-3:]]), np.concatenate([f.hi[:f.K], f.hi[-3:]])
+    f.y = f.y[:f.W + 1]
+    th = random_theta(f, 40, seed=11)
+    th[:, :f.K] *= 0.5
+    th[:, 1] = 0.0  # no transmission in the second segment
+    b = make_batch([f], [40])
+    theta, obs = b.pack_theta([th]), b.pack_obs([f.y])
+    print(f"case segment sweep spd={spd} W={f.W} K={f.K} seg_days={f.seg_days}", flush=True)
+    g, _ = S.sird_loss_backward(b, theta, obs, "ssre", ckpt_interval=SEG)
+    h = b.unpack_theta(g)[0]
+    prob = oracle_problem(f)
+    for p in range(0, 40, 5):
+        assert_grad_close(h[p], *oracle_grad(prob, th[p], f.y, "ssre"), f"spd {spd} particle {p}")
+
+
+@pytest.mark.parametrize("kind", ["ssre", "mxse"])
+def test_segment_parallel_sweep_uneven_batch_and_saved_forward(kind):
+    """An uneven batch (different windows, populations including 0 and 1,
+    upstream gradients): the segment-parallel gradient equals its
+    single-problem launches bitwise and the sequential sweep's to rounding;
+    sird_loss with the segment workspace, then the reverse sweep alone,
+    equals the self-contained call bitwise."""
+    wl = synth.c3(regions=list(range(6)))
+    n_parts = [100, 64, 1, 0, 33, 70]
+    ths = [random_theta(f, n, seed=40 + r) for r, (f, n) in enumerate(zip(wl.fits, n_parts))]
+    b = make_batch(wl.fits, n_parts)
+    theta, obs = b.pack_theta(ths), b.pack_obs([f.y for f in wl.fits])
+    scale = torch.linspace(-1, 2, b.total_particles, dtype=torch.float64, device="cuda")
+    print(f"case segment sweep uneven batch {kind}", flush=True)
+    g, L = S.sird_loss_backward(b, theta, obs, kind, grad_loss=scale,
+                                loss_out=b.empty_particles(), ckpt_interval=SEG)
+    g0, L0 = S.sird_loss_backward(b, theta, obs, kind, grad_loss=scale,
+                                  loss_out=b.empty_particles())
+    assert torch.equal(L, L0)
+    ws = torch.empty(S.sird_loss_backward_workspace(b, SEG), dtype=torch.uint8, device="cuda")
+    L_ws = S.sird_loss(b, theta, obs, kind, workspace=ws, ckpt_interval=SEG)
+    g_rev, L_rev = S.sird_loss_backward(b, theta, obs, kind, grad_loss=scale,
+                                        loss_out=b.empty_particles(), ckpt_interval=SEG,
+                                        workspace=ws, from_forward=True)
+    assert torch.equal(g_rev, g) and torch.equal(L_rev, L) and torch.equal(L_ws, L)
+    G, G0 = b.unpack_theta(g), b.unpack_theta(g0)
+    sc = b.split_particles(scale)
+    for r, f in enumerate(wl.fits):
+        if n_parts[r] == 0:
+            continue
+        bs = make_batch([f], [n_parts[r]])
+        gs, _ = S.sird_loss_backward(bs, bs.pack_theta([ths[r]]), bs.pack_obs([f.y]), kind,
+                                     grad_loss=torch.from_numpy(sc[r]).cuda(),
+                                     ckpt_interval=SEG)
+        assert np.array_equal(bs.unpack_theta(gs)[0], G[r]), r
+        prob = oracle_problem(f)
+        for p in {0, n_parts[r] - 1}:
+            _, scl = oracle_grad(prob, ths[r][p], f.y, kind)
+            assert_grad_close(G[r][p], G0[r][p], np.abs(sc[r][p]) * scl,
+                              f"region {r} particle {p} vs sequential")
