@@ -410,8 +410,13 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
                     next_ck += sp;
                 }
                 double jd = 0.0;
+                if (spd % 10 == 0) {
+#pragma unroll 10
+                    for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
+                } else {
 #pragma unroll 4
-                for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
+                    for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
+                }
                 st += spd;
                 end_of_day(day, yo, wo, jd);
             }

@@ -263,8 +263,14 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
             for (; day < dend; ++day) {
                 if (WITH_S) rescale(y, sc);
                 const DayObs o = day_obs(day + 1);
+                // a day of ten or twenty steps runs without a remainder loop
+                if (spd % 10 == 0) {
+#pragma unroll 10
+                    for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
+                } else {
 #pragma unroll 4
-                for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
+                    for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
+                }
                 emit(day + 1, o);
             }
         }

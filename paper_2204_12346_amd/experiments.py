@@ -249,7 +249,7 @@ def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=2
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
     loss = rb.empty_particles()
-    ci = 0  # the library's default checkpoint interval
+    ci = fit.default_ckpt_interval(rb)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
                      device=b.device)
     best = curve[-1][1]
@@ -276,7 +276,7 @@ def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10)
     rb = Batch(specs, device=b.device, obs_series=b.obs_series)
     theta = sird_gather(b, sw.pbest_x, params.lo, rb, idx, k)
     st = LbfgsState(rb, theta)
-    ci = 0  # the library's default checkpoint interval
+    ci = fit.default_ckpt_interval(rb)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
                      device=b.device)
     sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f,

@@ -13,11 +13,20 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from .core import (Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm, pso_init,
-                   pso_topk, sird_adam_step, sird_gather, sird_integrate, sird_lbfgs_accept,
-                   sird_lbfgs_propose, sird_loss, sird_loss_backward,
+from .core import (CKPT_SEGMENTS, Batch, Graph, LbfgsState, ProblemSpec, PsoParams, Swarm,
+                   pso_init, pso_topk, sird_adam_step, sird_gather, sird_integrate,
+                   sird_lbfgs_accept, sird_lbfgs_propose, sird_loss, sird_loss_backward,
                    sird_loss_backward_workspace, sird_pso_iterate)
 
+
+def default_ckpt_interval(batch: Batch) -> int:
+    """Checkpoint interval of a refinement's gradients: the segment-parallel
+    sweep (CKPT_SEGMENTS) when the batch's tiles times its segments fit in
+    four wavefronts per SIMD, where the sequential sweep (one wavefront per
+    tile) would leave most SIMDs idle and the call's latency is what counts;
+    else the sequential sweep's default (0)."""
+    simds = 4 * torch.cuda.get_device_properties(batch.device).multi_processor_count
+    return CKPT_SEGMENTS if batch.n_tiles * (batch.c.max_d - 3) <= 4 * simds else 0
 
 def run_swarm(batch: Batch, params: PsoParams, obs, kind="ssre", iters=100, hist=True,
               graph_chunk=0, swarm: Optional[Swarm] = None, init=True) -> Swarm:
@@ -60,7 +69,7 @@ def refine_topk(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre",
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
     if ckpt_interval is None:
-        ckpt_interval = 0  # the library's default (whole days per LDS slice)
+        ckpt_interval = default_ckpt_interval(rb)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
@@ -92,7 +101,7 @@ def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre",
     loss and gradient at st.theta.  callback(round) every check_every rounds
     may return True to stop."""
     if ckpt_interval is None:
-        ckpt_interval = 0  # the library's default (whole days per LDS slice)
+        ckpt_interval = default_ckpt_interval(rb)
     ws = workspace
     if ws is None:
         ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8),
@@ -120,7 +129,7 @@ def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre"
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
     if ckpt_interval is None:
-        ckpt_interval = 0  # the library's default (whole days per LDS slice)
+        ckpt_interval = default_ckpt_interval(rb)
     st = LbfgsState(rb, theta, m=m)
     ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
                      device=batch.device)
