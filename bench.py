@@ -281,6 +281,9 @@ def extra_tasks():
     # replayed twice
     t.append(("c4_gradients_65536x7300steps_interval90",
               lambda: X.gradients_per_s(*synth.c4(), ckpt_interval=90)))
+    # a refinement's gradient call (32 and 1024 vectors of the segmented
+    # fit): the sequential and the segment-parallel reverse sweep
+    t.append(("c2_refine_gradient_latency", lambda: X.refine_gradient_latency(synth.c2())))
     # M2: plain swarm against swarm + refinement of the top k by the adjoint
     # (projected L-BFGS, and the projected Adam the protocol names, with a
     # decaying step)
@@ -348,6 +351,13 @@ def summarize(ex):
             "ckpt_interval": g["ckpt_interval"],
             "gradients_per_s_interval90": g90.get("gradients_per_s"),
         }
+    lat = ex.get("c2_refine_gradient_latency")
+    if lat:
+        out["gradients"] = out.get("gradients", {})
+        out["gradients"]["refinement_latency_ms"] = {
+            "workload": "one gradient call on k vectors of the segmented fit (180 days, "
+                        "dt 0.1, 13 segments)",
+            **{k: {n: round(v, 4) for n, v in row.items()} for k, row in lat.items()}}
     o = {}
     for k in ("c1_constant_beta_256x60d", "c2_segmented_8192x180d_f64",
               "c2_segmented_8192x180d_f32"):

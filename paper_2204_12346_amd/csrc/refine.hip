@@ -260,21 +260,17 @@ __device__ __forceinline__ double grad_u(const Coord &c, double th, double g)
     return c.lg ? g * th * c.w : g * c.w;
 }
 
-// Lane j's value of x, read by every lane.
-__device__ __forceinline__ double lane_value(double x, int j)
-{
-    const unsigned long long bits = __builtin_bit_cast(unsigned long long, x);
-    const unsigned lo32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, j);
-    const unsigned hi32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), j);
-    return __builtin_bit_cast(double, ((unsigned long long)hi32 << 32) | lo32);
-}
-
 // x_0 + x_1 + ... + x_{d-1} over lanes 0..d-1, added in that order (the
-// rounding of a loop over the dimensions).
-__device__ __forceinline__ double ordered_sum(double x, int d)
+// rounding of a loop over the dimensions); buf: the wavefront's 64 doubles
+// of LDS.  Every lane writes its x and reads all d back (broadcast reads,
+// all issued before the first add).
+__device__ __forceinline__ double ordered_sum(double x, int d, double *buf)
 {
+    wave_sync();  // every lane's reads of the previous sum are done
+    buf[threadIdx.x & (kWave - 1)] = x;
+    wave_sync();
     double s = 0.0;
-    for (int j = 0; j < d; ++j) s = s + lane_value(x, j);
+    for (int j = 0; j < d; ++j) s = s + buf[j];
     return s;
 }
 
@@ -284,7 +280,9 @@ __device__ __forceinline__ double ordered_sum(double x, int d)
 // the dimensions computes, without a memory round trip per pair.
 __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
 {
+    __shared__ double sums[4][kWave];
     const int j = threadIdx.x & (kWave - 1);
+    double *const buf = sums[threadIdx.x / kWave];
     const int v = wave_tile_index();  // the vector: tile v / 64, its lane v % 64
     const int t = v / kWave;
     if (t >= a.n_tiles) return;
@@ -322,21 +320,21 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     for (int k = 0; k < kLbfgsMaxM; ++k) {  // newest to oldest
         coef[k] = 0.0;
         if (k < cnt) {
-            coef[k] = rho[k] * ordered_sum(Sk[k] * r, d);
+            coef[k] = rho[k] * ordered_sum(Sk[k] * r, d, buf);
             r = r - coef[k] * Yk[k];
         }
     }
     double h0 = 1.0;
     if (cnt > 0) {
-        const double sy = ordered_sum(Sk[0] * Yk[0], d);
-        const double yy = ordered_sum(Yk[0] * Yk[0], d);
+        const double sy = ordered_sum(Sk[0] * Yk[0], d, buf);
+        const double yy = ordered_sum(Yk[0] * Yk[0], d, buf);
         if (yy > 0.0) h0 = sy / yy;
     }
     r = h0 * r;
 #pragma unroll
     for (int k = kLbfgsMaxM - 1; k >= 0; --k) {  // oldest to newest
         if (k < cnt) {
-            const double b = rho[k] * ordered_sum(Yk[k] * r, d);
+            const double b = rho[k] * ordered_sum(Yk[k] * r, d, buf);
             r = r + Sk[k] * (coef[k] - b);
         }
     }
@@ -344,17 +342,20 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     const double u = to_u(c, th);
     double p = -r;
     if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
-    double gp = ordered_sum(gu * p, d);
+    double gp = ordered_sum(gu * p, d, buf);
     if (!(gp < 0.0)) {  // not a descent direction: steepest descent
         cnt = 0;
         p = -gu;
         if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
-        gp = ordered_sum(gu * p, d);
+        gp = ordered_sum(gu * p, d, buf);
     }
     double alpha = a.st.alpha[pidx];
     if (cnt == 0) {
         double pmax = 0.0;
-        for (int i = 0; i < d; ++i) pmax = fmax(pmax, fabs(lane_value(p, i)));
+        wave_sync();
+        buf[j] = p;
+        wave_sync();
+        for (int i = 0; i < d; ++i) pmax = fmax(pmax, fabs(buf[i]));
         if (pmax > 0.0 && alpha * pmax > 0.01) alpha = 0.01 / pmax;
     }
     if (j == 0) {

@@ -18,8 +18,9 @@ import numpy as np
 import torch
 
 from . import fit
-from .core import (Batch, Graph, ProblemSpec, PsoParams, Swarm, pso_init, sird_integrate,
-                   sird_loss, sird_loss_backward, sird_loss_backward_workspace, sird_pso_iterate)
+from .core import (CKPT_SEGMENTS, Batch, Graph, ProblemSpec, PsoParams, Swarm, pso_init,
+                   sird_integrate, sird_loss, sird_loss_backward, sird_loss_backward_workspace,
+                   sird_pso_iterate)
 
 
 def _events():
@@ -131,6 +132,38 @@ def gradients_per_s(wl, thetas, reps=10, ckpt_interval=0, warm_pairs=5) -> Dict:
             "ms_forward": ms_f, "reverse_over_forward": ms_rev / ms_f,
             "ckpt_interval": ckpt_interval or "default: whole days per LDS slice (one day here)",
             "particle_steps": b.particle_steps, "workspace_bytes": int(ws.numel())}
+
+
+def refine_gradient_latency(wl, ks=(32, 1024), reps=30, seed=12) -> Dict:
+    """Latency of one self-contained gradient call (forward + reverse sweep)
+    at a refinement's size: k parameter vectors drawn in the workload's box,
+    with the sequential sweep (default interval) and with the
+    segment-parallel sweep (CKPT_SEGMENTS)."""
+    f = wl.fits[0]
+    rng = np.random.default_rng(seed)
+    out = {}
+    for k in ks:
+        b = Batch([ProblemSpec.from_fit(f, k)])
+        th = f.lo + rng.random((k, len(f.lo))) * (f.hi - f.lo)
+        theta, obs = b.pack_theta([th]), b.pack_obs([f.y])
+        grad = b.empty_theta()
+        row = {}
+        for name, ci in (("sequential", 0), ("segments", CKPT_SEGMENTS)):
+            ws = torch.empty(max(sird_loss_backward_workspace(b, ci), 8), dtype=torch.uint8,
+                             device=b.device)
+            for _ in range(5):
+                sird_loss_backward(b, theta, obs, wl.loss, grad_theta=grad, ckpt_interval=ci,
+                                   workspace=ws)
+            e0, e1 = _events()
+            e0.record()
+            for _ in range(reps):
+                sird_loss_backward(b, theta, obs, wl.loss, grad_theta=grad, ckpt_interval=ci,
+                                   workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            row[f"ms_{name}"] = e0.elapsed_time(e1) / reps
+        out[f"k{k}"] = row
+    return out
 
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
