@@ -375,73 +375,57 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     }
 }
 
-// The accepted step's arrays of one lane (column stride n).  The arrays are
-// distinct buffers; the restrict-qualified parameters let the compiler issue
-// the loads of a loop ahead of its stores instead of one element at a time.
-__device__ __forceinline__ void lbfgs_take(size_t n, int d, const double *lo, const double *hi,
-                                           int lgl, double *__restrict__ th,
-                                           double *__restrict__ g,
-                                           const double *__restrict__ tt,
-                                           const double *__restrict__ gt,
-                                           double *__restrict__ S, double *__restrict__ Y,
-                                           bool keep)
-{
-    if (keep) {
-        for (int j = 0; j < d; ++j) {
-            const Coord c = coord_of(lo, hi, j, d, lgl);
-            S[j * n] = to_u(c, tt[j * n]) - to_u(c, th[j * n]);
-            Y[j * n] = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
-        }
-    }
-    for (int j = 0; j < d; ++j) {
-        th[j * n] = tt[j * n];
-        g[j * n] = gt[j * n];
-    }
-}
-
+// A wavefront per parameter vector, lane j for dimension j, as the proposal:
+// the Armijo test on the trial point, and on acceptance the new pair (kept
+// when s.y > 0, s.y summed in dimension order) and the step.
 __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int t = wave_tile_index();
+    __shared__ double sums[4][kWave];
+    const int j = threadIdx.x & (kWave - 1);
+    double *const buf = sums[threadIdx.x / kWave];
+    const int v = wave_tile_index();
+    const int t = v / kWave;
     if (t >= a.n_tiles) return;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
-    const int pl = tl.p0 + lane;
+    const int pl = tl.p0 + v % kWave;
     if (pl >= P.n_part) return;
     const int d = P.n_seg + 3;
+    const bool on = j < d;
     const int m = a.st.m;
     const size_t n = (size_t)P.n_part;
-    const size_t col = (size_t)P.theta_off + pl;
+    const size_t cj = (size_t)P.theta_off + (size_t)(on ? j : 0) * n + pl;
     const size_t pidx = (size_t)P.p_off + pl;
-    const double *lo = a.lo + P.box_off;
-    const double *hi = a.hi + P.box_off;
-    double *th = a.st.theta + col;
-    double *g = a.st.grad + col;
-    const double *tt = a.st.theta_t + col;
-    const double *gt = a.st.grad_t + col;
     const double ft = a.st.f_t[pidx];
     const double alpha = a.st.alpha[pidx];
     const bool ok = isfinite(ft) && ft <= a.st.f[pidx] + a.c1 * alpha * a.st.gp[pidx];
     if (ok) {
-        const int lgl = a.st.log_last;
-        double sy = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const Coord c = coord_of(lo, hi, j, d, lgl);
-            const double sj = to_u(c, tt[j * n]) - to_u(c, th[j * n]);
-            const double yj = grad_u(c, tt[j * n], gt[j * n]) - grad_u(c, th[j * n], g[j * n]);
-            sy = sy + sj * yj;
-        }
+        const Coord c =
+            coord_of(a.lo + P.box_off, a.hi + P.box_off, on ? j : 0, d, a.st.log_last);
+        const double tt = a.st.theta_t[cj], th = a.st.theta[cj];
+        const double gt = a.st.grad_t[cj], g = a.st.grad[cj];
+        const double sj = to_u(c, tt) - to_u(c, th);
+        const double yj = grad_u(c, tt, gt) - grad_u(c, th, g);
+        const double sy = ordered_sum(sj * yj, d, buf);
         const int head = a.st.head[pidx];
-        lbfgs_take(n, d, lo, hi, lgl, th, g, tt, gt, a.st.S + (size_t)head * a.theta_len + col,
-                   a.st.Y + (size_t)head * a.theta_len + col, sy > 0.0);
-        if (sy > 0.0) {
-            a.st.rho[(size_t)head * a.total_particles + pidx] = 1.0 / sy;
-            a.st.head[pidx] = (head + 1) % m;
-            if (a.st.count[pidx] < m) a.st.count[pidx] = a.st.count[pidx] + 1;
+        if (sy > 0.0 && on) {
+            a.st.S[(size_t)head * a.theta_len + cj] = sj;
+            a.st.Y[(size_t)head * a.theta_len + cj] = yj;
         }
-        a.st.f[pidx] = ft;
-        a.st.alpha[pidx] = 1.0;
-    } else {
+        if (on) {
+            a.st.theta[cj] = tt;
+            a.st.grad[cj] = gt;
+        }
+        if (j == 0) {
+            if (sy > 0.0) {
+                a.st.rho[(size_t)head * a.total_particles + pidx] = 1.0 / sy;
+                a.st.head[pidx] = (head + 1) % m;
+                if (a.st.count[pidx] < m) a.st.count[pidx] = a.st.count[pidx] + 1;
+            }
+            a.st.f[pidx] = ft;
+            a.st.alpha[pidx] = 1.0;
+        }
+    } else if (j == 0) {
         const double half = 0.5 * alpha;
         if (half < 1e-20) {
             a.st.count[pidx] = 0;
@@ -508,10 +492,11 @@ extern "C" int sird_lbfgs_accept(const sird_batch *batch, const lbfgs_state *sta
     int st = check_lbfgs(batch, state, lo, hi, "sird_lbfgs_accept");
     if (st) return st;
     if (!(c1 > 0.0 && c1 < 1.0)) return fail(SIRD_EINVAL, "sird_lbfgs_accept: c1 outside (0,1)");
-    const int grid = tile_blocks(batch->n_tiles);
-    if (grid == 0) return SIRD_OK;
-    hipLaunchKernelGGL(k_lbfgs_accept, dim3(grid), dim3(256), 0, (hipStream_t)stream,
-                       lbfgs_args(batch, state, lo, hi, c1));
+    // a wavefront per parameter vector: 64 per tile, four per block
+    if (batch->n_tiles == 0) return SIRD_OK;
+    const int64_t waves = (int64_t)batch->n_tiles * kWave;
+    hipLaunchKernelGGL(k_lbfgs_accept, dim3((unsigned)((waves + 3) / 4)), dim3(4 * kWave), 0,
+                       (hipStream_t)stream, lbfgs_args(batch, state, lo, hi, c1));
     return hip_status(hipGetLastError(), "sird_lbfgs_accept");
 }
 
