@@ -85,6 +85,7 @@ struct BwdArgs {
     int seg;         // 1: the segment-parallel sweep (checkpoints at every
                      // day start, then k_seg_transfer and k_seg_combine)
     int seg_rows;    // steps a wavefront of k_seg_transfer holds in LDS
+    int max_pieces;  // bound on the segment-parallel sweep's pieces per problem
 };
 
 // Modes of k_backward.
@@ -824,19 +825,34 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
 // forward pass has saved Dhat.  So the sweep over one beta segment maps the
 // adjoint c_end at the segment's end to c_start = A c_end + b, and the
 // segment's sums (of s_s I_s u, I_s u and I_s kbar.I over its stages) are
-// affine in c_end too.  k_seg_transfer runs every segment of every parameter
-// vector at once (a wavefront per tile and segment, replaying each day from
-// the checkpoint at its start) and walks three adjoints backwards through
-// the segment, with the same reverse step as the sequential sweep: c = (1, 0)
-// and c = (0, 1) without a_D (the columns of A, and the sums' slopes), and
-// c = 0 with a_D (b, and the sums' offsets).  k_seg_combine then chains the
-// segments from the last, one lane per vector.  The gradient is the
+// affine in c_end too, and so is the map of any run of days within a
+// segment.  k_seg_transfer cuts every segment into pieces of at most
+// kSegPieceDays days and runs every piece of every parameter vector at once
+// (a wavefront per tile and piece, replaying each day from the checkpoint at
+// its start), walking three adjoints backwards through the piece with the
+// same reverse step as the sequential sweep: c = (1, 0) and c = (0, 1)
+// without a_D (the columns of A, and the sums' slopes), and c = 0 with a_D
+// (b, and the sums' offsets).  k_seg_combine then chains the pieces from the
+// last, one lane per vector, adding up each segment's sums.  The gradient is the
 // sequential sweep's up to rounding (its sums are added in another order).
 
-// Workspace slots of one segment's affine map, after the two tail slots:
+// Workspace slots of one piece's affine map, after the two tail slots:
 // A (c_S, c_I of both unit walks), b, and per walk the sums of s_s I_s u,
-// I_s u and I_s kbar.I, then the segment's part of the mu sum's D part.
+// I_s u and I_s kbar.I, then the piece's part of the mu sum's D part.
 constexpr int kSegSlots = 16;
+// A segment is walked in pieces of at most this many days, a wavefront each
+// (a segment's map is the chain of its pieces' maps).
+constexpr int kSegPieceDays = 7;
+
+// The days [d0, d1) of segment k <= k_last (segments start at day starts;
+// the last one runs to the window's end) and its number of pieces.
+__device__ __forceinline__ int seg_pieces(int k, int k_last, int SS, int spd, int W, int &d0,
+                                          int &d1)
+{
+    d0 = (k * SS) / spd;
+    d1 = k == k_last ? W : ((k + 1) * SS) / spd;
+    return (d1 - d0 + kSegPieceDays - 1) / kSegPieceDays;
+}
 
 // The workspace column of one lane: slot q of particle p at ws[q * stride + p],
 // addressed as a uniform base (the tile's first particle) plus the lane's
@@ -863,7 +879,7 @@ struct WsLane {
 // Slots of the segment-parallel sweep's workspace (no stored sub-interval
 // starts): checkpoint d at 3d .. 3d + 2 (s, I, S), then Dhat, S at every
 // segment start, the sums of J, the tail (MXSE's day, the loss) and the
-// segments' affine maps.
+// pieces' affine maps.
 struct SegSlots {
     size_t day, seg, jd, tail, map;
     __device__ __forceinline__ SegSlots(const BwdArgs &a)
@@ -876,15 +892,16 @@ struct SegSlots {
     }
 };
 
-// One wavefront per (tile, segment), one lane per parameter vector.
+// One wavefront per (tile, piece), one lane per parameter vector; pieces are
+// numbered segment by segment from the first.
 template <int KIND>
 __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
 {
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_uniform((int)blockIdx.x);
-    const int t = wv / a.max_seg;
-    const int k = wv - t * a.max_seg;
+    const int t = wv / a.max_pieces;
+    const int piece = wv - t * a.max_pieces;
     if (t >= a.n_tiles) return;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
@@ -892,7 +909,19 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
     const int T = W * spd;
     const int SS = (int)min((long)P.seg_days * spd, (long)T + 1);
     const int k_last = seg_of(T - 1, SS, K);
-    if (k > k_last) return;  // no step of the window in this segment
+    // the piece's segment k and days [d0, d1)
+    int k = 0, j = piece, d0 = 0, d1 = 0;
+    for (; k <= k_last; ++k) {
+        const int np = seg_pieces(k, k_last, SS, spd, W, d0, d1);
+        if (j < np) break;
+        j -= np;
+    }
+    if (k > k_last) return;  // past the problem's last piece
+    {
+        const int s0 = d0 + j * kSegPieceDays;
+        d1 = min(s0 + kSegPieceDays, d1);
+        d0 = s0;
+    }
     const int pl = tl.p0 + lane;
     const bool active = pl < n;
     const int pc = active ? pl : n - 1;
@@ -903,7 +932,7 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
     const SegSlots q(a);
     // LDS of the wavefront: the deceased counts and their weights, then
     // [2 slack][seg_rows][2][64], (s, I) of the lane before each step of one
-    // piece of a day (the walk's read-ahead touches the slack rows below
+    // part of a day (the walk's read-ahead touches the slack rows below
     // row 0 and never uses them)
     double *const ly = lds;
     double *const lw = ly + (a.max_days + 1);
@@ -922,10 +951,7 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
     StepConst<double> sc = step_const<double>(gamma, mu, spd);
     set_beta(sc, th[(size_t)k * ld], 1.0 / P.N);
     const int imax = (int)ws.load(q.tail);
-    // the segment's days d0 .. d1 - 1 (segments start at day starts)
-    const int d0 = (k * SS) / spd;
-    const int d1 = k == k_last ? W : ((k + 1) * SS) / spd;
-    // a_D over the segment's last day: the cost's gradient at days W down to
+    // a_D over the piece's last day: the cost's gradient at days W down to
     // d1, added in the sequential sweep's order; Dhat is loaded sixteen days
     // at a time (one memory round trip per sixteen days, not per day)
     double aD = cost_grad(KIND, W, W, ws.load(q.day + W), ly[W], lw[W], imax);
@@ -943,7 +969,7 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
     RevSums g1{0.0, 0.0, 0.0, 0.0, 0.0}, g2 = g1, g3 = g1;
     double muD = 0.0;
     const int R = a.seg_rows;
-    const int npieces = (spd + R - 1) / R;
+    const int nparts = (spd + R - 1) / R;
     // the day's checkpoint, Dhat and sum of J are loaded a day ahead
     double nDd = ws.load(q.day + d1 - 1), nJd = ws.load(q.jd + d1 - 1);
     double nck_s = ws.load(3 * (size_t)(d1 - 1)), nck_I = ws.load(3 * (size_t)(d1 - 1) + 1);
@@ -956,10 +982,10 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
             nck_s = ws.load(3 * (size_t)(d - 1));
             nck_I = ws.load(3 * (size_t)(d - 1) + 1);
         }
-        // the day's steps in pieces of at most R, the last piece first; a
-        // piece is replayed from the day's checkpoint
-        for (int j = npieces - 1; j >= 0; --j) {
-            const int b0 = j * R;
+        // the day's steps in parts of at most R, the last part first; a part
+        // is replayed from the day's checkpoint
+        for (int u = nparts - 1; u >= 0; --u) {
+            const int b0 = u * R;
             const int b1 = min(spd, b0 + R);
             SirdState<double> y;
             y.s = ck_s;
@@ -1001,7 +1027,7 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
         aD += cost_grad(KIND, d, W, Dd, ly[d], lw[d], imax);
     }
     if (active) {
-        const size_t m = q.map + (size_t)kSegSlots * k;
+        const size_t m = q.map + (size_t)kSegSlots * piece;
         const double out[kSegSlots] = {c1S,
                                        c1I,
                                        c2S,
@@ -1023,8 +1049,8 @@ __global__ void __launch_bounds__(kWave) k_seg_transfer(BwdArgs a)
     }
 }
 
-// One lane per parameter vector: the segments' maps chained from the last
-// segment (where c = 0) to the first, the gradient written.
+// One lane per parameter vector: the pieces' maps chained from the last
+// (where c = 0) to the first, the gradient written.
 __global__ void __launch_bounds__(256) k_seg_combine(BwdArgs a)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -1050,24 +1076,40 @@ __global__ void __launch_bounds__(256) k_seg_combine(BwdArgs a)
     for (int k = k_last + 1; k < K; ++k)
         if (active) gout[(size_t)k * ld] = 0.0;  // segments past the window end
     const double invN = 1.0 / P.N;
-    double cS = 0.0, cI = 0.0, tI = 0.0, muD = 0.0;
-    for (int k = k_last; k >= 0; --k) {
-        const size_t m = q.map + (size_t)kSegSlots * k;
-        double v[kSegSlots];
+    int total = 0, d0 = 0, d1 = 0;
+    for (int k = 0; k <= k_last; ++k) total += seg_pieces(k, k_last, SS, spd, W, d0, d1);
+    // the pieces from the last: a segment's sums over its pieces, its beta's
+    // gradient after its first piece; a piece's map is loaded a piece ahead
+    double cS = 0.0, cI = 0.0, tI = 0.0, muD = 0.0, G = 0.0, Gv = 0.0;
+    int k = k_last;
+    int left = seg_pieces(k, k_last, SS, spd, W, d0, d1);  // pieces of k to chain
+    double v[kSegSlots], nv[kSegSlots];
 #pragma unroll
-        for (int i = 0; i < kSegSlots; ++i) v[i] = ws.load(m + i);
-        const double G = fma(v[6], cS, fma(v[7], cI, v[8]));
-        const double Gv = fma(v[9], cS, fma(v[10], cI, v[11]));
-        const double Tk = fma(v[12], cS, fma(v[13], cI, v[14]));
-        const double b = th[(size_t)k * ld] * invN;
-        const double g = b != 0.0 ? (G / b) * invN : (ws.load(q.seg + k) * Gv) * invN;
-        if (active) gout[(size_t)k * ld] = g * gl;
-        tI += Tk;
+    for (int i = 0; i < kSegSlots; ++i)
+        nv[i] = ws.load(q.map + (size_t)kSegSlots * (total - 1) + i);
+    for (int g = total - 1; g >= 0; --g) {
+#pragma unroll
+        for (int i = 0; i < kSegSlots; ++i) v[i] = nv[i];
+        if (g > 0) {
+#pragma unroll
+            for (int i = 0; i < kSegSlots; ++i)
+                nv[i] = ws.load(q.map + (size_t)kSegSlots * (g - 1) + i);
+        }
+        G += fma(v[6], cS, fma(v[7], cI, v[8]));
+        Gv += fma(v[9], cS, fma(v[10], cI, v[11]));
+        tI += fma(v[12], cS, fma(v[13], cI, v[14]));
         muD += v[15];
         const double nS = fma(v[0], cS, fma(v[2], cI, v[4]));
         const double nI = fma(v[1], cS, fma(v[3], cI, v[5]));
         cS = nS;
         cI = nI;
+        if (--left == 0) {
+            const double b = th[(size_t)k * ld] * invN;
+            const double gk = b != 0.0 ? (G / b) * invN : (ws.load(q.seg + k) * Gv) * invN;
+            if (active) gout[(size_t)k * ld] = gk * gl;
+            G = Gv = 0.0;
+            if (--k >= 0) left = seg_pieces(k, k_last, SS, spd, W, d0, d1);
+        }
     }
     if (active) {
         const double h6 = step_const<double>(0.0, 0.0, spd).h6;
@@ -1102,6 +1144,13 @@ static int64_t checkpoints(const sird_batch *b, int ckpt_interval)
     return per_lc > aligned ? per_lc : aligned;
 }
 
+// A bound on the segment-parallel sweep's pieces of any problem: a segment
+// of n days has ceil(n / kSegPieceDays) pieces, at most n / kSegPieceDays + 1.
+static int seg_max_pieces(const sird_batch *b)
+{
+    return (b->max_days + kSegPieceDays - 1) / kSegPieceDays + (b->max_d - 3);
+}
+
 // Workspace slots per particle: 3 per checkpoint (s, I, S), 3 per LDS
 // sub-interval of an interval longer than one (the first and last
 // sub-intervals' slots go unused: the first starts at the checkpoint, the
@@ -1111,7 +1160,7 @@ static size_t ws_slots(const sird_batch *b, int ckpt_interval)
 {
     if (ckpt_interval == SIRD_CKPT_SEGMENTS)
         return (size_t)(3 * (int64_t)b->max_days + b->max_days + 1 + (b->max_d - 3) +
-                        b->max_days + 2 + (int64_t)kSegSlots * (b->max_d - 3));
+                        b->max_days + 2 + (int64_t)kSegSlots * seg_max_pieces(b));
     const int lc = lds_steps(b);
     const int64_t n_ck = checkpoints(b, ckpt_interval);
     const int64_t n_sub =
@@ -1196,6 +1245,7 @@ static int adjoint_prepare(const sird_batch *batch, const double *theta, const d
         const long rows = (kBwdLdsBudget / 8L - 2L * (batch->max_days + 1)) / (2L * kWave) - 2;
         if (rows < 1) return fail(SIRD_EINVAL, w + ": window too long for LDS");
         a->seg_rows = (int)(rows < kLcMax ? rows : kLcMax);
+        a->max_pieces = seg_max_pieces(batch);
     }
     a->lds_wave = 2 * (batch->max_days + 1) + kWave * (a->max_seg + 3 + 2 * (4 + a->lc));
     *lds = sizeof(double) * (size_t)a->lds_wave;
@@ -1245,14 +1295,14 @@ static void launch_seg_transfer(int kind, int grid, size_t lds, hipStream_t s,
     }
 }
 
-// The reverse sweep of the segment-parallel form: the segments' maps, then
+// The reverse sweep of the segment-parallel form: the pieces' maps, then
 // their chain (grid: tiles).
 static int seg_reverse(int loss_kind, int grid, hipStream_t stream, const BwdArgs &a,
                        const char *who)
 {
     const size_t lds = sizeof(double) * (2 * (size_t)(a.max_days + 1) +
                                          (size_t)kWave * 2 * (size_t)(a.seg_rows + 2));
-    launch_seg_transfer(loss_kind, grid * a.max_seg, lds, stream, a);
+    launch_seg_transfer(loss_kind, grid * a.max_pieces, lds, stream, a);
     int st = hip_status(hipGetLastError(), who);
     if (st) return st;
     hipLaunchKernelGGL(k_seg_combine, dim3(tile_blocks(grid)), dim3(256), 0, stream, a);
@@ -1266,7 +1316,7 @@ static int adjoint_launch(int mode, int loss_kind, int grid, size_t lds, hipStre
     if (grid == 0) return SIRD_OK;
     if (a.seg && mode != kFwdOnly) {
         // the forward pass (checkpoints at every day start) unless it is
-        // saved, then the segments' maps and their chain
+        // saved, then the pieces' maps and their chain
         if (mode == kBoth) {
             const int st = adjoint_launch(kFwdOnly, loss_kind, grid, lds, stream, a, who);
             if (st) return st;

@@ -231,12 +231,13 @@ def test_batch_plan_and_per_call_checks_on_host(L):
     ws100 = lib.sird_loss_backward_workspace(ctypes.byref(b.c), 100)
     assert ws100 == (3 * 3 + 3 * int(np.ceil(100 / lc)) + 46 + 4 + 45 + 2) * 165 * 8
     # the segment-parallel sweep: a checkpoint per day (3 x 45), Dhat, S at
-    # every segment start, the sums of J, the tail and 16 slots per segment
+    # every segment start, the sums of J, the tail and 16 slots per piece
+    # (segments walked in pieces of at most 7 days: at most ceil(45 / 7) + 4)
     text = open(HEADER).read()
     m = re.search(r"#define SIRD_CKPT_SEGMENTS \((-?\d+)\)", text)
     assert m and int(m.group(1)) == core.CKPT_SEGMENTS
     wseg = lib.sird_loss_backward_workspace(ctypes.byref(b.c), core.CKPT_SEGMENTS)
-    assert wseg == (3 * 45 + 46 + 4 + 45 + 2 + 16 * 4) * 165 * 8
+    assert wseg == (3 * 45 + 46 + 4 + 45 + 2 + 16 * (7 + 4)) * 165 * 8
     assert lib.sird_loss_backward_workspace(ctypes.byref(b.c), -2) == 0
     st = lib.sird_loss_backward(ctypes.byref(b.c), dummy.data_ptr(), dummy.data_ptr(), 0, None,
                                 dummy.data_ptr(), None, -2, 0, ctypes.c_void_p(4096), 1 << 30,

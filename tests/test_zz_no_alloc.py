@@ -53,6 +53,11 @@ def test_static_scratch_gradient_equals_workspace_gradient():
                                "mse", 13, grad_loss=scale)
     assert torch.equal(g, g_ref) and torch.equal(L, L_ref)
     assert np.all(np.isfinite(g.cpu().numpy()))
+    # call 3: the segment-parallel sweep on the same scratch
+    print("case static scratch: uneven batch, segment-parallel sweep", flush=True)
+    g, L, g_ref, L_ref = _both(b2, b2.pack_theta(ths), b2.pack_obs([fr.y for fr in wl.fits]),
+                               "mse", S.CKPT_SEGMENTS, grad_loss=scale)
+    assert torch.equal(g, g_ref) and torch.equal(L, L_ref)
 
 
 def test_static_scratch_refuses_an_oversized_batch():
