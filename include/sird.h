@@ -153,7 +153,10 @@ typedef struct sird_batch {
                                 set by sird_batch_plan                     */
     int32_t max_part;        /* max n_part over problems; set by
                                 sird_batch_plan (picks the global-best
-                                kernel's shape)                            */
+                                kernel's shape and the L-BFGS kernels'
+                                wavefronts per tile, min(64, max_part); a
+                                value below the true maximum would leave
+                                vectors out, 0 means 64)                   */
     int32_t waves_per_simd;  /* 0: as many wavefronts of the integration
                                 kernels per SIMD as registers and LDS allow;
                                 1..8: at most this many (the launch reserves

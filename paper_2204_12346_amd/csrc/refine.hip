@@ -211,6 +211,7 @@ struct LbfgsArgs {
     const sird_problem *probs;
     const sird_tile *tiles;
     int n_tiles;
+    int per_tile;  // wavefronts per tile: min(64, the batch's max_part)
     int64_t theta_len;
     int64_t total_particles;
     lbfgs_state st;
@@ -283,12 +284,12 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     __shared__ double sums[4][kWave];
     const int j = threadIdx.x & (kWave - 1);
     double *const buf = sums[threadIdx.x / kWave];
-    const int v = wave_tile_index();  // the vector: tile v / 64, its lane v % 64
-    const int t = v / kWave;
+    const int v = wave_tile_index();  // the vector: lane v % per_tile of tile v / per_tile
+    const int t = v / a.per_tile;
     if (t >= a.n_tiles) return;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
-    const int pl = tl.p0 + v % kWave;
+    const int pl = tl.p0 + v % a.per_tile;
     if (pl >= P.n_part) return;
     const int d = P.n_seg + 3;
     const bool on = j < d;
@@ -384,11 +385,11 @@ __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
     const int j = threadIdx.x & (kWave - 1);
     double *const buf = sums[threadIdx.x / kWave];
     const int v = wave_tile_index();
-    const int t = v / kWave;
+    const int t = v / a.per_tile;
     if (t >= a.n_tiles) return;
     const sird_tile tl = a.tiles[t];
     const sird_problem P = a.probs[tl.prob];
-    const int pl = tl.p0 + v % kWave;
+    const int pl = tl.p0 + v % a.per_tile;
     if (pl >= P.n_part) return;
     const int d = P.n_seg + 3;
     const bool on = j < d;
@@ -460,6 +461,9 @@ static LbfgsArgs lbfgs_args(const sird_batch *b, const lbfgs_state *st, const do
     a.probs = b->probs;
     a.tiles = b->tiles;
     a.n_tiles = b->n_tiles;
+    // a tile holds particles p0 .. p0 + 63 of one problem, so no tile has
+    // more vectors than the largest problem
+    a.per_tile = (b->max_part > 0 && b->max_part < kWave) ? b->max_part : kWave;
     a.theta_len = b->theta_len;
     a.total_particles = b->total_particles;
     a.st = *st;
@@ -478,11 +482,12 @@ extern "C" int sird_lbfgs_propose(const sird_batch *batch, const lbfgs_state *st
 {
     int st = check_lbfgs(batch, state, lo, hi, "sird_lbfgs_propose");
     if (st) return st;
-    // a wavefront per parameter vector: 64 per tile, four per block
+    // a wavefront per parameter vector (per_tile per tile), four per block
     if (batch->n_tiles == 0) return SIRD_OK;
-    const int64_t waves = (int64_t)batch->n_tiles * kWave;
+    const LbfgsArgs a = lbfgs_args(batch, state, lo, hi, 0.0);
+    const int64_t waves = (int64_t)batch->n_tiles * a.per_tile;
     hipLaunchKernelGGL(k_lbfgs_propose, dim3((unsigned)((waves + 3) / 4)), dim3(4 * kWave), 0,
-                       (hipStream_t)stream, lbfgs_args(batch, state, lo, hi, 0.0));
+                       (hipStream_t)stream, a);
     return hip_status(hipGetLastError(), "sird_lbfgs_propose");
 }
 
@@ -492,11 +497,12 @@ extern "C" int sird_lbfgs_accept(const sird_batch *batch, const lbfgs_state *sta
     int st = check_lbfgs(batch, state, lo, hi, "sird_lbfgs_accept");
     if (st) return st;
     if (!(c1 > 0.0 && c1 < 1.0)) return fail(SIRD_EINVAL, "sird_lbfgs_accept: c1 outside (0,1)");
-    // a wavefront per parameter vector: 64 per tile, four per block
+    // a wavefront per parameter vector (per_tile per tile), four per block
     if (batch->n_tiles == 0) return SIRD_OK;
-    const int64_t waves = (int64_t)batch->n_tiles * kWave;
+    const LbfgsArgs a = lbfgs_args(batch, state, lo, hi, c1);
+    const int64_t waves = (int64_t)batch->n_tiles * a.per_tile;
     hipLaunchKernelGGL(k_lbfgs_accept, dim3((unsigned)((waves + 3) / 4)), dim3(4 * kWave), 0,
-                       (hipStream_t)stream, lbfgs_args(batch, state, lo, hi, c1));
+                       (hipStream_t)stream, a);
     return hip_status(hipGetLastError(), "sird_lbfgs_accept");
 }
 

@@ -19,14 +19,26 @@ from .core import (CKPT_SEGMENTS, Batch, Graph, LbfgsState, ProblemSpec, PsoPara
                    sird_loss_backward_workspace, sird_pso_iterate)
 
 
+# Days per piece of the segment-parallel sweep (the library walks each beta
+# segment in pieces of at most this many days, one wavefront per tile and
+# piece).
+SEG_PIECE_DAYS = 7
+
+
 def default_ckpt_interval(batch: Batch) -> int:
     """Checkpoint interval of a refinement's gradients: the segment-parallel
-    sweep (CKPT_SEGMENTS) when the batch's tiles times its segments fit in
-    four wavefronts per SIMD, where the sequential sweep (one wavefront per
-    tile) would leave most SIMDs idle and the call's latency is what counts;
-    else the sequential sweep's default (0)."""
+    sweep (CKPT_SEGMENTS) when all its transfer wavefronts (tiles times the
+    bound on pieces per vector, ceil(days / 7) + segments) fit in one
+    wavefront per SIMD, the residency their LDS slices allow; there the
+    sequential sweep (one wavefront per tile) would leave most SIMDs idle
+    and the call's latency is what counts.  Else the sequential sweep's
+    default (0): with more wavefronts than SIMDs the transfers run in
+    rounds and walk more steps than the sequential sweep."""
     simds = 4 * torch.cuda.get_device_properties(batch.device).multi_processor_count
-    return CKPT_SEGMENTS if batch.n_tiles * (batch.c.max_d - 3) <= 4 * simds else 0
+    c = batch.c
+    pieces = -(-c.max_days // SEG_PIECE_DAYS) + (c.max_d - 3)
+    return CKPT_SEGMENTS if batch.n_tiles * pieces <= simds else 0
+
 
 def run_swarm(batch: Batch, params: PsoParams, obs, kind="ssre", iters=100, hist=True,
               graph_chunk=0, swarm: Optional[Swarm] = None, init=True) -> Swarm:

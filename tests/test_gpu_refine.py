@@ -251,6 +251,54 @@ def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds):
         np.testing.assert_allclose(st.alpha.cpu().numpy(), ost.alpha, rtol=1e-13)
 
 
+@pytest.mark.parametrize("counts", [(5, 17, 2), (70, 3, 40)])
+def test_lbfgs_rounds_match_oracle_on_uneven_problems(counts):
+    """Problems of different sizes and dimensions in one batch: the kernels
+    run as many wavefronts per tile as the largest problem needs (below 64:
+    that count; else 64), so every vector of every problem is proposed and
+    accepted, in lockstep with the oracle fed the same (f, grad)."""
+    wl = synth.c3(regions=[0, 1, 3])
+    fits = wl.fits
+    ths = [random_theta(f, n, seed=20 + i) for i, (f, n) in enumerate(zip(fits, counts))]
+    b = make_batch(fits, list(counts))
+    lo = b.pack_box([f.lo for f in fits])
+    hi = b.pack_box([f.hi for f in fits])
+    st = S.LbfgsState(b, b.pack_theta(ths), m=4, log_last=True)
+    osts = [oracle.Lbfgs(t, m=4, log_last=True) for t in ths]
+    probs = [oracle_problem(f) for f in fits]
+
+    def fg(i, t):
+        return oracle.loss_grad_fwd(probs[i], t, fits[i].y, "ssre")
+
+    for i, o in enumerate(osts):
+        for q in range(counts[i]):
+            o.f[q], o.grad[q] = fg(i, ths[i][q])
+    st.f.copy_(torch.from_numpy(np.concatenate([o.f for o in osts])).cuda())
+    st.grad.copy_(b.pack_theta([o.grad for o in osts]))
+    for rnd in range(6):
+        S.sird_lbfgs_propose(b, st, lo, hi)
+        tts = b.unpack_theta(st.theta_t)
+        for i, o in enumerate(osts):
+            o.propose(fits[i].lo, fits[i].hi)
+            np.testing.assert_allclose(tts[i], o.theta_t, rtol=1e-13, atol=1e-300,
+                                       err_msg=f"round {rnd}, problem {i}")
+            for q in range(counts[i]):
+                o.f_t[q], o.grad_t[q] = fg(i, o.theta_t[q])
+        st.theta_t.copy_(b.pack_theta([o.theta_t for o in osts]))
+        st.f_t.copy_(torch.from_numpy(np.concatenate([o.f_t for o in osts])).cuda())
+        st.grad_t.copy_(b.pack_theta([o.grad_t for o in osts]))
+        S.sird_lbfgs_accept(b, st, lo, hi, 1e-4)
+        got = b.unpack_theta(st.theta)
+        for i, o in enumerate(osts):
+            o.accept(fits[i].lo, fits[i].hi, 1e-4)
+            np.testing.assert_allclose(got[i], o.theta, rtol=1e-13,
+                                       err_msg=f"round {rnd}, problem {i}")
+        assert np.array_equal(st.count.cpu().numpy(), np.concatenate([o.count for o in osts]))
+        assert np.array_equal(st.head.cpu().numpy(), np.concatenate([o.head for o in osts]))
+        np.testing.assert_allclose(st.alpha.cpu().numpy(),
+                                   np.concatenate([o.alpha for o in osts]), rtol=1e-13)
+
+
 def test_lbfgs_refinement_recovers_noise_free_truth():
     wl = synth.c1(n_part=64, iters=20)
     f = wl.fits[0]
