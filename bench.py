@@ -288,8 +288,9 @@ def extra_tasks():
     # (projected L-BFGS, and the projected Adam the protocol names, with a
     # decaying step)
     t.append(("time_to_fit_c2",
-              lambda: X.time_to_fit(synth.c2(), pso_first=(100,), ks=(32, 1024),
-                                    adam_arms=((100, 32),), adam_lr_end=1e-5)))
+              lambda: X.time_to_fit(synth.c2(), pso_first=(50, 100), ks=(32, 128, 1024),
+                                    adam_arms=((100, 32),), adam_lr_end=1e-5,
+                                    trials=(1, 4))))
     for dt in ("f64", "f32"):
         t.append((f"paper_euler_ramp_ird_mxse_10000x92d_{dt}",
                   lambda dt=dt: X.paper_iteration(synth.paper(), dt)))

@@ -458,10 +458,16 @@ int sird_adam_step(const sird_batch *batch, double *theta, const double *grad, d
                    const adam_params *params, void *stream);
 
 /* State of projected L-BFGS refinement (all device memory, caller-owned).
- * theta-shaped: theta, grad, theta_t, grad_t; particle-indexed: f, f_t,
- * alpha, gp, count, head; S and Y: m theta-shaped arrays back to back
- * ([m][theta_len]); rho: [m][total_particles].  Start with count = head = 0,
- * alpha = 1, f and grad evaluated at theta. */
+ * theta-shaped: theta, grad; particle-indexed: f, alpha, gp, count, head;
+ * S and Y: m theta-shaped arrays back to back ([m][theta_len]); rho:
+ * [m][total_particles].  The trial points: theta_t and grad_t are T
+ * theta-shaped arrays back to back ([T][theta_len]), f_t T particle-indexed
+ * ones ([T][total_particles]), T = max(n_trials, 1); trial t of every
+ * vector is the t-th block (a batch whose problems are the batch's own
+ * repeated T times, trial-major, with theta and particle offsets shifted
+ * by t theta_len and t total_particles, evaluates all trials in one
+ * sird_loss_backward call).  Start with count = head = 0, alpha = 1, f and
+ * grad evaluated at theta. */
 typedef struct lbfgs_state {
     double *theta;
     double *grad;
@@ -479,6 +485,7 @@ typedef struct lbfgs_state {
     int32_t m;        /* pairs kept, 1..32 */
     int32_t log_last; /* 1: the last parameter (I0) is optimised as log I0
                          in [log lo, log hi] (requires lo > 0) */
+    int32_t n_trials; /* trial points per round, 0..8 (0 means 1) */
 } lbfgs_state;
 
 /* Projected L-BFGS (Liu & Nocedal 1989, two-loop recursion of Nocedal 1980)
@@ -492,14 +499,16 @@ typedef struct lbfgs_state {
  *     newest pair, I when none); p = -r with fixed dimensions and components
  *     pushing past an active bound zeroed; if g_u.p >= 0 the memory is
  *     dropped and p = -g_u; without stored pairs alpha is capped so that
- *     max |alpha p| <= 0.01; theta_t = lo + clamp(u + alpha p, 0, 1)(hi - lo);
- *     gp = g_u.p.
- *   accept: if f_t is finite and f_t <= f + c1 alpha gp, keep the trial
- *     (store the pair (u_t - u, g_u,t - g_u) when s.y > 0; alpha = 1), else
- *     halve alpha (below 1e-20: drop the memory, alpha = 1).
+ *     max |alpha p| <= 0.01; trial t = 0..T-1 at the step a_t = alpha 2^t:
+ *     theta_t[t] = lo + clamp(u + a_t p, 0, 1)(hi - lo); gp = g_u.p.
+ *   accept: among the trials with finite f_t[t] <= f + c1 a_t gp, keep the
+ *     one of lowest f_t (the first on ties): store the pair (u_t - u,
+ *     g_u,t - g_u) when s.y > 0, alpha = 1; with none, halve alpha (below
+ *     1e-20: drop the memory, alpha = 1).  T = 1 is backtracking by
+ *     halving; more trials try longer steps in the same evaluation.
  * Parameter vectors are independent; d <= 64.
  * Errors: SIRD_EINVAL (null pointer, m outside 1..32, c1 outside (0,1),
- * log_last not 0/1), SIRD_EHIP. */
+ * log_last not 0/1, n_trials outside 0..8), SIRD_EHIP. */
 int sird_lbfgs_propose(const sird_batch *batch, const lbfgs_state *state, const double *lo,
                        const double *hi, void *stream);
 int sird_lbfgs_accept(const sird_batch *batch, const lbfgs_state *state, const double *lo,

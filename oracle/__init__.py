@@ -81,9 +81,9 @@ def lib():
                                          _D, _I64, _D, _D, _D, _D, _D, _D, ctypes.c_int]
         L.orc_loss_grad_fwd.argtypes = prob + [_D, _D, ctypes.c_int, _D, _D, _D]
         _IP = ctypes.POINTER(ctypes.c_int)
-        L.orc_lbfgs_propose.argtypes = [ctypes.c_int] * 4 + [_D, _D, _D, _D, _D, _D, _D, _IP,
+        L.orc_lbfgs_propose.argtypes = [ctypes.c_int] * 5 + [_D, _D, _D, _D, _D, _D, _D, _IP,
                                                              _IP, _D, _D, _D, _D]
-        L.orc_lbfgs_accept.argtypes = [ctypes.c_int] * 4 + [_D, _D, ctypes.c_double, _D, _D, _D,
+        L.orc_lbfgs_accept.argtypes = [ctypes.c_int] * 5 + [_D, _D, ctypes.c_double, _D, _D, _D,
                                                             _D, _D, _D, _D, _D, _D, _D, _IP,
                                                             _IP, _D]
         L.orc_integrate_model.argtypes = [ctypes.c_int] + prob + [_D, _D]
@@ -295,18 +295,22 @@ def adam_step(theta, grad, m, v, lo, hi, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8)
 class Lbfgs:
     """State of the oracle's projected L-BFGS over n vectors of dimension d
     (row-major [n][d]; memory [n][m][d]); log_last optimises the last
-    dimension as its logarithm within [log lo, log hi]."""
+    dimension as its logarithm within [log lo, log hi].  n_trials trial
+    points per round: trial t of vector q in row t n + q of theta_t,
+    grad_t and f_t."""
 
-    def __init__(self, theta, m=8, log_last=False):
+    def __init__(self, theta, m=8, log_last=False, n_trials=1):
         self.log_last = int(bool(log_last))
         self.theta = _f64(theta).copy()
         n, d = self.theta.shape
         self.m = m
+        self.n_trials = int(n_trials)
+        assert 1 <= self.n_trials <= 8
         self.grad = np.zeros((n, d))
         self.f = np.zeros(n)
-        self.theta_t = np.zeros((n, d))
-        self.grad_t = np.zeros((n, d))
-        self.f_t = np.zeros(n)
+        self.theta_t = np.zeros((self.n_trials * n, d))
+        self.grad_t = np.zeros((self.n_trials * n, d))
+        self.f_t = np.zeros(self.n_trials * n)
         self.p = np.zeros((n, d))
         self.gp = np.zeros(n)
         self.S = np.zeros((n, m, d))
@@ -320,8 +324,8 @@ class Lbfgs:
         lo, hi = _f64(lo), _f64(hi)
         n, d = self.theta.shape
         ip = ctypes.POINTER(ctypes.c_int)
-        lib().orc_lbfgs_propose(n, d, self.m, self.log_last, _dp(lo), _dp(hi), _dp(self.theta), _dp(self.grad),
-                                _dp(self.S), _dp(self.Y), _dp(self.rho),
+        lib().orc_lbfgs_propose(n, d, self.m, self.log_last, self.n_trials, _dp(lo), _dp(hi),
+                                _dp(self.theta), _dp(self.grad), _dp(self.S), _dp(self.Y), _dp(self.rho),
                                 self.count.ctypes.data_as(ip), self.head.ctypes.data_as(ip),
                                 _dp(self.alpha), _dp(self.p), _dp(self.gp), _dp(self.theta_t))
 
@@ -329,8 +333,8 @@ class Lbfgs:
         lo, hi = _f64(lo), _f64(hi)
         n, d = self.theta.shape
         ip = ctypes.POINTER(ctypes.c_int)
-        lib().orc_lbfgs_accept(n, d, self.m, self.log_last, _dp(lo), _dp(hi), c1, _dp(self.theta),
-                               _dp(self.grad), _dp(self.f), _dp(self.theta_t), _dp(self.grad_t),
+        lib().orc_lbfgs_accept(n, d, self.m, self.log_last, self.n_trials, _dp(lo), _dp(hi),
+                               c1, _dp(self.theta), _dp(self.grad), _dp(self.f), _dp(self.theta_t), _dp(self.grad_t),
                                _dp(self.f_t), _dp(self.gp), _dp(self.S), _dp(self.Y),
                                _dp(self.rho), self.count.ctypes.data_as(ip),
                                self.head.ctypes.data_as(ip), _dp(self.alpha))

@@ -589,11 +589,16 @@ void orc_adam_step(int n, int d, double *theta, const double *grad, double *m,
 /*    p > 0) and fixed dimensions are zeroed; if g_u.p >= 0 the memory   */
 /*    is dropped and p = -g_u (projected); with no stored pair the step  */
 /*    is capped so that max |alpha p| <= 0.01;                           */
-/*    u_t = clamp(u + alpha p, 0, 1), theta_t = lo + u_t (hi - lo).      */
-/*  accept: Armijo f_t <= f + c1 alpha g_u.p (finite f_t) keeps the      */
-/*    trial: the pair (u_t - u, g_u,t - g_u) is stored when s.y > 0,     */
-/*    alpha = 1; otherwise alpha is halved, and below 1e-20 the memory   */
-/*    is dropped and alpha = 1.                                          */
+/*    n_trials trial points along p, trial t at the step a_t = alpha 2^t */
+/*    (rows t n + q of [n_trials n][d] arrays):                          */
+/*    u_t = clamp(u + a_t p, 0, 1), theta_t = lo + u_t (hi - lo).        */
+/*  accept: among the trials with finite f_t passing Armijo              */
+/*    f_t <= f + c1 a_t g_u.p, the one of lowest f_t (the first on ties) */
+/*    is kept: the pair (u_t - u, g_u,t - g_u) is stored when s.y > 0,   */
+/*    alpha = 1; with none, alpha is halved, and below 1e-20 the memory  */
+/*    is dropped and alpha = 1.  One trial is classical backtracking by  */
+/*    halving; more try longer steps in the same evaluation, which the   */
+/*    ill-conditioned fits take (more progress per round).               */
 /* ------------------------------------------------------------------ */
 /* Box coordinate of dimension j: u = (phi(theta) - a)/w with phi the
  * identity, or the logarithm for the last dimension when log_last is set
@@ -633,10 +638,11 @@ static double orc_grad_u(orc_coord c, double th, double g)
     return c.lg ? g * th * c.w : g * c.w;
 }
 
-void orc_lbfgs_propose(int n, int d, int m, int log_last, const double *lo, const double *hi,
-                       const double *theta, const double *grad, const double *S,
-                       const double *Y, const double *rho, int *count, const int *head,
-                       double *alpha, double *p_out, double *gp_out, double *theta_t)
+void orc_lbfgs_propose(int n, int d, int m, int log_last, int n_trials, const double *lo,
+                       const double *hi, const double *theta, const double *grad,
+                       const double *S, const double *Y, const double *rho, int *count,
+                       const int *head, double *alpha, double *p_out, double *gp_out,
+                       double *theta_t)
 {
     for (int q = 0; q < n; ++q) {
         const double *th = theta + (long)q * d;
@@ -706,35 +712,51 @@ void orc_lbfgs_propose(int n, int d, int m, int log_last, const double *lo, cons
             if (pmax > 0.0 && alpha[q] * pmax > 0.01) alpha[q] = 0.01 / pmax;
         }
         gp_out[q] = gp;
-        for (int j = 0; j < d; ++j) {
-            orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
-            if (c.w == 0.0) { theta_t[(long)q * d + j] = th[j]; continue; }
-            double ut = u[j] + alpha[q] * p[j];
-            if (ut < 0.0) ut = 0.0;
-            if (ut > 1.0) ut = 1.0;
-            theta_t[(long)q * d + j] = orc_from_u(c, ut);
+        /* trial t at the step alpha 2^t, in row t n + q */
+        for (int t = 0; t < n_trials; ++t) {
+            const double at = alpha[q] * (double)(1 << t);
+            double *tt = theta_t + ((long)t * n + q) * d;
+            for (int j = 0; j < d; ++j) {
+                orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
+                if (c.w == 0.0) { tt[j] = th[j]; continue; }
+                double ut = u[j] + at * p[j];
+                if (ut < 0.0) ut = 0.0;
+                if (ut > 1.0) ut = 1.0;
+                tt[j] = orc_from_u(c, ut);
+            }
         }
     }
 }
 
-void orc_lbfgs_accept(int n, int d, int m, int log_last, const double *lo, const double *hi,
-                      double c1,
+void orc_lbfgs_accept(int n, int d, int m, int log_last, int n_trials, const double *lo,
+                      const double *hi, double c1,
                       double *theta, double *grad, double *f, const double *theta_t,
                       const double *grad_t, const double *f_t, const double *gp,
                       double *S, double *Y, double *rho, int *count, int *head,
                       double *alpha)
 {
     for (int q = 0; q < n; ++q) {
-        double ft = f_t[q];
-        int ok = isfinite(ft) && ft <= f[q] + c1 * alpha[q] * gp[q];
-        if (ok) {
+        /* the trial of lowest loss among those passing the Armijo test at
+           their own step alpha 2^t (the first on ties) */
+        int best = -1;
+        double ft = 0.0;
+        for (int t = 0; t < n_trials; ++t) {
+            const double at = alpha[q] * (double)(1 << t);
+            const double fx = f_t[(long)t * n + q];
+            if (isfinite(fx) && fx <= f[q] + c1 * at * gp[q] && (best < 0 || fx < ft)) {
+                best = t;
+                ft = fx;
+            }
+        }
+        if (best >= 0) {
+            const double *tht = theta_t + ((long)best * n + q) * d;
+            const double *grt = grad_t + ((long)best * n + q) * d;
             double sv[64], yv[64], sy = 0.0;
             for (int j = 0; j < d; ++j) {
                 orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
-                double a = theta[(long)q * d + j], b = theta_t[(long)q * d + j];
+                double a = theta[(long)q * d + j], b = tht[j];
                 sv[j] = orc_to_u(c, b) - orc_to_u(c, a);
-                yv[j] = orc_grad_u(c, b, grad_t[(long)q * d + j]) -
-                        orc_grad_u(c, a, grad[(long)q * d + j]);
+                yv[j] = orc_grad_u(c, b, grt[j]) - orc_grad_u(c, a, grad[(long)q * d + j]);
                 sy = sy + sv[j] * yv[j];
             }
             if (sy > 0.0) {
@@ -746,8 +768,8 @@ void orc_lbfgs_accept(int n, int d, int m, int log_last, const double *lo, const
                 if (count[q] < m) count[q] = count[q] + 1;
             }
             for (int j = 0; j < d; ++j) {
-                theta[(long)q * d + j] = theta_t[(long)q * d + j];
-                grad[(long)q * d + j] = grad_t[(long)q * d + j];
+                theta[(long)q * d + j] = tht[j];
+                grad[(long)q * d + j] = grt[j];
             }
             f[q] = ft;
             alpha[q] = 1.0;

@@ -82,7 +82,8 @@ class adam_params(ctypes.Structure):
 class lbfgs_state(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("theta", "grad", "f", "theta_t", "grad_t", "f_t", "S", "Y", "rho", "alpha",
-                 "gp", "count", "head")] + [("m", ctypes.c_int32), ("log_last", ctypes.c_int32)]
+                 "gp", "count", "head")] + [("m", ctypes.c_int32), ("log_last", ctypes.c_int32),
+                                            ("n_trials", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

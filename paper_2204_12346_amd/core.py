@@ -109,24 +109,39 @@ class ProblemSpec:
 
 class Batch:
     """A planned batch of problems resident on one device.  obs_series = 3
-    lays out I, R and D observations per problem (the F_IRD costs)."""
+    lays out I, R and D observations per problem (the F_IRD costs).
+    replicas = T > 1 repeats the problems T times, replica-major: replica t
+    of problem r has its own parameter vectors (theta and particle offsets
+    shifted by t theta_len and t total_particles of one replica) and shares
+    the observations and box of replica 0 -- the layout of the L-BFGS trial
+    points, T theta-shaped blocks back to back."""
 
     def __init__(self, specs: Sequence[ProblemSpec], dtype="f64", block=0, persistent=0,
-                 with_traj=False, device="cuda", obs_series=1, waves_per_simd=0, ppl=1):
-        specs = list(specs)
+                 with_traj=False, device="cuda", obs_series=1, waves_per_simd=0, ppl=1,
+                 replicas=1):
+        base = list(specs)
+        self.replicas = int(replicas)
+        if self.replicas < 1 or (self.replicas > 1 and with_traj):
+            raise ValueError("replicas must be >= 1, and 1 with trajectories")
+        specs = base * self.replicas
         n = len(specs)
         self.obs_series = int(obs_series)
         tab = np.zeros(n, dtype=_lib.PROBLEM_DTYPE)
         p_off = theta_off = obs_off = traj_off = box_off = 0
+        shared = []   # (obs_off, box_off) of replica 0
         for r, s in enumerate(specs):
+            if r < len(base):
+                shared.append((obs_off, box_off))
+            o_off, b_off = shared[r % len(base)]
             tab[r] = (s.W, s.spd, s.seg_days, s.K, s.n_part, s.model, s.N, s.R0, s.D0,
-                      p_off, theta_off, obs_off, traj_off if with_traj else 0, box_off, s.stream)
+                      p_off, theta_off, o_off, traj_off if with_traj else 0, b_off, s.stream)
             p_off += s.n_part
             theta_off += s.d * s.n_part
-            obs_off += self.obs_series * (s.W + 1)
+            if r < len(base):
+                obs_off += self.obs_series * (s.W + 1)
+                box_off += s.d
             if with_traj:
                 traj_off += 4 * (s.W + 1) * s.n_part
-            box_off += s.d
         self.specs = specs
         self.table = tab
         self.total_particles = p_off
@@ -477,23 +492,32 @@ def sird_adam_step(batch: Batch, theta, grad, m, v, lo, hi, t, lr=1e-3, beta1=0.
 class LbfgsState:
     """Device state of projected L-BFGS over the parameter vectors of a
     batch (lbfgs_state); theta is copied in, f/grad are evaluated by the
-    caller before the first round."""
+    caller before the first round.  n_trials > 1 trial points per round:
+    theta_t, grad_t and f_t hold n_trials blocks, and trial_batch (the
+    batch with that many replicas) evaluates them in one call."""
 
-    def __init__(self, batch: Batch, theta, m=32, log_last=True):
+    def __init__(self, batch: Batch, theta, m=32, log_last=True, n_trials=1):
         dev = batch.device
         th = max(batch.theta_len, 1)
         P = max(batch.total_particles, 1)
         f64 = dict(dtype=torch.float64, device=dev)
         self.m = int(m)
+        self.n_trials = int(n_trials)
+        if not 1 <= self.n_trials <= 8:
+            raise ValueError("n_trials must be in 1..8")
+        T = self.n_trials
+        self.trial_batch = batch if T == 1 else Batch(
+            batch.specs[:batch.n_prob // batch.replicas], dtype="f64", device=dev,
+            obs_series=batch.obs_series, replicas=T * batch.replicas)
         a = Args(batch)
         a(theta, batch.theta_len, "theta")
         a.device()
         self.theta = theta.detach().clone()
         self.grad = torch.zeros(th, **f64)
         self.f = torch.zeros(P, **f64)
-        self.theta_t = torch.zeros(th, **f64)
-        self.grad_t = torch.zeros(th, **f64)
-        self.f_t = torch.zeros(P, **f64)
+        self.theta_t = torch.zeros(T * th, **f64)
+        self.grad_t = torch.zeros(T * th, **f64)
+        self.f_t = torch.zeros(T * P, **f64)
         self.S = torch.zeros(self.m * th, **f64)
         self.Y = torch.zeros(self.m * th, **f64)
         self.rho = torch.zeros(self.m * P, **f64)
@@ -507,6 +531,7 @@ class LbfgsState:
             setattr(c, name, ptr(getattr(self, name)))
         c.m = self.m
         c.log_last = int(bool(log_last))
+        c.n_trials = T
         self.c = c
 
 

@@ -206,12 +206,14 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 
 // ---------------------------------------------------------------- L-BFGS
 constexpr int kLbfgsMaxM = 32;
+constexpr int kLbfgsMaxTrials = 8;
 
 struct LbfgsArgs {
     const sird_problem *probs;
     const sird_tile *tiles;
     int n_tiles;
     int per_tile;  // wavefronts per tile: min(64, the batch's max_part)
+    int n_trials;  // trial points per vector and round
     int64_t theta_len;
     int64_t total_particles;
     lbfgs_state st;
@@ -365,20 +367,25 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
         a.st.gp[pidx] = gp;
     }
     if (on) {
-        double tt = th;
-        if (c.w != 0.0) {
-            double ut = u + alpha * p;
-            if (ut < 0.0) ut = 0.0;
-            if (ut > 1.0) ut = 1.0;
-            tt = from_u(c, ut);
+        // trial t at the step alpha 2^t, in the t-th theta-shaped block
+        for (int tr = 0; tr < a.n_trials; ++tr) {
+            const double at = alpha * (double)(1 << tr);
+            double tt = th;
+            if (c.w != 0.0) {
+                double ut = u + at * p;
+                if (ut < 0.0) ut = 0.0;
+                if (ut > 1.0) ut = 1.0;
+                tt = from_u(c, ut);
+            }
+            a.st.theta_t[(size_t)tr * a.theta_len + cj] = tt;
         }
-        a.st.theta_t[cj] = tt;
     }
 }
 
 // A wavefront per parameter vector, lane j for dimension j, as the proposal:
-// the Armijo test on the trial point, and on acceptance the new pair (kept
-// when s.y > 0, s.y summed in dimension order) and the step.
+// the Armijo test on every trial point, the one of lowest loss among those
+// that pass (the first on ties), and on acceptance the new pair (kept when
+// s.y > 0, s.y summed in dimension order) and the step.
 __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
 {
     __shared__ double sums[4][kWave];
@@ -397,14 +404,24 @@ __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
     const size_t n = (size_t)P.n_part;
     const size_t cj = (size_t)P.theta_off + (size_t)(on ? j : 0) * n + pl;
     const size_t pidx = (size_t)P.p_off + pl;
-    const double ft = a.st.f_t[pidx];
     const double alpha = a.st.alpha[pidx];
-    const bool ok = isfinite(ft) && ft <= a.st.f[pidx] + a.c1 * alpha * a.st.gp[pidx];
-    if (ok) {
+    const double f0 = a.st.f[pidx], gp = a.st.gp[pidx];
+    int best = -1;
+    double ft = 0.0;
+    for (int tr = 0; tr < a.n_trials; ++tr) {
+        const double at = alpha * (double)(1 << tr);
+        const double fx = a.st.f_t[(size_t)tr * a.total_particles + pidx];
+        if (isfinite(fx) && fx <= f0 + a.c1 * at * gp && (best < 0 || fx < ft)) {
+            best = tr;
+            ft = fx;
+        }
+    }
+    if (best >= 0) {
         const Coord c =
             coord_of(a.lo + P.box_off, a.hi + P.box_off, on ? j : 0, d, a.st.log_last);
-        const double tt = a.st.theta_t[cj], th = a.st.theta[cj];
-        const double gt = a.st.grad_t[cj], g = a.st.grad[cj];
+        const size_t ct = (size_t)best * a.theta_len + cj;
+        const double tt = a.st.theta_t[ct], th = a.st.theta[cj];
+        const double gt = a.st.grad_t[ct], g = a.st.grad[cj];
         const double sj = to_u(c, tt) - to_u(c, th);
         const double yj = grad_u(c, tt, gt) - grad_u(c, th, g);
         const double sy = ordered_sum(sj * yj, d, buf);
@@ -450,6 +467,8 @@ static int check_lbfgs(const sird_batch *b, const lbfgs_state *st, const double 
     if (st->m < 1 || st->m > kLbfgsMaxM) return fail(SIRD_EINVAL, w + ": m must be in 1..32");
     if (st->log_last != 0 && st->log_last != 1)
         return fail(SIRD_EINVAL, w + ": log_last must be 0 or 1");
+    if (st->n_trials < 0 || st->n_trials > kLbfgsMaxTrials)
+        return fail(SIRD_EINVAL, w + ": n_trials must be in 0..8");
     if (b->max_d > 64) return fail(SIRD_EINVAL, w + ": d > 64");
     return SIRD_OK;
 }
@@ -467,6 +486,7 @@ static LbfgsArgs lbfgs_args(const sird_batch *b, const lbfgs_state *st, const do
     a.theta_len = b->theta_len;
     a.total_particles = b->total_particles;
     a.st = *st;
+    a.n_trials = st->n_trials > 0 ? st->n_trials : 1;
     a.lo = lo;
     a.hi = hi;
     a.c1 = c1;

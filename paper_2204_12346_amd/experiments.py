@@ -168,14 +168,15 @@ def refine_gradient_latency(wl, ks=(32, 1024), reps=30, seed=12) -> Dict:
 
 def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 200),
                 ks=(64, 1024, 4096), refine_steps=2000, lr=1e-2, rels=(1e-2, 1e-3, 1e-4, 1e-6),
-                chunk=50, method="lbfgs", adam_arms=(), adam_lr_end=None) -> Dict:
+                chunk=50, method="lbfgs", adam_arms=(), adam_lr_end=None, trials=(1,)) -> Dict:
     """Wall time from pso_init until the loss is within rel of the best
     loss any run of either arm found (L_best), per seed:
       plain arm: swarm iterations (graph chunks of `chunk`), capped;
       adjoint arm: I' swarm iterations, then refinement of the k best
       personal bests with gradients from the discrete adjoint: projected
-      L-BFGS rounds (method "lbfgs", I0 in log coordinates) or projected
-      Adam steps ("adam"); one arm per (I', k), plus projected Adam arms
+      L-BFGS rounds (method "lbfgs", I0 in log coordinates; one arm per
+      number of trial steps per round in trials, named _t<T> when T > 1) or
+      projected Adam steps ("adam"); one arm per (I', k), plus projected Adam arms
       for the (I', k) in adam_arms (judged against the same L_best).  Adam's
       step is lr, or decays geometrically from lr to adam_lr_end over the
       refine_steps steps when adam_lr_end is given.  A round on k vectors of
@@ -211,10 +212,13 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
         g.close()
         curves["plain"][seed] = curve
         _progress(f"time_to_fit plain seed {seed}: {curve[-1][0]:.2f} s, loss {curve[-1][1]:.9g}")
-    arms = [(I1, k, method) for k in ks for I1 in pso_first]
-    arms += [(I1, k, "adam") for I1, k in adam_arms]
-    for I1, k, meth in arms:
+    arms = [(I1, k, method, T) for k in ks for I1 in pso_first
+            for T in (trials if method == "lbfgs" else (1,))]
+    arms += [(I1, k, "adam", 1) for I1, k in adam_arms]
+    for I1, k, meth, T in arms:
         arm = f"adjoint_I{I1}_k{k}" if meth == method else f"{meth}_I{I1}_k{k}"
+        if T > 1:
+            arm += f"_t{T}"
         curves[arm] = {}
         for seed in seeds:
             b, params, obs = new(seed)
@@ -229,7 +233,8 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
                 _adam_curve(b, sw, params, obs, wl.loss, k, refine_steps, lr, t0, curve,
                             lr_end=adam_lr_end)
             else:
-                _lbfgs_curve(b, sw, params, obs, wl.loss, k, refine_steps, t0, curve)
+                _lbfgs_curve(b, sw, params, obs, wl.loss, k, refine_steps, t0, curve,
+                             n_trials=T)
             curves[arm][seed] = curve
             _progress(f"time_to_fit {arm} seed {seed}: {curve[-1][0]:.2f} s, "
                       f"loss {curve[-1][1]:.9g}")
@@ -243,7 +248,8 @@ def time_to_fit(wl, seeds=(2, 3, 4, 5, 6), plain_cap=10000, pso_first=(50, 100, 
 
     res = {"L_best": L_best, "rels": list(rels), "seeds": list(seeds),
            "plain_cap_iterations": plain_cap, "refine": method,
-           "refine_steps_cap": refine_steps, "k": list(ks), "pso_first": list(pso_first)}
+           "refine_steps_cap": refine_steps, "k": list(ks), "pso_first": list(pso_first),
+           "trials": list(trials)}
     if method == "adam" or adam_arms:
         res["lr"] = lr
         res["lr_end"] = adam_lr_end
@@ -300,18 +306,19 @@ def _adam_curve(b, sw, params, obs, kind, k, steps, lr, t0, curve, check_every=2
     return rb
 
 
-def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10):
-    """Projected L-BFGS from the top-k personal bests, appending
-    (elapsed s, best loss so far, round) every check_every rounds."""
+def _lbfgs_curve(b, sw, params, obs, kind, k, rounds, t0, curve, check_every=10, n_trials=1):
+    """Projected L-BFGS from the top-k personal bests (n_trials trial steps
+    per round), appending (elapsed s, best loss so far, round) every
+    check_every rounds."""
     from .core import LbfgsState, pso_topk, sird_gather
     idx = pso_topk(b, sw.pbest_f, k)
     specs = [s.with_particles(k) for s in b.specs]
     rb = Batch(specs, device=b.device, obs_series=b.obs_series)
     theta = sird_gather(b, sw.pbest_x, params.lo, rb, idx, k)
-    st = LbfgsState(rb, theta)
-    ci = fit.default_ckpt_interval(rb)
-    ws = torch.empty(max(sird_loss_backward_workspace(rb, ci), 8), dtype=torch.uint8,
-                     device=b.device)
+    st = LbfgsState(rb, theta, n_trials=n_trials)
+    ci = fit.default_ckpt_interval(st.trial_batch)
+    ws = torch.empty(max(sird_loss_backward_workspace(st.trial_batch, ci), 8),
+                     dtype=torch.uint8, device=b.device)
     sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f,
                        ckpt_interval=ci, workspace=ws)
     best = [curve[-1][1]]

@@ -109,18 +109,21 @@ def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre",
                  c1=1e-4, ckpt_interval=None, workspace=None, callback=None, check_every=0):
     """Run projected L-BFGS rounds on every parameter vector of rb: each
     round is sird_lbfgs_propose, the adjoint at the trial points
-    (sird_loss_backward), sird_lbfgs_accept.  st.f / st.grad must hold the
-    loss and gradient at st.theta.  callback(round) every check_every rounds
-    may return True to stop."""
+    (sird_loss_backward on st.trial_batch: all st.n_trials trials of every
+    vector in one call), sird_lbfgs_accept.  st.f / st.grad must hold the
+    loss and gradient at st.theta.  ckpt_interval and workspace serve the
+    trial batch.  callback(round) every check_every rounds may return True
+    to stop."""
+    tb = st.trial_batch
     if ckpt_interval is None:
-        ckpt_interval = default_ckpt_interval(rb)
+        ckpt_interval = default_ckpt_interval(tb)
     ws = workspace
     if ws is None:
-        ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8),
+        ws = torch.empty(max(sird_loss_backward_workspace(tb, ckpt_interval), 8),
                          dtype=torch.uint8, device=rb.device)
     for r in range(1, rounds + 1):
         sird_lbfgs_propose(rb, st, params.lo, params.hi)
-        sird_loss_backward(rb, st.theta_t, obs, kind, grad_theta=st.grad_t, loss_out=st.f_t,
+        sird_loss_backward(tb, st.theta_t, obs, kind, grad_theta=st.grad_t, loss_out=st.f_t,
                            ckpt_interval=ckpt_interval, workspace=ws)
         sird_lbfgs_accept(rb, st, params.lo, params.hi, c1)
         if callback is not None and check_every and r % check_every == 0:
@@ -131,20 +134,22 @@ def lbfgs_rounds(rb: Batch, st: LbfgsState, params: PsoParams, obs, kind="ssre",
 
 def refine_lbfgs(batch: Batch, swarm: Swarm, params: PsoParams, obs, kind="ssre", k=32,
                  max_rounds=500, rel_tol=1e-12, check_every=25, m=32,
-                 ckpt_interval=None) -> Refined:
+                 ckpt_interval=None, n_trials=1) -> Refined:
     """Projected L-BFGS from the k best personal bests of every problem, in
-    box-normalised coordinates, with gradients from the discrete adjoint.
-    Stops after max_rounds, or when no vector's loss changed by more than
-    rel_tol (relative) over check_every rounds."""
+    box-normalised coordinates, with gradients from the discrete adjoint
+    and n_trials trial steps per round.  Stops after max_rounds, or when no
+    vector's loss changed by more than rel_tol (relative) over check_every
+    rounds."""
     idx = pso_topk(batch, swarm.pbest_f, k)
     specs = [s.with_particles(k) for s in batch.specs]
     rb = Batch(specs, dtype="f64", device=batch.device, obs_series=batch.obs_series)
     theta = sird_gather(batch, swarm.pbest_x, params.lo, rb, idx, k)
+    st = LbfgsState(rb, theta, m=m, n_trials=n_trials)
     if ckpt_interval is None:
-        ckpt_interval = default_ckpt_interval(rb)
-    st = LbfgsState(rb, theta, m=m)
-    ws = torch.empty(max(sird_loss_backward_workspace(rb, ckpt_interval), 8), dtype=torch.uint8,
-                     device=batch.device)
+        ckpt_interval = default_ckpt_interval(st.trial_batch)
+    # the trial batch's workspace also serves the k vectors themselves
+    ws = torch.empty(max(sird_loss_backward_workspace(st.trial_batch, ckpt_interval), 8),
+                     dtype=torch.uint8, device=batch.device)
     sird_loss_backward(rb, st.theta, obs, kind, grad_theta=st.grad, loss_out=st.f,
                        ckpt_interval=ckpt_interval, workspace=ws)
     prev = [st.f.clone()]

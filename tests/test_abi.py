@@ -57,6 +57,8 @@ int main(void) {
   printf("%zu %zu\n", offsetof(pso_state, f), offsetof(pso_state, hist_len));
   printf("%zu %zu %zu\n", offsetof(sird_batch, ppl), offsetof(sird_batch, n_pairs),
          offsetof(sird_batch, pair_tiles));
+  printf("%zu %zu %zu\n", sizeof(lbfgs_state), offsetof(lbfgs_state, m),
+         offsetof(lbfgs_state, n_trials));
   return 0;
 }
 ''')
@@ -80,6 +82,8 @@ int main(void) {
     assert vals[2] == 136
     assert vals[11] == L.pso_state.f.offset
     assert vals[12] == L.pso_state.hist_len.offset
+    assert vals[16:19] == [ctypes.sizeof(L.lbfgs_state), L.lbfgs_state.m.offset,
+                           L.lbfgs_state.n_trials.offset]
 
 
 def _table(rows):

@@ -210,18 +210,21 @@ def test_autotuner_of_the_fused_iteration_restores_the_swarm(tmp_path, monkeypat
         assert torch.equal(bits(getattr(sw, n)), bits(getattr(ref, n))), n
 
 
-@pytest.mark.parametrize("m,rounds", [(5, 12), (32, 40)])
-def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds):
+@pytest.mark.parametrize("m,rounds,T", [(5, 12, 1), (32, 40, 1), (8, 16, 4)])
+def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds, T):
     """Same (f, grad) inputs on both sides -> the same proposals and updates
-    (the second case wraps the 32-pair memory)."""
+    (the second case wraps the 32-pair memory; the third tries four steps
+    per round, its trials laid out and evaluated as the trial batch's)."""
     f = synth.c2().fits[0]
     P = 40
     th = random_theta(f, P, seed=11)
     th[:, :f.K] *= 0.5
     b = make_batch([f], [P])
     lo, hi = b.pack_box([f.lo]), b.pack_box([f.hi])
-    st = S.LbfgsState(b, b.pack_theta([th]), m=m, log_last=True)
-    ost = oracle.Lbfgs(th, m=m, log_last=True)
+    st = S.LbfgsState(b, b.pack_theta([th]), m=m, log_last=True, n_trials=T)
+    tb = st.trial_batch
+    assert tb.theta_len == T * b.theta_len and tb.total_particles == T * P
+    ost = oracle.Lbfgs(th, m=m, log_last=True, n_trials=T)
     prob = oracle_problem(f)
 
     def fg(t):
@@ -229,26 +232,31 @@ def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds):
 
     for q in range(P):
         ost.f[q], ost.grad[q] = fg(th[q])
-    st.f.copy_(torch.from_numpy(np.concatenate([ost.f, np.zeros(0)])).cuda())
+    st.f.copy_(torch.from_numpy(ost.f.copy()).cuda())
     st.grad.copy_(b.pack_theta([ost.grad]))
+    kept = set()
     for rnd in range(rounds):
         S.sird_lbfgs_propose(b, st, lo, hi)
         ost.propose(f.lo, f.hi)
-        tt = b.unpack_theta(st.theta_t)[0]
+        tt = np.concatenate(tb.unpack_theta(st.theta_t))
         np.testing.assert_allclose(tt, ost.theta_t, rtol=1e-13, atol=1e-300, err_msg=f"round {rnd}")
         np.testing.assert_allclose(st.gp.cpu().numpy(), ost.gp, rtol=1e-12)
         # evaluate at the oracle's trial points, feed both sides the same values
-        for q in range(P):
-            ost.f_t[q], ost.grad_t[q] = fg(ost.theta_t[q])
-        st.theta_t.copy_(b.pack_theta([ost.theta_t]))
+        for i in range(T * P):
+            ost.f_t[i], ost.grad_t[i] = fg(ost.theta_t[i])
+        st.theta_t.copy_(tb.pack_theta(np.split(ost.theta_t, T)))
         st.f_t.copy_(torch.from_numpy(ost.f_t.copy()).cuda())
-        st.grad_t.copy_(b.pack_theta([ost.grad_t]))
+        st.grad_t.copy_(tb.pack_theta(np.split(ost.grad_t, T)))
         S.sird_lbfgs_accept(b, st, lo, hi, 1e-4)
         ost.accept(f.lo, f.hi, 1e-4)
+        for t in range(T):
+            kept |= {t for q in range(P) if np.array_equal(ost.theta_t[t * P + q], ost.theta[q])}
         np.testing.assert_allclose(b.unpack_theta(st.theta)[0], ost.theta, rtol=1e-13)
         assert np.array_equal(st.count.cpu().numpy(), ost.count)
         assert np.array_equal(st.head.cpu().numpy(), ost.head)
         np.testing.assert_allclose(st.alpha.cpu().numpy(), ost.alpha, rtol=1e-13)
+    if T > 1:
+        assert len(kept) > 1   # rounds kept trials other than the first
 
 
 @pytest.mark.parametrize("counts", [(5, 17, 2), (70, 3, 40)])
