@@ -263,17 +263,30 @@ __device__ __forceinline__ double grad_u(const Coord &c, double th, double g)
     return c.lg ? g * th * c.w : g * c.w;
 }
 
-// x_0 + x_1 + ... + x_{d-1} over lanes 0..d-1, added in that order (the
-// rounding of a loop over the dimensions); buf: the wavefront's 64 doubles
-// of LDS.  Every lane writes its x and reads all d back (broadcast reads,
-// all issued before the first add).
-__device__ __forceinline__ double ordered_sum(double x, int d, double *buf)
+// The double held by lane j (a uniform j) in every lane's scalar registers.
+__device__ __forceinline__ double lane_value(double x, int j)
 {
-    wave_sync();  // every lane's reads of the previous sum are done
-    buf[threadIdx.x & (kWave - 1)] = x;
-    wave_sync();
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), j);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), j);
+    return __hiloint2double(hi, lo);
+}
+
+// x_0 + x_1 + ... + x_{d-1} over lanes 0..d-1, added in that order (the
+// rounding of a loop over the dimensions).  The values are read across the
+// wavefront eight at a time, all reads issued before the adds, so only the
+// adds wait on each other.
+__device__ __forceinline__ double ordered_sum(double x, int d)
+{
     double s = 0.0;
-    for (int j = 0; j < d; ++j) s = s + buf[j];
+    int j = 0;
+    for (; j + 8 <= d; j += 8) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = lane_value(x, j + i);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s = s + v[i];
+    }
+    for (; j < d; ++j) s = s + lane_value(x, j);
     return s;
 }
 
@@ -283,9 +296,7 @@ __device__ __forceinline__ double ordered_sum(double x, int d, double *buf)
 // the dimensions computes, without a memory round trip per pair.
 __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
 {
-    __shared__ double sums[4][kWave];
     const int j = threadIdx.x & (kWave - 1);
-    double *const buf = sums[threadIdx.x / kWave];
     const int v = wave_tile_index();  // the vector: lane v % per_tile of tile v / per_tile
     const int t = v / a.per_tile;
     if (t >= a.n_tiles) return;
@@ -305,16 +316,23 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     const double gu = grad_u(c, th, a.st.grad[cj]);
     int cnt = a.st.count[pidx];
     const int head = a.st.head[pidx];
-    // the stored pairs, newest first
+    // the stored pairs, newest first: pair k in slot head - 1 - k (mod m).
+    // All m slots of the memory are allocated, so every load reads a valid
+    // slot and all are issued together, without branches; pairs past cnt
+    // are zeroed afterwards.
     double Sk[kLbfgsMaxM], Yk[kLbfgsMaxM], rho[kLbfgsMaxM];
+    {
+        int slot = min(max(head, 0), m - 1);  // a valid state has 0 <= head < m
 #pragma unroll
-    for (int k = 0; k < kLbfgsMaxM; ++k) {
-        Sk[k] = Yk[k] = rho[k] = 0.0;
-        if (k < cnt) {
-            const int slot = ((head - 1 - k) % m + m) % m;
+        for (int k = 0; k < kLbfgsMaxM; ++k) {
+            slot = (slot == 0 ? m : slot) - 1;
             Sk[k] = a.st.S[(size_t)slot * a.theta_len + cj];
             Yk[k] = a.st.Y[(size_t)slot * a.theta_len + cj];
             rho[k] = a.st.rho[(size_t)slot * a.total_particles + pidx];
+        }
+#pragma unroll
+        for (int k = 0; k < kLbfgsMaxM; ++k) {
+            if (k >= cnt) Sk[k] = Yk[k] = rho[k] = 0.0;
         }
     }
     double r = gu;
@@ -323,21 +341,21 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     for (int k = 0; k < kLbfgsMaxM; ++k) {  // newest to oldest
         coef[k] = 0.0;
         if (k < cnt) {
-            coef[k] = rho[k] * ordered_sum(Sk[k] * r, d, buf);
+            coef[k] = rho[k] * ordered_sum(Sk[k] * r, d);
             r = r - coef[k] * Yk[k];
         }
     }
     double h0 = 1.0;
     if (cnt > 0) {
-        const double sy = ordered_sum(Sk[0] * Yk[0], d, buf);
-        const double yy = ordered_sum(Yk[0] * Yk[0], d, buf);
+        const double sy = ordered_sum(Sk[0] * Yk[0], d);
+        const double yy = ordered_sum(Yk[0] * Yk[0], d);
         if (yy > 0.0) h0 = sy / yy;
     }
     r = h0 * r;
 #pragma unroll
     for (int k = kLbfgsMaxM - 1; k >= 0; --k) {  // oldest to newest
         if (k < cnt) {
-            const double b = rho[k] * ordered_sum(Yk[k] * r, d, buf);
+            const double b = rho[k] * ordered_sum(Yk[k] * r, d);
             r = r + Sk[k] * (coef[k] - b);
         }
     }
@@ -345,20 +363,17 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     const double u = to_u(c, th);
     double p = -r;
     if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
-    double gp = ordered_sum(gu * p, d, buf);
+    double gp = ordered_sum(gu * p, d);
     if (!(gp < 0.0)) {  // not a descent direction: steepest descent
         cnt = 0;
         p = -gu;
         if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
-        gp = ordered_sum(gu * p, d, buf);
+        gp = ordered_sum(gu * p, d);
     }
     double alpha = a.st.alpha[pidx];
     if (cnt == 0) {
         double pmax = 0.0;
-        wave_sync();
-        buf[j] = p;
-        wave_sync();
-        for (int i = 0; i < d; ++i) pmax = fmax(pmax, fabs(buf[i]));
+        for (int i = 0; i < d; ++i) pmax = fmax(pmax, fabs(lane_value(p, i)));
         if (pmax > 0.0 && alpha * pmax > 0.01) alpha = 0.01 / pmax;
     }
     if (j == 0) {
@@ -388,9 +403,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
 // s.y > 0, s.y summed in dimension order) and the step.
 __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
 {
-    __shared__ double sums[4][kWave];
     const int j = threadIdx.x & (kWave - 1);
-    double *const buf = sums[threadIdx.x / kWave];
     const int v = wave_tile_index();
     const int t = v / a.per_tile;
     if (t >= a.n_tiles) return;
@@ -424,7 +437,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
         const double gt = a.st.grad_t[ct], g = a.st.grad[cj];
         const double sj = to_u(c, tt) - to_u(c, th);
         const double yj = grad_u(c, tt, gt) - grad_u(c, th, g);
-        const double sy = ordered_sum(sj * yj, d, buf);
+        const double sy = ordered_sum(sj * yj, d);
         const int head = a.st.head[pidx];
         if (sy > 0.0 && on) {
             a.st.S[(size_t)head * a.theta_len + cj] = sj;
