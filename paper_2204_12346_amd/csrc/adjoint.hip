@@ -1079,22 +1079,20 @@ __global__ void __launch_bounds__(256) k_seg_combine(BwdArgs a)
     int total = 0, d0 = 0, d1 = 0;
     for (int k = 0; k <= k_last; ++k) total += seg_pieces(k, k_last, SS, spd, W, d0, d1);
     // the pieces from the last: a segment's sums over its pieces, its beta's
-    // gradient after its first piece; a piece's map is loaded a piece ahead
+    // gradient after its first piece.  The chain is a few operations per
+    // piece and its maps come from memory, so the maps are loaded four
+    // pieces ahead (four register sets in turn).
     double cS = 0.0, cI = 0.0, tI = 0.0, muD = 0.0, G = 0.0, Gv = 0.0;
     int k = k_last;
     int left = seg_pieces(k, k_last, SS, spd, W, d0, d1);  // pieces of k to chain
-    double v[kSegSlots], nv[kSegSlots];
-#pragma unroll
-    for (int i = 0; i < kSegSlots; ++i)
-        nv[i] = ws.load(q.map + (size_t)kSegSlots * (total - 1) + i);
-    for (int g = total - 1; g >= 0; --g) {
-#pragma unroll
-        for (int i = 0; i < kSegSlots; ++i) v[i] = nv[i];
-        if (g > 0) {
+    auto load_map = [&](double(&dst)[kSegSlots], int g) {
+        if (g >= 0) {
 #pragma unroll
             for (int i = 0; i < kSegSlots; ++i)
-                nv[i] = ws.load(q.map + (size_t)kSegSlots * (g - 1) + i);
+                dst[i] = ws.load(q.map + (size_t)kSegSlots * g + i);
         }
+    };
+    auto chain = [&](const double(&v)[kSegSlots]) {
         G += fma(v[6], cS, fma(v[7], cI, v[8]));
         Gv += fma(v[9], cS, fma(v[10], cI, v[11]));
         tI += fma(v[12], cS, fma(v[13], cI, v[14]));
@@ -1110,6 +1108,24 @@ __global__ void __launch_bounds__(256) k_seg_combine(BwdArgs a)
             G = Gv = 0.0;
             if (--k >= 0) left = seg_pieces(k, k_last, SS, spd, W, d0, d1);
         }
+    };
+    double m0[kSegSlots] = {}, m1[kSegSlots] = {}, m2[kSegSlots] = {}, m3[kSegSlots] = {};
+    load_map(m0, total - 1);
+    load_map(m1, total - 2);
+    load_map(m2, total - 3);
+    load_map(m3, total - 4);
+    for (int g = total - 1; g >= 0; g -= 4) {
+        chain(m0);
+        load_map(m0, g - 4);
+        if (g < 1) break;
+        chain(m1);
+        load_map(m1, g - 5);
+        if (g < 2) break;
+        chain(m2);
+        load_map(m2, g - 6);
+        if (g < 3) break;
+        chain(m3);
+        load_map(m3, g - 7);
     }
     if (active) {
         const double h6 = step_const<double>(0.0, 0.0, spd).h6;
