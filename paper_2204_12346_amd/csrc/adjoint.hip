@@ -55,6 +55,7 @@
 #include <cmath>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -395,32 +396,44 @@ __global__ void __launch_bounds__(4 * kWave) k_backward(BwdArgs a)
             wjd += PS;
         };
         if (dpc > 0) {
-            // checkpoints at day starts: the loss kernel's day loop
-            double *wck = wsb;
-            for (int day = 0; day < W; ++day) {
-                // the day's observation, read before its steps
-                const double yo = ly[day + 1], wo = lw[day + 1];
-                if (st == next) change_segment(y, sc, kf, next, lb, lane, invN, SS, K, T);
-                if (st == next_ck) {
-                    if (active) {
-                        store_at(wck, y.s);
-                        store_at(wck + PS, y.I);
-                        store_at(wck + 2 * PS, y.S);
+            // checkpoints at day starts: the loss kernel's day loop,
+            // instantiated for days of a multiple of ten steps (blocks of ten
+            // unrolled steps) and for others (unrolled by four), chosen
+            // outside the loop so the state stays in its registers
+            auto days = [&](auto tens) __attribute__((always_inline)) {
+                constexpr bool TENS = decltype(tens)::value;
+                double *wck = wsb;
+                for (int day = 0; day < W; ++day) {
+                    // the day's observation, read before its steps
+                    const double yo = ly[day + 1], wo = lw[day + 1];
+                    if (st == next) change_segment(y, sc, kf, next, lb, lane, invN, SS, K, T);
+                    if (st == next_ck) {
+                        if (active) {
+                            store_at(wck, y.s);
+                            store_at(wck + PS, y.I);
+                            store_at(wck + 2 * PS, y.S);
+                        }
+                        wck += 3 * PS;
+                        next_ck += sp;
                     }
-                    wck += 3 * PS;
-                    next_ck += sp;
-                }
-                double jd = 0.0;
-                if (spd % 10 == 0) {
-#pragma unroll 10
-                    for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
-                } else {
+                    double jd = 0.0;
+                    if constexpr (TENS) {
+                        for (int i = 0; i < spd; i += 10) {
+#pragma unroll
+                            for (int u = 0; u < 10; ++u) jd += rk4_step<double, false, false>(y, sc);
+                        }
+                    } else {
 #pragma unroll 4
-                    for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
+                        for (int i = 0; i < spd; ++i) jd += rk4_step<double, false, false>(y, sc);
+                    }
+                    st += spd;
+                    end_of_day(day, yo, wo, jd);
                 }
-                st += spd;
-                end_of_day(day, yo, wo, jd);
-            }
+            };
+            if (spd % 10 == 0)
+                days(std::true_type{});
+            else
+                days(std::false_type{});
         } else {
             size_t cq = 0;
             for (int day = 0; day < W; ++day) {

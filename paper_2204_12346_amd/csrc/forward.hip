@@ -20,6 +20,7 @@
 
 #include <atomic>
 #include <string>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -241,39 +242,51 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, int t, int lane, doub
         StepConst<R> sc = step_const<R>(gamma, mu, spd);
         const double invN = 1.0 / N;
         const int seg = P.seg_days;
-        int day = 0;
-        double beta_next = from_move ? mv0[3] : th[0];
-        for (int k = 0; k < K; ++k) {
-            const double beta_k = beta_next;
-            if (k + 1 < K) {
-                if (lazy && (k & 3) == 0) {
-                    // block k/4 + 1: slots k+4 .. k+7, beta_{k+1} .. beta_{k+4}
-                    double xn[4] = {0.0, 0.0, 0.0, 0.0};
-                    if (active) pso_move_block_seq(a.mv, P, pl, it, k / 4 + 1, xn);
-                    beta_next = active ? xn[0] : th[(size_t)(k + 1) * ld];
-                } else {
-                    beta_next = th[(size_t)(k + 1) * ld];  // prefetch
+        // the segments and their days, instantiated twice: days of a
+        // multiple of ten steps run in blocks of ten unrolled steps, other
+        // days unrolled by four; choosing outside the day loop keeps the
+        // loop-carried state in the same registers from day to day
+        auto segments = [&](auto tens) {
+            constexpr bool TENS = decltype(tens)::value;
+            int day = 0;
+            double beta_next = from_move ? mv0[3] : th[0];
+            for (int k = 0; k < K; ++k) {
+                const double beta_k = beta_next;
+                if (k + 1 < K) {
+                    if (lazy && (k & 3) == 0) {
+                        // block k/4 + 1: slots k+4 .. k+7, beta_{k+1} .. beta_{k+4}
+                        double xn[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (active) pso_move_block_seq(a.mv, P, pl, it, k / 4 + 1, xn);
+                        beta_next = active ? xn[0] : th[(size_t)(k + 1) * ld];
+                    } else {
+                        beta_next = th[(size_t)(k + 1) * ld];  // prefetch
+                    }
                 }
-            }
-            const int dend = (k == K - 1) ? W : (int)min((long)W, (long)(k + 1) * seg);
-            if (day >= dend) continue;
-            if (!WITH_S && day > 0) unscale(y, sc);
-            set_beta(sc, beta_k, invN);
-            if (!WITH_S) rescale(y, sc);
-            for (; day < dend; ++day) {
-                if (WITH_S) rescale(y, sc);
-                const DayObs o = day_obs(day + 1);
-                // a day of ten or twenty steps runs without a remainder loop
-                if (spd % 10 == 0) {
-#pragma unroll 10
-                    for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
-                } else {
+                const int dend = (k == K - 1) ? W : (int)min((long)W, (long)(k + 1) * seg);
+                if (day >= dend) continue;
+                if (!WITH_S && day > 0) unscale(y, sc);
+                set_beta(sc, beta_k, invN);
+                if (!WITH_S) rescale(y, sc);
+                for (; day < dend; ++day) {
+                    if (WITH_S) rescale(y, sc);
+                    const DayObs o = day_obs(day + 1);
+                    if constexpr (TENS) {
+                        for (int s = 0; s < spd; s += 10) {
+#pragma unroll
+                            for (int u = 0; u < 10; ++u) rk4_step<R, WITH_R, WITH_S>(y, sc);
+                        }
+                    } else {
 #pragma unroll 4
-                    for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
+                        for (int s = 0; s < spd; ++s) rk4_step<R, WITH_R, WITH_S>(y, sc);
+                    }
+                    emit(day + 1, o);
                 }
-                emit(day + 1, o);
             }
-        }
+        };
+        if (spd % 10 == 0)
+            segments(std::true_type{});
+        else
+            segments(std::false_type{});
     } else {
         const RampConst<R> rc = ramp_const<R>(xr[0], xr[1], xr[2], xr[3], gamma, mu, N, spd);
         const double h = 1.0 / (double)spd;
