@@ -259,20 +259,24 @@ def test_lbfgs_rounds_match_oracle_in_lockstep(m, rounds, T):
         assert len(kept) > 1   # rounds kept trials other than the first
 
 
-@pytest.mark.parametrize("counts", [(5, 17, 2), (70, 3, 40)])
-def test_lbfgs_rounds_match_oracle_on_uneven_problems(counts):
+@pytest.mark.parametrize("counts,T", [((5, 17, 2), 1), ((70, 3, 40), 1), ((5, 17, 2), 4)])
+def test_lbfgs_rounds_match_oracle_on_uneven_problems(counts, T):
     """Problems of different sizes and dimensions in one batch: the kernels
     run as many wavefronts per tile as the largest problem needs (below 64:
     that count; else 64), so every vector of every problem is proposed and
-    accepted, in lockstep with the oracle fed the same (f, grad)."""
+    accepted, in lockstep with the oracle fed the same (f, grad); with four
+    trial steps, the trials of every problem in the trial batch's blocks
+    and their losses from one gradient call on it."""
     wl = synth.c3(regions=[0, 1, 3])
     fits = wl.fits
     ths = [random_theta(f, n, seed=20 + i) for i, (f, n) in enumerate(zip(fits, counts))]
     b = make_batch(fits, list(counts))
     lo = b.pack_box([f.lo for f in fits])
     hi = b.pack_box([f.hi for f in fits])
-    st = S.LbfgsState(b, b.pack_theta(ths), m=4, log_last=True)
-    osts = [oracle.Lbfgs(t, m=4, log_last=True) for t in ths]
+    st = S.LbfgsState(b, b.pack_theta(ths), m=4, log_last=True, n_trials=T)
+    tb = st.trial_batch
+    osts = [oracle.Lbfgs(t, m=4, log_last=True, n_trials=T) for t in ths]
+    obs = b.pack_obs([f.y for f in fits])
     probs = [oracle_problem(f) for f in fits]
 
     def fg(i, t):
@@ -283,18 +287,32 @@ def test_lbfgs_rounds_match_oracle_on_uneven_problems(counts):
             o.f[q], o.grad[q] = fg(i, ths[i][q])
     st.f.copy_(torch.from_numpy(np.concatenate([o.f for o in osts])).cuda())
     st.grad.copy_(b.pack_theta([o.grad for o in osts]))
+    n_prob = len(fits)
+
+    def blocks(arrs):   # oracle rows [T n][...] per problem -> trial batch order
+        return [np.split(a, T)[t] for t in range(T) for a in arrs]
+
     for rnd in range(6):
         S.sird_lbfgs_propose(b, st, lo, hi)
-        tts = b.unpack_theta(st.theta_t)
+        tts = tb.unpack_theta(st.theta_t)
         for i, o in enumerate(osts):
             o.propose(fits[i].lo, fits[i].hi)
-            np.testing.assert_allclose(tts[i], o.theta_t, rtol=1e-13, atol=1e-300,
+            got = np.concatenate([tts[t * n_prob + i] for t in range(T)])
+            np.testing.assert_allclose(got, o.theta_t, rtol=1e-13, atol=1e-300,
                                        err_msg=f"round {rnd}, problem {i}")
-            for q in range(counts[i]):
+            for q in range(T * counts[i]):
                 o.f_t[q], o.grad_t[q] = fg(i, o.theta_t[q])
-        st.theta_t.copy_(b.pack_theta([o.theta_t for o in osts]))
-        st.f_t.copy_(torch.from_numpy(np.concatenate([o.f_t for o in osts])).cuda())
-        st.grad_t.copy_(b.pack_theta([o.grad_t for o in osts]))
+        if T > 1 and rnd == 0:
+            # one gradient call on the trial batch gives every trial's loss
+            f_gpu = tb.empty_particles()
+            S.sird_loss_backward(tb, st.theta_t, obs, "ssre", loss_out=f_gpu)
+            f_split = tb.split_particles(f_gpu)
+            for i, o in enumerate(osts):
+                got = np.concatenate([f_split[t * n_prob + i] for t in range(T)])
+                np.testing.assert_allclose(got, o.f_t, rtol=TOL64, err_msg=f"trial losses {i}")
+        st.theta_t.copy_(tb.pack_theta(blocks([o.theta_t for o in osts])))
+        st.f_t.copy_(torch.from_numpy(np.concatenate(blocks([o.f_t for o in osts]))).cuda())
+        st.grad_t.copy_(tb.pack_theta(blocks([o.grad_t for o in osts])))
         S.sird_lbfgs_accept(b, st, lo, hi, 1e-4)
         got = b.unpack_theta(st.theta)
         for i, o in enumerate(osts):
