@@ -146,7 +146,7 @@ __device__ __forceinline__ void gbest_scan(const double *f, int n, int first, in
 {
     bf = INFINITY;
     bi = n;  // sentinel above every index
-#pragma unroll 8
+#pragma unroll 16
     for (int p = first; p < n; p += stride) {
         const double v = f[p];
         if (better(v, p, bf, bi)) {
@@ -209,11 +209,11 @@ __device__ __forceinline__ void gbest_advance_iteration(const PsoArgs &a, uint64
 // 1024 threads, so that ten thousand particles cost about two memory
 // latencies.
 constexpr int kGbestBlock = 1024;
-// Smaller problems: one wavefront per problem and four problems per block,
+// Smaller problems: one wavefront per problem and sixteen problems per block,
 // so that a batch of many problems needs few blocks (every block takes one
 // same-address atomic to advance the iteration, and those serialise).
 constexpr int kGbestWaveMax = 4096;
-constexpr int kGbestWaveBlock = 256;
+constexpr int kGbestWaveBlock = 1024;
 
 __global__ void __launch_bounds__(kGbestBlock) k_pso_gbest(PsoArgs a)
 {
