@@ -583,6 +583,8 @@ void orc_adam_step(int n, int d, double *theta, const double *grad, double *m,
 /* log theta for the last dimension when log_last is set), for          */
 /* refining parameter vectors with gradients of the discrete loss.      */
 /* Per vector (row q of [n][d] arrays; memory arrays [n][m][d]):         */
+/* Every dot product over the d dimensions adds its rounded products in  */
+/* pairs (orc_pair_dot), the order of a reduction across lanes.          */
 /*  propose: r = H g_u by the two-loop recursion over the stored pairs   */
 /*    (initial H = (s.y / y.y) I of the newest pair, I when none);       */
 /*    p = -r; components at an active bound (u = 0 and p < 0, u = 1 and */
@@ -638,6 +640,21 @@ static double orc_grad_u(orc_coord c, double th, double g)
     return c.lg ? g * th * c.w : g * c.w;
 }
 
+/* sum over j < d (d <= 64) of a[j] b[j]: the products rounded, then added
+ * in pairs over the dimensions padded with zeros to the next power of two
+ * w -- first neighbours (0+1, 2+3, ...), then pairs of those, up to the
+ * width w -- the order in which a reduction across lanes adds them. */
+static double orc_pair_dot(const double *a, const double *b, int d)
+{
+    double v[64];
+    int w = 1;
+    while (w < d) w <<= 1;
+    for (int j = 0; j < w; ++j) v[j] = j < d ? a[j] * b[j] : 0.0;
+    for (int h = 1; h < w; h <<= 1)
+        for (int j = 0; j < w; j += 2 * h) v[j] = v[j] + v[j + h];
+    return v[0];
+}
+
 void orc_lbfgs_propose(int n, int d, int m, int log_last, int n_trials, const double *lo,
                        const double *hi, const double *theta, const double *grad,
                        const double *S, const double *Y, const double *rho, int *count,
@@ -660,8 +677,7 @@ void orc_lbfgs_propose(int n, int d, int m, int log_last, int n_trials, const do
             int slot = ((head[q] - 1 - k) % m + m) % m;
             const double *s = S + ((long)q * m + slot) * d;
             const double *y = Y + ((long)q * m + slot) * d;
-            double sr = 0.0;
-            for (int j = 0; j < d; ++j) sr = sr + s[j] * r[j];
+            const double sr = orc_pair_dot(s, r, d);
             a[k] = rho[(long)q * m + slot] * sr;
             for (int j = 0; j < d; ++j) r[j] = r[j] - a[k] * y[j];
         }
@@ -670,8 +686,7 @@ void orc_lbfgs_propose(int n, int d, int m, int log_last, int n_trials, const do
             int slot = ((head[q] - 1) % m + m) % m;
             const double *s = S + ((long)q * m + slot) * d;
             const double *y = Y + ((long)q * m + slot) * d;
-            double sy = 0.0, yy = 0.0;
-            for (int j = 0; j < d; ++j) { sy = sy + s[j] * y[j]; yy = yy + y[j] * y[j]; }
+            const double sy = orc_pair_dot(s, y, d), yy = orc_pair_dot(y, y, d);
             if (yy > 0.0) h0 = sy / yy;
         }
         for (int j = 0; j < d; ++j) r[j] = h0 * r[j];
@@ -680,30 +695,27 @@ void orc_lbfgs_propose(int n, int d, int m, int log_last, int n_trials, const do
             int slot = ((head[q] - 1 - k) % m + m) % m;
             const double *s = S + ((long)q * m + slot) * d;
             const double *y = Y + ((long)q * m + slot) * d;
-            double yr = 0.0;
-            for (int j = 0; j < d; ++j) yr = yr + y[j] * r[j];
+            const double yr = orc_pair_dot(y, r, d);
             double b = rho[(long)q * m + slot] * yr;
             for (int j = 0; j < d; ++j) r[j] = r[j] + s[j] * (a[k] - b);
         }
         double *p = p_out + (long)q * d;
-        double gp = 0.0;
         for (int j = 0; j < d; ++j) {
             double w = orc_coord_of(lo, hi, j, d, log_last).w;
             double pj = -r[j];
             if (w == 0.0 || (u[j] <= 0.0 && pj < 0.0) || (u[j] >= 1.0 && pj > 0.0)) pj = 0.0;
             p[j] = pj;
-            gp = gp + gu[j] * pj;
         }
+        double gp = orc_pair_dot(gu, p, d);
         if (!(gp < 0.0)) { /* not a descent direction: steepest descent */
             cnt = 0;
-            gp = 0.0;
             for (int j = 0; j < d; ++j) {
                 double w = orc_coord_of(lo, hi, j, d, log_last).w;
                 double pj = -gu[j];
                 if (w == 0.0 || (u[j] <= 0.0 && pj < 0.0) || (u[j] >= 1.0 && pj > 0.0)) pj = 0.0;
                 p[j] = pj;
-                gp = gp + gu[j] * pj;
             }
+            gp = orc_pair_dot(gu, p, d);
         }
         count[q] = cnt;
         if (cnt == 0) {
@@ -751,14 +763,14 @@ void orc_lbfgs_accept(int n, int d, int m, int log_last, int n_trials, const dou
         if (best >= 0) {
             const double *tht = theta_t + ((long)best * n + q) * d;
             const double *grt = grad_t + ((long)best * n + q) * d;
-            double sv[64], yv[64], sy = 0.0;
+            double sv[64], yv[64];
             for (int j = 0; j < d; ++j) {
                 orc_coord c = orc_coord_of(lo, hi, j, d, log_last);
                 double a = theta[(long)q * d + j], b = tht[j];
                 sv[j] = orc_to_u(c, b) - orc_to_u(c, a);
                 yv[j] = orc_grad_u(c, b, grt[j]) - orc_grad_u(c, a, grad[(long)q * d + j]);
-                sy = sy + sv[j] * yv[j];
             }
+            const double sy = orc_pair_dot(sv, yv, d);
             if (sy > 0.0) {
                 double *s = S + ((long)q * m + head[q]) * d;
                 double *y = Y + ((long)q * m + head[q]) * d;

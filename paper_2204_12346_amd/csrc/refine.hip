@@ -271,29 +271,41 @@ __device__ __forceinline__ double lane_value(double x, int j)
     return __hiloint2double(hi, lo);
 }
 
-// x_0 + x_1 + ... + x_{d-1} over lanes 0..d-1, added in that order (the
-// rounding of a loop over the dimensions).  The values are read across the
-// wavefront eight at a time, all reads issued before the adds, so only the
-// adds wait on each other.
-__device__ __forceinline__ double ordered_sum(double x, int d)
+// The double of lane j's partner under a DPP row permutation CTRL.
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x)
 {
-    double s = 0.0;
-    int j = 0;
-    for (; j + 8 <= d; j += 8) {
-        double v[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = lane_value(x, j + i);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) s = s + v[i];
-    }
-    for (; j < d; ++j) s = s + lane_value(x, j);
-    return s;
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// x_0 + x_1 + ... + x_{d-1} over lanes 0..d-1 (d <= 64), returned to every
+// lane.  In the first power-of-two block w >= d, lanes d..w-1 add zeros and
+// neighbours are added in pairs, then pairs of those, up to w: at each level
+// a lane adds the value of the lane whose index differs in that bit, so all
+// lanes of a block hold the same bits, the pairwise sum the oracle's dot
+// products compute.  Within a row of 16 the partners come by DPP (after the
+// first two levels a block of four holds one value, so mirroring within
+// eight or sixteen lanes finds the same partner value as flipping bit 2 or
+// 3).
+__device__ __forceinline__ double pair_sum(double x, int d)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double s = lane < d ? x : 0.0;
+    if (d > 1) s = s + dpp_partner<0xB1>(s);   // quad_perm [1,0,3,2]: bit 0
+    if (d > 2) s = s + dpp_partner<0x4E>(s);   // quad_perm [2,3,0,1]: bit 1
+    if (d > 4) s = s + dpp_partner<0x141>(s);  // row_half_mirror: bit 2
+    if (d > 8) s = s + dpp_partner<0x140>(s);  // row_mirror: bit 3
+    if (d > 16) s = s + __shfl_xor(s, 16);
+    if (d > 32) s = s + __shfl_xor(s, 32);
+    return lane_value(s, 0);  // lane 0's, uniform across the wavefront
 }
 
 // One wavefront per parameter vector, lane j for dimension j (d <= 64).  All
 // stored pairs are loaded at once, and every dot product is summed across the
-// lanes in the order of the dimensions, so the proposal is the one a loop over
-// the dimensions computes, without a memory round trip per pair.
+// lanes in pairs (pair_sum), the order the oracle's dot products take, without
+// a memory round trip per pair.
 __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
 {
     const int j = threadIdx.x & (kWave - 1);
@@ -341,21 +353,21 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     for (int k = 0; k < kLbfgsMaxM; ++k) {  // newest to oldest
         coef[k] = 0.0;
         if (k < cnt) {
-            coef[k] = rho[k] * ordered_sum(Sk[k] * r, d);
+            coef[k] = rho[k] * pair_sum(Sk[k] * r, d);
             r = r - coef[k] * Yk[k];
         }
     }
     double h0 = 1.0;
     if (cnt > 0) {
-        const double sy = ordered_sum(Sk[0] * Yk[0], d);
-        const double yy = ordered_sum(Yk[0] * Yk[0], d);
+        const double sy = pair_sum(Sk[0] * Yk[0], d);
+        const double yy = pair_sum(Yk[0] * Yk[0], d);
         if (yy > 0.0) h0 = sy / yy;
     }
     r = h0 * r;
 #pragma unroll
     for (int k = kLbfgsMaxM - 1; k >= 0; --k) {  // oldest to newest
         if (k < cnt) {
-            const double b = rho[k] * ordered_sum(Yk[k] * r, d);
+            const double b = rho[k] * pair_sum(Yk[k] * r, d);
             r = r + Sk[k] * (coef[k] - b);
         }
     }
@@ -363,12 +375,12 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
     const double u = to_u(c, th);
     double p = -r;
     if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
-    double gp = ordered_sum(gu * p, d);
+    double gp = pair_sum(gu * p, d);
     if (!(gp < 0.0)) {  // not a descent direction: steepest descent
         cnt = 0;
         p = -gu;
         if (c.w == 0.0 || (u <= 0.0 && p < 0.0) || (u >= 1.0 && p > 0.0)) p = 0.0;
-        gp = ordered_sum(gu * p, d);
+        gp = pair_sum(gu * p, d);
     }
     double alpha = a.st.alpha[pidx];
     if (cnt == 0) {
@@ -400,7 +412,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_propose(LbfgsArgs a)
 // A wavefront per parameter vector, lane j for dimension j, as the proposal:
 // the Armijo test on every trial point, the one of lowest loss among those
 // that pass (the first on ties), and on acceptance the new pair (kept when
-// s.y > 0, s.y summed in dimension order) and the step.
+// s.y > 0, s.y summed in pairs) and the step.
 __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
 {
     const int j = threadIdx.x & (kWave - 1);
@@ -437,7 +449,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_accept(LbfgsArgs a)
         const double gt = a.st.grad_t[ct], g = a.st.grad[cj];
         const double sj = to_u(c, tt) - to_u(c, th);
         const double yj = grad_u(c, tt, gt) - grad_u(c, th, g);
-        const double sy = ordered_sum(sj * yj, d);
+        const double sy = pair_sum(sj * yj, d);
         const int head = a.st.head[pidx];
         if (sy > 0.0 && on) {
             a.st.S[(size_t)head * a.theta_len + cj] = sj;
