@@ -92,3 +92,44 @@ def test_autograd_rejects_float32_theta(batch):
     th = torch.zeros(batch.theta_len, dtype=torch.float32, requires_grad=True)
     with pytest.raises(TypeError, match="float64"):
         SirdLoss.apply(th, batch, f64(batch.obs_len), "ssre", 0)
+
+
+def test_replicated_batch_layout():
+    """Batch(replicas=T), the layout of the L-BFGS trial points: replica t of
+    problem r has its own parameters and particles at t theta_len and t
+    total_particles past replica 0's (one replica's sizes), and shares replica
+    0's observations and box; the plan sees T times the problems and tiles."""
+    specs = [core.ProblemSpec(30, 10, 14, 3, 1e6, n_part=100, stream=0),
+             core.ProblemSpec(45, 2, 14, 4, 1e7, n_part=65, stream=2)]
+    one = core.Batch(specs, device="cpu")
+    T = 3
+    rep = core.Batch(specs, device="cpu", replicas=T)
+    assert rep.n_prob == T * one.n_prob and rep.n_tiles == T * one.n_tiles
+    assert rep.theta_len == T * one.theta_len
+    assert rep.total_particles == T * one.total_particles
+    assert rep.obs_len == one.obs_len and rep.box_len == one.box_len
+    for t in range(T):
+        for r in range(one.n_prob):
+            a, b = one.table[r], rep.table[t * one.n_prob + r]
+            assert b["theta_off"] == a["theta_off"] + t * one.theta_len
+            assert b["p_off"] == a["p_off"] + t * one.total_particles
+            assert b["obs_off"] == a["obs_off"] and b["box_off"] == a["box_off"]
+            assert b["n_part"] == a["n_part"] and b["n_seg"] == a["n_seg"]
+    # pack/unpack see the replicas as problems of their own
+    th = [np.full((s.n_part, s.d), 10.0 * t + r) for t in range(T) for r, s in enumerate(specs)]
+    flat = rep.pack_theta(th).cpu().numpy()
+    for t in range(T):
+        np.testing.assert_array_equal(flat[t * one.theta_len:(t + 1) * one.theta_len],
+                                      one.pack_theta(th[t * 2:(t + 1) * 2]).cpu().numpy())
+
+
+def test_replicas_and_trials_are_validated():
+    specs = [core.ProblemSpec(30, 10, 14, 3, 1e6, n_part=10)]
+    with pytest.raises(ValueError, match="replicas"):
+        core.Batch(specs, device="cpu", replicas=0)
+    with pytest.raises(ValueError, match="replicas"):
+        core.Batch(specs, device="cpu", replicas=2, with_traj=True)
+    b = core.Batch(specs, device="cpu")
+    for T in (0, 9):
+        with pytest.raises(ValueError, match="n_trials"):
+            core.LbfgsState(b, f64(b.theta_len), n_trials=T)

@@ -337,3 +337,17 @@ def test_lbfgs_refinement_recovers_noise_free_truth():
     th, L = fit.best_per_problem(ref.batch, ref.theta, ref.loss)
     assert L[0] < 1e-14
     np.testing.assert_allclose(th[0], f.truth, rtol=1e-5)
+
+
+def test_lbfgs_rejects_trials_outside_range():
+    """The C entry points refuse n_trials outside 0..8 before any launch."""
+    f = synth.c2().fits[0]
+    b = make_batch([f], [8])
+    lo, hi = b.pack_box([f.lo]), b.pack_box([f.hi])
+    st = S.LbfgsState(b, b.pack_theta([random_theta(f, 8, seed=1)]))
+    for T in (-1, 9):
+        st.c.n_trials = T
+        with pytest.raises(S.SirdError, match="n_trials"):
+            S.sird_lbfgs_propose(b, st, lo, hi)
+        with pytest.raises(S.SirdError, match="n_trials"):
+            S.sird_lbfgs_accept(b, st, lo, hi)
