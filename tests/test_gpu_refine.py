@@ -351,3 +351,65 @@ def test_lbfgs_rejects_trials_outside_range():
             S.sird_lbfgs_propose(b, st, lo, hi)
         with pytest.raises(S.SirdError, match="n_trials"):
             S.sird_lbfgs_accept(b, st, lo, hi)
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_lbfgs_lockstep_beyond_sixteen_dimensions(T):
+    """Dot products over more than 16 and more than 32 dimensions (the
+    pairwise sum's levels across rows of lanes): a 22-parameter window and a
+    50-parameter one (326 days in 7-day beta segments), in lockstep with the
+    oracle fed the same (f, grad)."""
+    import dataclasses
+    wl = synth.c3(regions=[6, 7])
+    base = wl.fits[0]
+    K = -(-base.W // 7)
+    lo, hi = synth.box(K)
+    wide = dataclasses.replace(base, seg_days=7, K=K, lo=lo, hi=hi, truth=None)
+    fits = [wl.fits[1], wide]
+    assert [f.d for f in fits] == [22, 50]
+    counts = (6, 5)
+    ths = [random_theta(f, n, seed=40 + i) for i, (f, n) in enumerate(zip(fits, counts))]
+    b = make_batch(fits, list(counts))
+    blo = b.pack_box([f.lo for f in fits])
+    bhi = b.pack_box([f.hi for f in fits])
+    st = S.LbfgsState(b, b.pack_theta(ths), m=6, log_last=True, n_trials=T)
+    tb = st.trial_batch
+    osts = [oracle.Lbfgs(t, m=6, log_last=True, n_trials=T) for t in ths]
+    probs = [oracle_problem(f) for f in fits]
+
+    def fg(i, t):
+        return oracle.loss_grad_fwd(probs[i], t, fits[i].y, "ssre")
+
+    for i, o in enumerate(osts):
+        for q in range(counts[i]):
+            o.f[q], o.grad[q] = fg(i, ths[i][q])
+    st.f.copy_(torch.from_numpy(np.concatenate([o.f for o in osts])).cuda())
+    st.grad.copy_(b.pack_theta([o.grad for o in osts]))
+    n_prob = len(fits)
+
+    def blocks(arrs):
+        return [np.split(a, T)[t] for t in range(T) for a in arrs]
+
+    for rnd in range(8):
+        S.sird_lbfgs_propose(b, st, blo, bhi)
+        tts = tb.unpack_theta(st.theta_t)
+        for i, o in enumerate(osts):
+            o.propose(fits[i].lo, fits[i].hi)
+            got = np.concatenate([tts[t * n_prob + i] for t in range(T)])
+            np.testing.assert_allclose(got, o.theta_t, rtol=1e-13, atol=1e-300,
+                                       err_msg=f"round {rnd}, problem {i}")
+            np.testing.assert_allclose(st.gp.cpu().numpy()[b.table[i]["p_off"]:][:counts[i]],
+                                       o.gp, rtol=1e-12, err_msg=f"gp, round {rnd}")
+            for q in range(T * counts[i]):
+                o.f_t[q], o.grad_t[q] = fg(i, o.theta_t[q])
+        st.theta_t.copy_(tb.pack_theta(blocks([o.theta_t for o in osts])))
+        st.f_t.copy_(torch.from_numpy(np.concatenate(blocks([o.f_t for o in osts]))).cuda())
+        st.grad_t.copy_(tb.pack_theta(blocks([o.grad_t for o in osts])))
+        S.sird_lbfgs_accept(b, st, blo, bhi, 1e-4)
+        got = b.unpack_theta(st.theta)
+        for i, o in enumerate(osts):
+            o.accept(fits[i].lo, fits[i].hi, 1e-4)
+            np.testing.assert_allclose(got[i], o.theta, rtol=1e-13,
+                                       err_msg=f"round {rnd}, problem {i}")
+        assert np.array_equal(st.count.cpu().numpy(), np.concatenate([o.count for o in osts]))
+    assert int(st.count.max().item()) > 1   # the recursion ran over stored pairs
