@@ -125,7 +125,7 @@ def _search(batch: Batch, key: str, run, use_cache: bool, verbose: bool,
     for r in range(rounds):
         for i, cand in enumerate(cands):
             if r > 0 and not times[i]:
-                continue  # the library refused this shape in round 0
+                continue  # the library refused this shape in the first timing pass
             batch.configure(**cand)
             if r == 0 and i == 0:
                 for _ in range(max(1, warm // 5)):
